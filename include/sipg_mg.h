@@ -1,0 +1,225 @@
+/*
+ * sipg_mg.h -- C ABI of the MI355X p-multigrid / weighted overlapping Schwarz
+ * solver for the nodal symmetric interior penalty DG (SIPG) discretization of
+ * the periodic Poisson problem -lap u = f on [0,lx] x [0,ly] x [0,lz]
+ * (Stiller, "Robust Multigrid for Cartesian Interior Penalty DG Formulations
+ * of the Poisson Equation in 3D", arXiv 1612.04796).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Vectors.  All vector arguments are DEVICE pointers (HIP global memory of
+ *   the current device), owned by the caller, holding one level's
+ *   coefficients in element-major order: index
+ *       ((ez*ney + ey)*nex + ex) * n^3 + (k*n + j)*n + i
+ *   with n = P_l + 1 GLL nodes per direction, x fastest inside and across
+ *   elements.  Level l has E*n_l^3 values (E = nex*ney*nez).  double* means
+ *   FP64; the precision of the preconditioner (sipg_params.precond_bits)
+ *   changes only internal storage.  Input and output vectors must not alias
+ *   unless the entry point says "in place".
+ * Levels.  Level 0 is the coarsest (P_0 = 1), level L the top (P_L = P);
+ *   the orders are 1, 2, 4, ..., 2^k < P, P (P_l = 2^l when P is a power of
+ *   two, Sec. 3.2).  level = -1 means the top level.
+ * Streams.  Every device operation is enqueued on the stream given to
+ *   sipg_setup (NULL = the default stream).  Entry points marked "async"
+ *   return without synchronizing; the solvers synchronize to read residual
+ *   norms.
+ * Errors.  Every entry point returns a sipg_status; on failure the message is
+ *   in sipg_last_error() (thread local) and the outputs are unspecified
+ *   unless the entry point says otherwise.  Invalid arguments are rejected
+ *   before any device work is enqueued.
+ */
+#ifndef SIPG_MG_H
+#define SIPG_MG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sipg_ctx sipg_ctx; /* opaque: hierarchy, tables and work space in HBM */
+
+typedef enum {
+  SIPG_OK = 0,
+  SIPG_EINVAL = -1,      /* invalid argument or unsupported configuration      */
+  SIPG_ENOMEM = -2,      /* device or host allocation failed                   */
+  SIPG_EHIP = -3,        /* a HIP runtime call or kernel launch failed         */
+  SIPG_ENOCONV = -4,     /* tolerance not reached within the iteration limit   */
+  SIPG_EBREAKDOWN = -5,  /* flexible CG breakdown (p.Ap <= 0 or not finite)    */
+  SIPG_ENOTFINITE = -6   /* a residual norm became NaN or infinite            */
+} sipg_status;
+
+/* Overlap of the element-centred Schwarz subdomains (Sec. 3.1, Tables 1-2):
+ *   MIN: one node layer from each neighbour (N_O = 1);
+ *   REL: width delta_O = omega * h_d in direction d;
+ *   MAX: width min(omega * max_k h_k, h_d).
+ * N_O on each level counts the neighbour nodes whose distance from the shared
+ * face is at most delta_O. */
+typedef enum { SIPG_OVL_MIN = 0, SIPG_OVL_REL = 1, SIPG_OVL_MAX = 2 } sipg_overlap_mode;
+
+typedef struct {
+  int32_t ne[3];          /* elements per direction (x, y, z); >= 3, and >= 4 in a
+                             direction whose subdomain takes whole neighbours      */
+  double len[3];          /* domain lengths lx, ly, lz > 0                         */
+  int32_t P;              /* polynomial order, 1..16                               */
+  double penalty;         /* c_mu: mu_d = c_mu P_l (P_l + 1) / h_d on level l;
+                             must exceed 1/2 (the stability threshold); 1.0 is
+                             the paper's setting read as twice the threshold      */
+  int32_t overlap_mode;   /* sipg_overlap_mode                                      */
+  double overlap;         /* omega in [0, 1]; ignored for SIPG_OVL_MIN             */
+  int32_t nsmooth_pre;    /* pre-smoothing steps on the top level  (V(1,1): 1)     */
+  int32_t nsmooth_post;   /* post-smoothing steps on the top level (V(1,1): 1)     */
+  int32_t smooth_growth;  /* steps on level l are multiplied by growth^(L-l);
+                             1 = fixed V-cycle, 3 = the variable V-cycle of Table 2 */
+  int32_t precond_bits;   /* precision of the multigrid preconditioner inside
+                             sipg_pcg_solve and of sipg_precond: 64 or 32
+                             (FP32 storage and arithmetic, coarse solve in FP64) */
+} sipg_params;
+
+/* Fills *p with the defaults: ne = 4^3, unit cube, P = 4, penalty 1.0,
+ * minimal overlap, omega 0.08, V(1,1), growth 1, precond_bits 64. */
+void sipg_default_params(sipg_params *p);
+
+/* Builds the level hierarchy (Sec. 3.2): for every level and direction the
+ * GLL rule, the 1D mass and SIPG stiffness blocks of eq. (A), the overlap
+ * layers N_O, the generalized eigenpairs of the restricted 1D pairs used by
+ * the fast diagonalization of Sec. 3.1, the hat weights, the interpolation
+ * matrices, and the global level-0 eigenpairs of the coarse pseudo-inverse;
+ * then allocates all level vectors and work space on the current device and
+ * uploads the tables on `hip_stream` (a hipStream_t, may be NULL).
+ * On success *out owns everything; release it with sipg_destroy. */
+int sipg_setup(const sipg_params *p, void *hip_stream, sipg_ctx **out);
+
+/* Frees all device and host memory of the context (NULL is accepted). */
+int sipg_destroy(sipg_ctx *c);
+
+/* Device bytes sipg_setup would allocate for *p (for admission control);
+ * computed on the host without touching the device. */
+int sipg_footprint(const sipg_params *p, size_t *bytes);
+
+/* Number of levels L + 1. */
+int sipg_nlevels(const sipg_ctx *c, int *nlevels);
+
+/* Order P_l, overlap layers N_O per direction and unknowns E*n^3 of level l. */
+int sipg_level_info(const sipg_ctx *c, int level, int *order, int no[3], int64_t *ndof);
+
+/* Discrete right-hand side of a Fourier load, async:
+ *   f(x) = sum_q amp[q] prod_d sin(2 pi k[3q+d] x_d / l_d + phi[3q+d]),
+ *   b = (Mz x My x Mx) f(GLL nodes)  (GLL quadrature of int v f, Sec. 2),
+ * followed by removal of the Euclidean mean of b (projection onto the range
+ * of the singular periodic operator).  k, phi, amp are HOST arrays of
+ * nmodes*3, nmodes*3 and nmodes entries (1 <= nmodes <= 64); b is a device
+ * vector of the top level. */
+int sipg_rhs_fourier(sipg_ctx *c, int nmodes, const int32_t *k, const double *phi,
+                     const double *amp, double *b);
+
+/* y = A_l u, async.  A_l is the Kronecker-sum operator of eq. (A) on level l,
+ * applied element by element by sum factorization with face coupling to the
+ * six neighbours. */
+int sipg_apply_A(sipg_ctx *c, int level, const double *u, double *y);
+
+/* r = f - A_l u, async (the residual form of Sec. 3.1). */
+int sipg_residual(sipg_ctx *c, int level, const double *u, const double *f, double *r);
+
+/* u += sum_s R_s^T W_s A_ss^{-1} R_s r on level l >= 1, async: one weighted
+ * additive Schwarz correction (eq. (correction:global)) with every local
+ * problem solved by fast diagonalization.  In place on u. */
+int sipg_schwarz(sipg_ctx *c, int level, const double *r, double *u);
+
+/* nsteps smoothing steps on level l >= 1, in place on u, async: each step is
+ * r = f - A_l u followed by sipg_schwarz. */
+int sipg_smooth(sipg_ctx *c, int level, double *u, const double *f, int nsteps);
+
+/* f_{l-1} = I_l^T r_l, async: transposed embedded interpolation (level l >= 1). */
+int sipg_restrict(sipg_ctx *c, int level, const double *r_fine, double *f_coarse);
+
+/* u_l += I_l u_{l-1}, async: embedded interpolation (level l >= 1), in place
+ * on u_fine. */
+int sipg_prolong_add(sipg_ctx *c, int level, const double *u_coarse, double *u_fine);
+
+/* u_0 = A_0^+ f_0, async: minimum Euclidean norm solution on level 0
+ * (Algorithm 1, coarse grid solution), by projecting f_0 onto the range of
+ * A_0 and fast diagonalization with the global periodic 1D eigenpairs. */
+int sipg_coarse_solve(sipg_ctx *c, const double *f0, double *u0);
+
+/* One multigrid V-cycle (Algorithm 1) in FP64 from the top-level value u for
+ * the right side f, in place on u, async. */
+int sipg_vcycle(sipg_ctx *c, double *u, const double *f);
+
+/* z = B r: one V-cycle started from zero, in the preconditioner precision of
+ * the context (FP64, or FP32 with the coarse solve in FP64), async.  This is
+ * the preconditioner of sipg_pcg_solve. */
+int sipg_precond(sipg_ctx *c, const double *r, double *z);
+
+/* Multigrid solve: repeats V-cycles from the value in u until
+ * ||f - A u||_2 <= rtol ||f - A u_start||_2.  On return *ncyc holds the
+ * cycles run and *relres the final relative residual.  SIPG_ENOCONV if maxcyc
+ * cycles do not reach rtol (u holds the last iterate).  Synchronizes. */
+int sipg_mg_solve(sipg_ctx *c, double *u, const double *f, double rtol, int maxcyc,
+                  int *ncyc, double *relres);
+
+/* Flexible (inexact preconditioned) CG (Sec. 3.2) with one V-cycle from zero
+ * as preconditioner, FP64 outer iteration, starting from the value in u,
+ * until the residual satisfies ||r||_2 <= rtol ||r_0||_2, confirmed by a
+ * recomputed FP64 residual.  *iters: operator applications in the loop.
+ * SIPG_ENOCONV / SIPG_EBREAKDOWN leave the last iterate in u.  Synchronizes. */
+int sipg_pcg_solve(sipg_ctx *c, double *u, const double *f, double rtol, int maxit,
+                   int *iters, double *relres);
+
+/* Residual norms of the last mg/pcg solve (index 0 = start); copies at most
+ * cap values to the HOST array out and sets *n to the number available. */
+int sipg_residual_history(const sipg_ctx *c, double *out, int cap, int *n);
+
+/* Kernels of the hot path that sipg_time_kernel can time in isolation. */
+typedef enum {
+  SIPG_KERNEL_RESIDUAL = 0,        /* r = f - A_l u (operator apply, eq. (A))          */
+  SIPG_KERNEL_SCHWARZ_SOLVE = 1,   /* the local fast-diagonalization solves of all
+                                      subdomains (writes the per-subdomain corrections) */
+  SIPG_KERNEL_SCHWARZ_ASSEMBLE = 2,/* u += sum of the weighted corrections             */
+  SIPG_KERNEL_RESTRICT = 3,        /* f_{l-1} = I_l^T (f_l - A_l u_l), fused           */
+  SIPG_KERNEL_PROLONG = 4          /* u_l += I_l u_{l-1}                                */
+} sipg_kernel;
+
+/* Measurement support: enqueues `reps` back-to-back launches of one kernel of
+ * the hot path on level l (>= 1) of the context, in precision bits (64, or 32
+ * for an FP32-preconditioner context), on the context stream, bracketed by two
+ * HIP events recorded on that same stream, and returns the mean duration of
+ * one launch in *ms.  The kernels run on the context's internal work vectors,
+ * whose contents are overwritten (set to a fixed pattern first).
+ * Synchronizes. */
+int sipg_time_kernel(sipg_ctx *c, int kernel, int level, int bits, int reps, double *ms);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *sipg_last_error(void);
+
+/* ---- host-only table queries (no device needed; for verification) ------ */
+typedef enum {
+  SIPG_TAB_NODES = 0,      /* GLL nodes xi (n)                                 */
+  SIPG_TAB_WEIGHTS = 1,    /* GLL weights (n)                                  */
+  SIPG_TAB_DERIV = 2,      /* D[i][j] = phi_j'(xi_i) (n x n)                   */
+  SIPG_TAB_MASS = 3,       /* element mass diagonal (h/2) w (n)                */
+  SIPG_TAB_LDIAG = 4,      /* element diagonal block of L_d (n x n)            */
+  SIPG_TAB_LUPPER = 5,     /* coupling block L_{e,e+1} of L_d (n x n)          */
+  SIPG_TAB_OVERLAP = 6,    /* N_O (1 value)                                    */
+  SIPG_TAB_SUB_L = 7,      /* restricted L_s (m x m)                           */
+  SIPG_TAB_SUB_M = 8,      /* restricted M_s (m)                               */
+  SIPG_TAB_SUB_LAM = 9,    /* generalized eigenvalues of (L_s, M_s), ascending */
+  SIPG_TAB_SUB_S = 10,     /* eigenvectors S (m x m, column j = pair j)        */
+  SIPG_TAB_SUB_W = 11,     /* 1D hat weights (m)                               */
+  SIPG_TAB_INTERP = 12,    /* J (n_l x n_{l-1}) from level l-1 to level l      */
+  SIPG_TAB_COARSE_LAM = 13,/* level-0 global eigenvalues (2 ne), zero mode = 0 */
+  SIPG_TAB_COARSE_S = 14   /* level-0 global eigenvectors (2ne x 2ne)          */
+} sipg_table;
+
+/* Copies table `which` of direction dir (0..2) on level `level` into the HOST
+ * array out (row-major), at most cap values; *count receives the table size.
+ * Computed on the host from *p alone. */
+int sipg_host_table(const sipg_params *p, int level, int dir, int which, double *out,
+                    int cap, int *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIPG_MG_H */

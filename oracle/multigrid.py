@@ -30,7 +30,7 @@ import numpy as np
 import scipy.linalg
 
 from .basis import interp_matrix
-from .sipg import Discretization1D, apply_A_global, to_global, to_element
+from .sipg import Discretization1D, apply_A_global, to_global, to_element, _along as _axis
 from .schwarz import SubdomainTables, overlap_delta, overlap_layers, schwarz_correction
 
 
@@ -123,16 +123,16 @@ def coarse_solve_global(F, hier):
     """u_0 = A_0^+ f_0 (minimum Euclidean norm) by global fast diagonalization."""
     (lx, Sx), (ly, Sy), (lz, Sz) = hier.coarse
     f = F - F.mean()
-    t = np.einsum('zyx,xa->zya', f, Sx)
-    t = np.einsum('zya,yb->zba', t, Sy)
-    t = np.einsum('zba,zc->cba', t, Sz)
+    t = _axis(f, Sx.T, 2)
+    t = _axis(t, Sy.T, 1)
+    t = _axis(t, Sz.T, 0)
     lam = lz[:, None, None] + ly[None, :, None] + lx[None, None, :]
     inv = 1.0 / np.where(lam == 0, 1.0, lam)
     inv[np.argmin(np.abs(lz)), np.argmin(np.abs(ly)), np.argmin(np.abs(lx))] = 0.0
     t = t * inv
-    t = np.einsum('cba,xa->cbx', t, Sx)
-    t = np.einsum('cbx,yb->cyx', t, Sy)
-    u = np.einsum('cyx,zc->zyx', t, Sz)
+    t = _axis(t, Sx, 2)
+    t = _axis(t, Sy, 1)
+    u = _axis(t, Sz, 0)
     return u - u.mean()
 
 

@@ -18,7 +18,7 @@ import math
 import numpy as np
 import scipy.linalg
 
-from .sipg import to_element, to_global
+from .sipg import to_element, to_global, _along as _axis
 
 
 def node_coordinates(disc):
@@ -80,16 +80,16 @@ def exact_solution(b, hier):
     n = hier.top.n
     f = to_global(b, hier.ne, n)
     f = f - f.mean()
-    t = np.einsum('zyx,xa->zya', f, Sx)
-    t = np.einsum('zya,yb->zba', t, Sy)
-    t = np.einsum('zba,zc->cba', t, Sz)
+    t = _axis(f, Sx.T, 2)
+    t = _axis(t, Sy.T, 1)
+    t = _axis(t, Sz.T, 0)
     lam = lz[:, None, None] + ly[None, :, None] + lx[None, None, :]
     inv = 1.0 / np.where(lam == 0, 1.0, lam)
     inv[np.argmin(np.abs(lz)), np.argmin(np.abs(ly)), np.argmin(np.abs(lx))] = 0.0
     t = t * inv
-    t = np.einsum('cba,xa->cbx', t, Sx)
-    t = np.einsum('cbx,yb->cyx', t, Sy)
-    u = np.einsum('cyx,zc->zyx', t, Sz)
+    t = _axis(t, Sx, 2)
+    t = _axis(t, Sy, 1)
+    u = _axis(t, Sz, 0)
     return to_element(u - u.mean(), hier.ne, n)
 
 

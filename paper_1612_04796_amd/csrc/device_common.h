@@ -1,0 +1,72 @@
+// Device-side common definitions for the gfx950 kernels: table views passed
+// by value to kernels, XCD-aware block numbering and small helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sipg {
+
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with a private L2.  Renumbering so that XCD x works on one contiguous range
+// of blocks keeps face neighbours (which are read again by the next blocks)
+// in the same L2.  The map is a bijection of [0, nblocks).
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+  constexpr int kXcd = 8;
+  const int q = nblocks / kXcd, r = nblocks % kXcd;
+  const int x = b % kXcd, local = b / kXcd;
+  return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+}
+
+struct Mesh {
+  int ne[3];   // elements per direction
+  int E;       // ne[0]*ne[1]*ne[2]
+};
+
+__device__ __forceinline__ int elem_index(const Mesh &g, int ex, int ey, int ez) {
+  return (ez * g.ne[1] + ey) * g.ne[0] + ex;
+}
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// 1D operator data of one level (eq. (A)): per direction the element diagonal
+// block Ld (n x n), the mass diagonal, the scaled face-derivative rows
+// DL = D[0][:]/h, DR = D[p][:]/h and the penalty.
+template <typename T>
+struct ApplyTabs {
+  const T *Ld[3];
+  const T *M[3];
+  const T *DL[3];
+  const T *DR[3];
+  T mu[3];
+};
+
+// Fast-diagonalization data of one level (Sec. 3.1): per direction the
+// eigenvectors S (m x m, S[a*m+j] = node a of pair j), the weighted
+// eigenvectors WS = diag(w) S and the eigenvalues, with m = n + 2 N_O.
+template <typename T>
+struct SchwarzTabs {
+  const T *S[3];
+  const T *WS[3];
+  const T *lam[3];
+  int m[3];
+  int no[3];
+};
+
+template <typename T>
+__device__ __forceinline__ T block_reduce_sum(T v, T *sh) {
+  // deterministic tree reduction over the whole block (blockDim.x <= 1024)
+  const int tid = threadIdx.x;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = tid & 63, wid = tid >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  const int nw = (blockDim.x + 63) >> 6;
+  T s = 0;
+  if (tid == 0)
+    for (int w = 0; w < nw; ++w) s += sh[w];
+  return s;  // valid in thread 0
+}
+
+}  // namespace sipg

@@ -1,0 +1,135 @@
+// Host-callable launchers of the gfx950 kernels.  Every launcher enqueues on
+// the given stream, never synchronizes, and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace sipg {
+
+enum ApplyMode { APPLY_PLAIN = 0, APPLY_RESID = 1, APPLY_RESTRICT = 2 };
+
+// y = A u (optionally with per-block partial sums of u.y), r = f - A u, or
+// f_c = J^T (f - A u) per element.  n = P_l + 1 (2..17).
+template <typename T>
+struct ApplyLaunch {
+  Mesh mesh;
+  int n;
+  ApplyTabs<T> tabs;
+  const T *u;
+  const T *f;       // RESID, RESTRICT
+  T *out;
+  int mode;
+  T *partial;       // PLAIN only: one partial dot product per block, or null
+  const T *J;       // RESTRICT: n x nc interpolation matrix
+  int nc;           // RESTRICT: coarse nodes per direction
+};
+template <typename T>
+hipError_t launch_apply(const ApplyLaunch<T> &a, hipStream_t st);
+
+// Number of partial sums launch_apply writes for a PLAIN launch with partials.
+int apply_num_blocks(int E, int n);
+
+// u_f += (J x J x J)(u_c - *mean) per element (mean may be null).
+template <typename T, typename TC>
+struct ProlongLaunch {
+  int E;
+  int nf, nc;
+  const T *J;
+  const TC *uc;
+  const double *mean;
+  T *uf;
+};
+template <typename T, typename TC>
+hipError_t launch_prolong(const ProlongLaunch<T, TC> &a, hipStream_t st);
+
+// One weighted additive Schwarz correction: C[s] = W_s A_ss^{-1} R_s r for
+// every subdomain s (m_x*m_y*m_z values per subdomain, layout [s][c][b][a]),
+// then u_out = u_in + sum_s R_s^T C[s] in a fixed order (u_in may be null,
+// u_out may equal u_in).
+template <typename T>
+struct SchwarzLaunch {
+  Mesh mesh;
+  int n;
+  SchwarzTabs<T> tabs;
+  const T *r;
+  T *C;             // scratch of E * m_x*m_y*m_z values
+  const T *u_in;
+  T *u_out;
+};
+template <typename T>
+hipError_t launch_schwarz(const SchwarzLaunch<T> &a, hipStream_t st);
+// the two phases separately: local solves into C, then the assembly into u
+template <typename T>
+hipError_t launch_schwarz_local(const SchwarzLaunch<T> &a, hipStream_t st);
+template <typename T>
+hipError_t launch_schwarz_assemble(const SchwarzLaunch<T> &a, hipStream_t st);
+// true if the subdomain tensor of this size is solved in LDS in one kernel
+bool schwarz_fits_lds(const int m[3], size_t elem_bytes);
+
+// Level-0 pseudo-inverse by global fast diagonalization; see kernels_coarse.hip.
+struct CoarseLaunch {
+  int ne[3];
+  int N[3];                 // 2 ne_d
+  const double *S[3];       // N x N
+  const double *colsum[3];  // column sums of S
+  const double *lam[3];     // eigenvalues, zero mode exactly 0
+  int zero[3];              // zero-mode index per direction
+  double *t0, *t1;          // two work arrays of N0 = N[0]*N[1]*N[2] doubles
+  double *partial;          // kCoarsePartials doubles
+  double *scalars;          // [0] mean of f0, [1] mean of u0
+};
+constexpr int kCoarsePartials = 256;
+template <typename TI>
+hipError_t launch_coarse(const CoarseLaunch &a, const TI *f0, double *u0, bool subtract_mean,
+                         hipStream_t st);
+
+// ---- vector kernels (kernels_vec.hip) -------------------------------------
+constexpr int kDotBlocks = 1024;
+// partial[b] = sum over block b of x[i]*y[i] (fixed partition, deterministic)
+template <typename T>
+hipError_t launch_dot_partials(const T *x, const T *y, int64_t n, double *partial, hipStream_t st);
+// out[0] = scale * sum_{b<np} partial[b], reduced in a fixed order by one block
+hipError_t launch_finalize(const double *partial, int np, double scale, double *out, hipStream_t st);
+// two dot products at once: partial[b] = x.y, partial[kDotBlocks+b] = z.w
+template <typename T>
+hipError_t launch_dot2_partials(const T *x, const T *y, const T *z, const T *w, int64_t n,
+                                double *partial, hipStream_t st);
+// partial[b] = sum over block b of x[i], kDotBlocks blocks
+template <typename T>
+hipError_t launch_sum_partials(const T *x, int64_t n, double *partial, hipStream_t st);
+// y[i] = a[i] - (*s)
+template <typename T>
+hipError_t launch_sub_scalar(T *y, int64_t n, const double *s, hipStream_t st);
+template <typename TO, typename TI>
+hipError_t launch_convert(const TI *x, TO *y, int64_t n, hipStream_t st);
+template <typename T>
+hipError_t launch_fill(T *x, int64_t n, T v, hipStream_t st);
+
+// Flexible CG scalars live in device memory: see kernels_vec.hip.
+enum FcgScalar { FS_RZ = 0, FS_PQ = 1, FS_RR = 2, FS_ZQ = 3, FS_RZNEW = 4, FS_ALPHA = 5, FS_BETA = 6, FS_COUNT = 8 };
+// x += alpha p; r -= alpha q; partial = r.r   (alpha = s[RZ] / s[PQ])
+hipError_t launch_fcg_xr(double *x, double *r, const double *p, const double *q, int64_t n,
+                         double *s, double *partial, hipStream_t st);
+// beta = -alpha s[ZQ] / s[RZ]; s[RZ] = s[RZNEW]; p = z + beta p
+hipError_t launch_fcg_p(double *p, const double *z, int64_t n, double *s, hipStream_t st);
+// s[ZQ] and s[RZNEW] from the dot2 partials
+hipError_t launch_fcg_finalize2(const double *partial, double *s, hipStream_t st);
+
+// Fourier right-hand side: b = M f(nodes) (before mean removal)
+struct RhsLaunch {
+  Mesh mesh;
+  int n;
+  const double *xi;      // GLL nodes (n)
+  const double *mass[3]; // element mass diagonals (n)
+  double h[3], len[3];
+  int nmodes;
+  const int *k;          // device arrays: nmodes*3, nmodes*3, nmodes
+  const double *phi;
+  const double *amp;
+};
+hipError_t launch_rhs(const RhsLaunch &a, double *b, hipStream_t st);
+
+}  // namespace sipg

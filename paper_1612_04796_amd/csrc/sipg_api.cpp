@@ -1,0 +1,853 @@
+// C ABI of the solver (include/sipg_mg.h): context set-up, the multigrid
+// V-cycle of Algorithm 1, the MG and flexible-CG solvers, and the host-only
+// table queries.  Every device operation is a kernel launch on the context
+// stream; host synchronization happens only where a solver reads a residual
+// norm.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "host_tables.h"
+#include "kernels.h"
+#include "sipg_mg.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+struct HipFailure : std::runtime_error {
+  explicit HipFailure(const std::string &s) : std::runtime_error(s) {}
+};
+
+void check(hipError_t e, const char *what) {
+  if (e != hipSuccess) throw HipFailure(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device table views of one level in precision T.
+template <typename T>
+struct LevelTabs {
+  sipg::ApplyTabs<T> apply;
+  sipg::SchwarzTabs<T> schwarz;
+  const T *J = nullptr;  // n x n_prev (levels >= 1)
+  int n = 0, nc = 0;
+  int64_t ndof = 0;
+};
+
+// Work vectors of the V-cycle in precision T.
+template <typename T>
+struct Work {
+  std::vector<T *> u, f;  // levels 0..L-1 (u[0] unused), plus top-level pair for internal use
+  T *uL = nullptr, *fL = nullptr;
+  T *r = nullptr;         // residual scratch, top-level size
+  T *C = nullptr;         // Schwarz correction scratch
+  bool ready = false;
+};
+
+// Arena for uploading tables: host staging with aligned offsets.
+struct Arena {
+  std::vector<unsigned char> host;
+  template <typename T>
+  size_t put(const std::vector<double> &v) {
+    size_t off = (host.size() + 255) / 256 * 256;
+    host.resize(off + v.size() * sizeof(T));
+    T *p = reinterpret_cast<T *>(host.data() + off);
+    for (size_t i = 0; i < v.size(); ++i) p[i] = (T)v[i];
+    return off;
+  }
+};
+
+}  // namespace
+
+struct sipg_ctx {
+  sipg::HierarchyHost H;
+  hipStream_t stream = nullptr;
+  int L = 0;
+  sipg::Mesh mesh{};
+  std::vector<void *> allocs;
+  unsigned char *tab_dev = nullptr;
+  std::vector<LevelTabs<double>> t64;
+  std::vector<LevelTabs<float>> t32;
+  sipg::CoarseLaunch coarse{};
+  double *u0 = nullptr;                 // level-0 solution, always FP64
+  Work<double> w64;
+  Work<float> w32;
+  // flexible CG vectors (FP64, top level) and device scalars
+  double *cg_r = nullptr, *cg_p = nullptr, *cg_q = nullptr, *cg_z = nullptr;
+  double *scal = nullptr;               // FS_COUNT scalars + spare
+  double *partial = nullptr;            // 2 * kDotBlocks
+  double *host_scal = nullptr;          // pinned host mirror
+  int *rhs_k = nullptr;
+  double *rhs_phi = nullptr, *rhs_amp = nullptr;
+  const double *xi_top = nullptr, *mass_top[3] = {nullptr, nullptr, nullptr};
+  std::vector<double> hist;
+  size_t bytes = 0;
+
+  template <typename T>
+  T *alloc(size_t count) {
+    void *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) throw std::bad_alloc();
+    allocs.push_back(p);
+    bytes += count * sizeof(T);
+    return static_cast<T *>(p);
+  }
+  ~sipg_ctx() {
+    for (void *p : allocs) (void)hipFree(p);
+    if (host_scal) (void)hipHostFree(host_scal);
+  }
+};
+
+namespace {
+
+template <typename T>
+LevelTabs<T> &tabs_of(sipg_ctx *c, int l);
+template <>
+LevelTabs<double> &tabs_of<double>(sipg_ctx *c, int l) { return c->t64[l]; }
+template <>
+LevelTabs<float> &tabs_of<float>(sipg_ctx *c, int l) { return c->t32[l]; }
+template <typename T>
+Work<T> &work_of(sipg_ctx *c);
+template <>
+Work<double> &work_of<double>(sipg_ctx *c) { return c->w64; }
+template <>
+Work<float> &work_of<float>(sipg_ctx *c) { return c->w32; }
+
+size_t max_sub(const sipg::HierarchyHost &H) {
+  size_t mx = 1;
+  for (size_t l = 1; l < H.lev.size(); ++l)
+    mx = std::max(mx, (size_t)H.lev[l].dir[0].m * H.lev[l].dir[1].m * H.lev[l].dir[2].m);
+  return mx;
+}
+
+int64_t level_ndof(const sipg::HierarchyHost &H, int l) {
+  const int64_t E = (int64_t)H.prm.ne[0] * H.prm.ne[1] * H.prm.ne[2];
+  const int64_t n = H.lev[l].n;
+  return E * n * n * n;
+}
+
+// Bytes of one precision's V-cycle work space.
+size_t work_bytes(const sipg::HierarchyHost &H, size_t eb) {
+  const int L = (int)H.lev.size() - 1;
+  const int64_t E = (int64_t)H.prm.ne[0] * H.prm.ne[1] * H.prm.ne[2];
+  size_t b = 0;
+  for (int l = 0; l < L; ++l) b += 2 * (size_t)level_ndof(H, l) * eb;
+  b += 3 * (size_t)level_ndof(H, L) * eb;  // r plus an internal top-level u, f pair
+  b += (size_t)E * max_sub(H) * eb;
+  return b;
+}
+
+template <typename T>
+void ensure_work(sipg_ctx *c) {
+  Work<T> &w = work_of<T>(c);
+  if (w.ready) return;
+  const sipg::HierarchyHost &H = c->H;
+  w.u.assign(c->L + 1, nullptr);
+  w.f.assign(c->L + 1, nullptr);
+  for (int l = 0; l < c->L; ++l) {
+    w.u[l] = c->alloc<T>(level_ndof(H, l));
+    w.f[l] = c->alloc<T>(level_ndof(H, l));
+  }
+  w.uL = c->alloc<T>(level_ndof(H, c->L));
+  w.fL = c->alloc<T>(level_ndof(H, c->L));
+  w.r = c->alloc<T>(level_ndof(H, c->L));
+  w.C = c->alloc<T>((size_t)c->mesh.E * max_sub(H));
+  w.ready = true;
+}
+
+void upload_tables(sipg_ctx *c) {
+  const sipg::HierarchyHost &H = c->H;
+  Arena A;
+  struct Off {
+    size_t Ld[3], M[3], DL[3], DR[3], S[3], WS[3], lam[3], J;
+  };
+  std::vector<Off> o64(c->L + 1), o32(c->L + 1);
+  auto put_level = [&](auto tag, std::vector<Off> &off) {
+    using T = decltype(tag);
+    for (int l = 0; l <= c->L; ++l) {
+      const sipg::LevelHost &lv = H.lev[l];
+      for (int d = 0; d < 3; ++d) {
+        const sipg::Dir1D &D = lv.dir[d];
+        off[l].Ld[d] = A.put<T>(D.Ld);
+        off[l].M[d] = A.put<T>(D.mass);
+        off[l].DL[d] = A.put<T>(D.DLs);
+        off[l].DR[d] = A.put<T>(D.DRs);
+        if (l > 0) {
+          std::vector<double> WS(D.S);
+          for (int a = 0; a < D.m; ++a)
+            for (int j = 0; j < D.m; ++j) WS[a * D.m + j] *= D.wsub[a];
+          off[l].S[d] = A.put<T>(D.S);
+          off[l].WS[d] = A.put<T>(WS);
+          off[l].lam[d] = A.put<T>(D.lam);
+        }
+      }
+      if (l > 0) off[l].J = A.put<T>(lv.J);
+    }
+  };
+  put_level(double(), o64);
+  put_level(float(), o32);
+  size_t cS[3], cC[3], cL[3];
+  for (int d = 0; d < 3; ++d) {
+    const int N = H.coarse.N[d];
+    std::vector<double> cs(N, 0.0);
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) cs[j] += H.coarse.S[d][i * N + j];
+    cS[d] = A.put<double>(H.coarse.S[d]);
+    cC[d] = A.put<double>(cs);
+    cL[d] = A.put<double>(H.coarse.lam[d]);
+  }
+  const size_t oxi = A.put<double>(H.lev[c->L].dir[0].xi);
+  size_t omass[3];
+  for (int d = 0; d < 3; ++d) omass[d] = A.put<double>(H.lev[c->L].dir[d].mass);
+
+  c->tab_dev = c->alloc<unsigned char>(A.host.size());
+  check(hipMemcpyAsync(c->tab_dev, A.host.data(), A.host.size(), hipMemcpyHostToDevice, c->stream),
+        "table upload");
+  check(hipStreamSynchronize(c->stream), "table upload");
+
+  auto fill = [&](auto tag, std::vector<Off> &off, auto &dst) {
+    using T = decltype(tag);
+    dst.assign(c->L + 1, {});
+    for (int l = 0; l <= c->L; ++l) {
+      const sipg::LevelHost &lv = H.lev[l];
+      auto &t = dst[l];
+      t.n = lv.n;
+      t.nc = l > 0 ? H.lev[l - 1].n : 0;
+      t.ndof = level_ndof(H, l);
+      for (int d = 0; d < 3; ++d) {
+        t.apply.Ld[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].Ld[d]);
+        t.apply.M[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].M[d]);
+        t.apply.DL[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].DL[d]);
+        t.apply.DR[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].DR[d]);
+        t.apply.mu[d] = (T)lv.dir[d].mu;
+        if (l > 0) {
+          t.schwarz.S[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].S[d]);
+          t.schwarz.WS[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].WS[d]);
+          t.schwarz.lam[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].lam[d]);
+          t.schwarz.m[d] = lv.dir[d].m;
+          t.schwarz.no[d] = lv.dir[d].no;
+        }
+      }
+      if (l > 0) t.J = reinterpret_cast<const T *>(c->tab_dev + off[l].J);
+    }
+  };
+  fill(double(), o64, c->t64);
+  fill(float(), o32, c->t32);
+  for (int d = 0; d < 3; ++d) {
+    c->coarse.ne[d] = H.prm.ne[d];
+    c->coarse.N[d] = H.coarse.N[d];
+    c->coarse.S[d] = reinterpret_cast<const double *>(c->tab_dev + cS[d]);
+    c->coarse.colsum[d] = reinterpret_cast<const double *>(c->tab_dev + cC[d]);
+    c->coarse.lam[d] = reinterpret_cast<const double *>(c->tab_dev + cL[d]);
+    c->coarse.zero[d] = H.coarse.zero[d];
+  }
+  c->xi_top = reinterpret_cast<const double *>(c->tab_dev + oxi);
+  for (int d = 0; d < 3; ++d) c->mass_top[d] = reinterpret_cast<const double *>(c->tab_dev + omass[d]);
+}
+
+// ---- level operations -----------------------------------------------------
+template <typename T>
+void op_apply(sipg_ctx *c, int l, const T *u, T *y, T *partial) {
+  const LevelTabs<T> &t = tabs_of<T>(c, l);
+  sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, nullptr, y, sipg::APPLY_PLAIN, partial, nullptr, 0};
+  check(sipg::launch_apply<T>(a, c->stream), "apply_A");
+}
+
+template <typename T>
+void op_residual(sipg_ctx *c, int l, const T *u, const T *f, T *r) {
+  const LevelTabs<T> &t = tabs_of<T>(c, l);
+  sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, f, r, sipg::APPLY_RESID, nullptr, nullptr, 0};
+  check(sipg::launch_apply<T>(a, c->stream), "residual");
+}
+
+template <typename T>
+void op_residual_restrict(sipg_ctx *c, int l, const T *u, const T *f, T *fc) {
+  const LevelTabs<T> &t = tabs_of<T>(c, l);
+  sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, f, fc, sipg::APPLY_RESTRICT, nullptr, t.J, t.nc};
+  check(sipg::launch_apply<T>(a, c->stream), "residual_restrict");
+}
+
+template <typename T>
+void op_schwarz(sipg_ctx *c, int l, const T *r, const T *u_in, T *u_out) {
+  const LevelTabs<T> &t = tabs_of<T>(c, l);
+  sipg::SchwarzLaunch<T> a{c->mesh, t.n, t.schwarz, r, work_of<T>(c).C, u_in, u_out};
+  check(sipg::launch_schwarz<T>(a, c->stream), "schwarz");
+}
+
+template <typename T, typename TC>
+void op_prolong(sipg_ctx *c, int l, const TC *uc, const double *mean, T *uf) {
+  const LevelTabs<T> &t = tabs_of<T>(c, l);
+  sipg::ProlongLaunch<T, TC> a{c->mesh.E, t.n, t.nc, t.J, uc, mean, uf};
+  check(sipg::launch_prolong<T, TC>(a, c->stream), "prolong");
+}
+
+template <typename T>
+void op_fill_zero(sipg_ctx *c, T *x, int64_t n) {
+  // a zero vector through a kernel (no memset nodes in captured graphs)
+  check(sipg::launch_fill<T>(x, n, (T)0, c->stream), "fill");
+}
+
+// One V-cycle (Algorithm 1).  uL is the top-level iterate (in place); if
+// zero_start it is treated as zero.  r_top, if given, is f - A uL already
+// computed for the first pre-smoothing step.
+template <typename T>
+void vcycle_impl(sipg_ctx *c, T *uL, const T *fL, bool zero_start, const T *r_top) {
+  ensure_work<T>(c);
+  Work<T> &w = work_of<T>(c);
+  const int L = c->L;
+  const sipg::HierarchyHost &H = c->H;
+  const int growth = H.prm.smooth_growth;
+  auto nsteps = [&](int base, int l) {
+    int s = base;
+    for (int k = l; k < L; ++k) s *= growth;
+    return s;
+  };
+  if (L == 0) {
+    check(sipg::launch_coarse<T>(c->coarse, fL, c->u0, true, c->stream), "coarse");
+    check(sipg::launch_convert<T, double>(c->u0, uL, level_ndof(H, 0), c->stream), "coarse copy");
+    return;
+  }
+  for (int l = L; l >= 1; --l) {
+    T *ul = (l == L) ? uL : w.u[l];
+    const T *fl = (l == L) ? fL : w.f[l];
+    const bool zero = (l < L) || zero_start;
+    const int ns = nsteps(H.prm.nsmooth_pre, l);
+    for (int s = 0; s < ns; ++s) {
+      if (zero && s == 0) {
+        op_schwarz<T>(c, l, fl, nullptr, ul);
+      } else if (s == 0 && l == L && r_top) {
+        op_schwarz<T>(c, l, r_top, ul, ul);
+      } else {
+        op_residual<T>(c, l, ul, fl, w.r);
+        op_schwarz<T>(c, l, w.r, ul, ul);
+      }
+    }
+    if (ns == 0 && zero) op_fill_zero<T>(c, ul, level_ndof(H, l));
+    op_residual_restrict<T>(c, l, ul, fl, w.f[l - 1]);
+  }
+  check(sipg::launch_coarse<T>(c->coarse, w.f[0], c->u0, false, c->stream), "coarse");
+  for (int l = 1; l <= L; ++l) {
+    T *ul = (l == L) ? uL : w.u[l];
+    const T *fl = (l == L) ? fL : w.f[l];
+    if (l == 1) op_prolong<T, double>(c, 1, c->u0, c->coarse.scalars + 1, ul);
+    else op_prolong<T, T>(c, l, w.u[l - 1], nullptr, ul);
+    const int ns = nsteps(H.prm.nsmooth_post, l);
+    for (int s = 0; s < ns; ++s) {
+      op_residual<T>(c, l, ul, fl, w.r);
+      op_schwarz<T>(c, l, w.r, ul, ul);
+    }
+  }
+}
+
+}  // namespace
+
+namespace {
+
+// z = B r with B one V-cycle from zero in the preconditioner precision.
+void precond_impl(sipg_ctx *c, const double *r, double *z) {
+  const int64_t N = level_ndof(c->H, c->L);
+  if (c->H.prm.precond_bits == 64) {
+    vcycle_impl<double>(c, z, r, true, nullptr);
+    return;
+  }
+  ensure_work<float>(c);
+  Work<float> &w = c->w32;
+  check(sipg::launch_convert<float, double>(r, w.fL, N, c->stream), "precond cast");
+  vcycle_impl<float>(c, w.uL, w.fL, true, nullptr);
+  check(sipg::launch_convert<double, float>(w.uL, z, N, c->stream), "precond cast");
+}
+
+// Device scalars -> host (synchronizes the stream).
+void read_scalars(sipg_ctx *c) {
+  check(hipMemcpyAsync(c->host_scal, c->scal, sipg::FS_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                       c->stream),
+        "scalar readback");
+  check(hipStreamSynchronize(c->stream), "scalar readback");
+}
+
+// ||x||^2 into scal[slot]
+void norm2(sipg_ctx *c, const double *x, int64_t n, int slot) {
+  check(sipg::launch_dot_partials<double>(x, x, n, c->partial, c->stream), "dot");
+  check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + slot, c->stream), "dot");
+}
+
+void dot(sipg_ctx *c, const double *x, const double *y, int64_t n, int slot) {
+  check(sipg::launch_dot_partials<double>(x, y, n, c->partial, c->stream), "dot");
+  check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + slot, c->stream), "dot");
+}
+
+int mg_solve_impl(sipg_ctx *c, double *u, const double *f, double rtol, int maxcyc, int *ncyc,
+                  double *relres) {
+  const int64_t N = level_ndof(c->H, c->L);
+  ensure_work<double>(c);
+  c->hist.clear();
+  double r0 = -1.0;
+  for (int cyc = 0;; ++cyc) {
+    op_residual<double>(c, c->L, u, f, c->cg_r);
+    norm2(c, c->cg_r, N, sipg::FS_RR);
+    read_scalars(c);
+    const double rn = std::sqrt(c->host_scal[sipg::FS_RR]);
+    c->hist.push_back(rn);
+    if (!std::isfinite(rn)) return fail(SIPG_ENOTFINITE, "residual norm is not finite");
+    if (r0 < 0) r0 = rn;
+    const double rel = r0 > 0 ? rn / r0 : 0.0;
+    if (ncyc) *ncyc = cyc;
+    if (relres) *relres = rel;
+    if (rn <= rtol * r0) return SIPG_OK;
+    if (cyc >= maxcyc) return fail(SIPG_ENOCONV, "mg_solve: tolerance not reached");
+    vcycle_impl<double>(c, u, f, false, c->cg_r);
+  }
+}
+
+int pcg_solve_impl(sipg_ctx *c, double *x, const double *b, double rtol, int maxit, int *iters,
+                   double *relres) {
+  const int64_t N = level_ndof(c->H, c->L);
+  double *r = c->cg_r, *p = c->cg_p, *q = c->cg_q, *z = c->cg_z;
+  c->hist.clear();
+  if (iters) *iters = 0;
+  op_residual<double>(c, c->L, x, b, r);
+  norm2(c, r, N, sipg::FS_RR);
+  read_scalars(c);
+  const double r0 = std::sqrt(c->host_scal[sipg::FS_RR]);
+  c->hist.push_back(r0);
+  if (!std::isfinite(r0)) return fail(SIPG_ENOTFINITE, "initial residual is not finite");
+  if (relres) *relres = 0.0;
+  if (r0 == 0.0) return SIPG_OK;
+  precond_impl(c, r, z);
+  dot(c, r, z, N, sipg::FS_RZ);
+  check(sipg::launch_convert<double, double>(z, p, N, c->stream), "copy");
+  for (int it = 1; it <= maxit; ++it) {
+    op_apply<double>(c, c->L, p, q, c->partial);
+    check(sipg::launch_finalize(c->partial, sipg::apply_num_blocks(c->mesh.E, c->t64[c->L].n), 1.0,
+                                c->scal + sipg::FS_PQ, c->stream),
+          "dot");
+    check(sipg::launch_fcg_xr(x, r, p, q, N, c->scal, c->partial, c->stream), "fcg update");
+    check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + sipg::FS_RR, c->stream), "dot");
+    read_scalars(c);
+    const double pq = c->host_scal[sipg::FS_PQ];
+    double rn = std::sqrt(c->host_scal[sipg::FS_RR]);
+    if (iters) *iters = it;
+    if (!(pq > 0.0) || !std::isfinite(pq)) {
+      if (relres) *relres = c->hist.back() / r0;
+      return fail(SIPG_EBREAKDOWN, "flexible CG breakdown (p.Ap <= 0 or not finite)");
+    }
+    if (!std::isfinite(rn)) return fail(SIPG_ENOTFINITE, "residual norm is not finite");
+    if (rn <= rtol * r0) {
+      // confirm with the recomputed residual b - A x
+      op_residual<double>(c, c->L, x, b, q);
+      norm2(c, q, N, sipg::FS_RR);
+      read_scalars(c);
+      const double rt = std::sqrt(c->host_scal[sipg::FS_RR]);
+      if (rt <= rtol * r0) {
+        c->hist.push_back(rt);
+        if (relres) *relres = rt / r0;
+        return SIPG_OK;
+      }
+      // keep iterating from the true residual; q is rebuilt below
+      check(sipg::launch_convert<double, double>(q, r, N, c->stream), "copy");
+      rn = rt;
+      op_apply<double>(c, c->L, p, q, nullptr);
+    }
+    c->hist.push_back(rn);
+    if (relres) *relres = rn / r0;
+    precond_impl(c, r, z);
+    check(sipg::launch_dot2_partials<double>(z, q, r, z, N, c->partial, c->stream), "dot2");
+    check(sipg::launch_fcg_finalize2(c->partial, c->scal, c->stream), "dot2");
+    check(sipg::launch_fcg_p(p, z, N, c->scal, c->stream), "fcg update");
+  }
+  return fail(SIPG_ENOCONV, "pcg_solve: tolerance not reached");
+}
+
+int resolve_level(const sipg_ctx *c, int level) {
+  if (level == -1) return c->L;
+  if (level < 0 || level > c->L) return -2;
+  return level;
+}
+
+template <typename F>
+int guarded(F &&fn) {
+  try {
+    return fn();
+  } catch (const HipFailure &e) {
+    return fail(SIPG_EHIP, e.what());
+  } catch (const std::bad_alloc &) {
+    return fail(SIPG_ENOMEM, "device or host allocation failed");
+  } catch (const std::invalid_argument &e) {
+    return fail(SIPG_EINVAL, e.what());
+  } catch (const std::exception &e) {
+    return fail(SIPG_EINVAL, e.what());
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void sipg_default_params(sipg_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->ne[0] = p->ne[1] = p->ne[2] = 4;
+  p->len[0] = p->len[1] = p->len[2] = 1.0;
+  p->P = 4;
+  p->penalty = 1.0;
+  p->overlap_mode = SIPG_OVL_MIN;
+  p->overlap = 0.08;
+  p->nsmooth_pre = 1;
+  p->nsmooth_post = 1;
+  p->smooth_growth = 1;
+  p->precond_bits = 64;
+}
+
+const char *sipg_last_error(void) { return g_err.c_str(); }
+
+int sipg_footprint(const sipg_params *p, size_t *bytes) {
+  if (!p || !bytes) return fail(SIPG_EINVAL, "null argument");
+  return guarded([&]() {
+    sipg::HierarchyHost H;
+    sipg::build_hierarchy(*p, H);
+    const int L = (int)H.lev.size() - 1;
+    const int64_t N = level_ndof(H, L);
+    size_t b = work_bytes(H, p->precond_bits == 32 ? sizeof(float) : sizeof(double));
+    if (p->precond_bits == 32) b += (size_t)level_ndof(H, 0) * sizeof(double);
+    b += 4 * (size_t)N * sizeof(double);                 // flexible CG vectors
+    b += (size_t)level_ndof(H, 0) * sizeof(double) * 3;  // coarse work
+    b += 1 << 20;                                        // tables and scalars (bound)
+    *bytes = b;
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_setup(const sipg_params *p, void *hip_stream, sipg_ctx **out) {
+  if (!p || !out) return fail(SIPG_EINVAL, "null argument");
+  *out = nullptr;
+  std::unique_ptr<sipg_ctx> c(new (std::nothrow) sipg_ctx());
+  if (!c) return fail(SIPG_ENOMEM, "host allocation failed");
+  int rc = guarded([&]() {
+    sipg::build_hierarchy(*p, c->H);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->L = (int)c->H.lev.size() - 1;
+    for (int d = 0; d < 3; ++d) c->mesh.ne[d] = p->ne[d];
+    c->mesh.E = p->ne[0] * p->ne[1] * p->ne[2];
+    upload_tables(c.get());
+    const int64_t N0 = level_ndof(c->H, 0), N = level_ndof(c->H, c->L);
+    c->u0 = c->alloc<double>(N0);
+    c->coarse.t0 = c->alloc<double>(N0);
+    c->coarse.t1 = c->alloc<double>(N0);
+    c->coarse.partial = c->alloc<double>(sipg::kCoarsePartials);
+    c->coarse.scalars = c->alloc<double>(4);
+    c->cg_r = c->alloc<double>(N);
+    c->cg_p = c->alloc<double>(N);
+    c->cg_q = c->alloc<double>(N);
+    c->cg_z = c->alloc<double>(N);
+    c->scal = c->alloc<double>(sipg::FS_COUNT);
+    // partial sums: the reductions use 2 * kDotBlocks, the fused p.Ap of the
+    // top-level apply one per apply workgroup
+    c->partial = c->alloc<double>(
+        std::max<size_t>(2 * sipg::kDotBlocks, sipg::apply_num_blocks(c->mesh.E, c->H.lev[c->L].n)));
+    c->rhs_k = c->alloc<int>(64 * 3);
+    c->rhs_phi = c->alloc<double>(64 * 3);
+    c->rhs_amp = c->alloc<double>(64);
+    if (hipHostMalloc((void **)&c->host_scal, sipg::FS_COUNT * sizeof(double)) != hipSuccess)
+      throw std::bad_alloc();
+    check(sipg::launch_fill<double>(c->scal, sipg::FS_COUNT, 0.0, c->stream), "init");
+    if (p->precond_bits == 64) ensure_work<double>(c.get());
+    else ensure_work<float>(c.get());
+    check(hipStreamSynchronize(c->stream), "setup");
+    return (int)SIPG_OK;
+  });
+  if (rc != SIPG_OK) return rc;
+  *out = c.release();
+  return SIPG_OK;
+}
+
+int sipg_destroy(sipg_ctx *c) {
+  if (!c) return SIPG_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  delete c;
+  return SIPG_OK;
+}
+
+int sipg_nlevels(const sipg_ctx *c, int *nlevels) {
+  if (!c || !nlevels) return fail(SIPG_EINVAL, "null argument");
+  *nlevels = c->L + 1;
+  return SIPG_OK;
+}
+
+int sipg_level_info(const sipg_ctx *c, int level, int *order, int no[3], int64_t *ndof) {
+  if (!c) return fail(SIPG_EINVAL, "null context");
+  const int l = resolve_level(c, level);
+  if (l < 0) return fail(SIPG_EINVAL, "level out of range");
+  if (order) *order = c->H.lev[l].p;
+  if (no)
+    for (int d = 0; d < 3; ++d) no[d] = c->H.lev[l].dir[d].no;
+  if (ndof) *ndof = level_ndof(c->H, l);
+  return SIPG_OK;
+}
+
+int sipg_rhs_fourier(sipg_ctx *c, int nmodes, const int32_t *k, const double *phi, const double *amp,
+                     double *b) {
+  if (!c || !k || !phi || !amp || !b) return fail(SIPG_EINVAL, "null argument");
+  if (nmodes < 1 || nmodes > 64) return fail(SIPG_EINVAL, "nmodes must be in 1..64");
+  for (int i = 0; i < 3 * nmodes; ++i)
+    if (!std::isfinite(phi[i])) return fail(SIPG_EINVAL, "non-finite phase");
+  for (int i = 0; i < nmodes; ++i)
+    if (!std::isfinite(amp[i])) return fail(SIPG_EINVAL, "non-finite amplitude");
+  return guarded([&]() {
+    const sipg::HierarchyHost &H = c->H;
+    check(hipMemcpyAsync(c->rhs_k, k, 3 * nmodes * sizeof(int), hipMemcpyHostToDevice, c->stream), "rhs");
+    check(hipMemcpyAsync(c->rhs_phi, phi, 3 * nmodes * sizeof(double), hipMemcpyHostToDevice, c->stream), "rhs");
+    check(hipMemcpyAsync(c->rhs_amp, amp, nmodes * sizeof(double), hipMemcpyHostToDevice, c->stream), "rhs");
+    sipg::RhsLaunch a{};
+    a.mesh = c->mesh;
+    a.n = H.lev[c->L].n;
+    a.xi = c->xi_top;
+    for (int d = 0; d < 3; ++d) {
+      a.mass[d] = c->mass_top[d];
+      a.h[d] = H.prm.len[d] / H.prm.ne[d];
+      a.len[d] = H.prm.len[d];
+    }
+    a.nmodes = nmodes;
+    a.k = c->rhs_k;
+    a.phi = c->rhs_phi;
+    a.amp = c->rhs_amp;
+    check(sipg::launch_rhs(a, b, c->stream), "rhs");
+    const int64_t N = level_ndof(H, c->L);
+    check(sipg::launch_sum_partials<double>(b, N, c->partial, c->stream), "rhs mean");
+    check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0 / (double)N, c->scal + sipg::FS_COUNT - 1,
+                                c->stream),
+          "rhs mean");
+    check(sipg::launch_sub_scalar<double>(b, N, c->scal + sipg::FS_COUNT - 1, c->stream), "rhs mean");
+    // the host-side copies of k/phi/amp must stay valid until the copies ran
+    check(hipStreamSynchronize(c->stream), "rhs");
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_apply_A(sipg_ctx *c, int level, const double *u, double *y) {
+  if (!c || !u || !y) return fail(SIPG_EINVAL, "null argument");
+  if (u == y) return fail(SIPG_EINVAL, "u and y must not alias");
+  const int l = resolve_level(c, level);
+  if (l < 0) return fail(SIPG_EINVAL, "level out of range");
+  return guarded([&]() {
+    op_apply<double>(c, l, u, y, nullptr);
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_residual(sipg_ctx *c, int level, const double *u, const double *f, double *r) {
+  if (!c || !u || !f || !r) return fail(SIPG_EINVAL, "null argument");
+  if (u == r) return fail(SIPG_EINVAL, "u and r must not alias");
+  const int l = resolve_level(c, level);
+  if (l < 0) return fail(SIPG_EINVAL, "level out of range");
+  return guarded([&]() {
+    op_residual<double>(c, l, u, f, r);
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_schwarz(sipg_ctx *c, int level, const double *r, double *u) {
+  if (!c || !r || !u) return fail(SIPG_EINVAL, "null argument");
+  if (r == u) return fail(SIPG_EINVAL, "r and u must not alias");
+  const int l = resolve_level(c, level);
+  if (l < 1) return fail(SIPG_EINVAL, "Schwarz smoothing needs level >= 1");
+  return guarded([&]() {
+    ensure_work<double>(c);
+    op_schwarz<double>(c, l, r, u, u);
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_smooth(sipg_ctx *c, int level, double *u, const double *f, int nsteps) {
+  if (!c || !u || !f) return fail(SIPG_EINVAL, "null argument");
+  if (u == f) return fail(SIPG_EINVAL, "u and f must not alias");
+  if (nsteps < 0) return fail(SIPG_EINVAL, "nsteps must be >= 0");
+  const int l = resolve_level(c, level);
+  if (l < 1) return fail(SIPG_EINVAL, "smoothing needs level >= 1");
+  return guarded([&]() {
+    ensure_work<double>(c);
+    for (int s = 0; s < nsteps; ++s) {
+      op_residual<double>(c, l, u, f, c->w64.r);
+      op_schwarz<double>(c, l, c->w64.r, u, u);
+    }
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_restrict(sipg_ctx *c, int level, const double *r_fine, double *f_coarse) {
+  if (!c || !r_fine || !f_coarse) return fail(SIPG_EINVAL, "null argument");
+  const int l = resolve_level(c, level);
+  if (l < 1) return fail(SIPG_EINVAL, "restriction needs level >= 1");
+  return guarded([&]() {
+    // J^T r = J^T (r - A 0): the fused residual-restriction kernel with u = 0
+    ensure_work<double>(c);
+    double *zero = c->w64.uL;
+    check(sipg::launch_fill<double>(zero, level_ndof(c->H, l), 0.0, c->stream), "fill");
+    op_residual_restrict<double>(c, l, zero, r_fine, f_coarse);
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_prolong_add(sipg_ctx *c, int level, const double *u_coarse, double *u_fine) {
+  if (!c || !u_coarse || !u_fine) return fail(SIPG_EINVAL, "null argument");
+  const int l = resolve_level(c, level);
+  if (l < 1) return fail(SIPG_EINVAL, "prolongation needs level >= 1");
+  return guarded([&]() {
+    op_prolong<double, double>(c, l, u_coarse, nullptr, u_fine);
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_coarse_solve(sipg_ctx *c, const double *f0, double *u0) {
+  if (!c || !f0 || !u0) return fail(SIPG_EINVAL, "null argument");
+  if (f0 == u0) return fail(SIPG_EINVAL, "f0 and u0 must not alias");
+  return guarded([&]() {
+    check(sipg::launch_coarse<double>(c->coarse, f0, u0, true, c->stream), "coarse");
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_vcycle(sipg_ctx *c, double *u, const double *f) {
+  if (!c || !u || !f) return fail(SIPG_EINVAL, "null argument");
+  if (u == f) return fail(SIPG_EINVAL, "u and f must not alias");
+  return guarded([&]() {
+    vcycle_impl<double>(c, u, f, false, nullptr);
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_precond(sipg_ctx *c, const double *r, double *z) {
+  if (!c || !r || !z) return fail(SIPG_EINVAL, "null argument");
+  if (r == z) return fail(SIPG_EINVAL, "r and z must not alias");
+  return guarded([&]() {
+    precond_impl(c, r, z);
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_mg_solve(sipg_ctx *c, double *u, const double *f, double rtol, int maxcyc, int *ncyc,
+                  double *relres) {
+  if (!c || !u || !f) return fail(SIPG_EINVAL, "null argument");
+  if (u == f) return fail(SIPG_EINVAL, "u and f must not alias");
+  if (!(rtol > 0.0) || maxcyc < 0) return fail(SIPG_EINVAL, "need rtol > 0 and maxcyc >= 0");
+  return guarded([&]() { return mg_solve_impl(c, u, f, rtol, maxcyc, ncyc, relres); });
+}
+
+int sipg_pcg_solve(sipg_ctx *c, double *u, const double *f, double rtol, int maxit, int *iters,
+                   double *relres) {
+  if (!c || !u || !f) return fail(SIPG_EINVAL, "null argument");
+  if (u == f) return fail(SIPG_EINVAL, "u and f must not alias");
+  if (!(rtol > 0.0) || maxit < 0) return fail(SIPG_EINVAL, "need rtol > 0 and maxit >= 0");
+  return guarded([&]() { return pcg_solve_impl(c, u, f, rtol, maxit, iters, relres); });
+}
+
+int sipg_time_kernel(sipg_ctx *c, int kernel, int level, int bits, int reps, double *ms) {
+  if (!c || !ms) return fail(SIPG_EINVAL, "null argument");
+  if (reps < 1 || reps > 100000) return fail(SIPG_EINVAL, "reps must be in 1..100000");
+  if (bits != 64 && bits != 32) return fail(SIPG_EINVAL, "bits must be 64 or 32");
+  const int l = resolve_level(c, level);
+  if (l < 1) return fail(SIPG_EINVAL, "level must be >= 1");
+  if (kernel < SIPG_KERNEL_RESIDUAL || kernel > SIPG_KERNEL_PROLONG) return fail(SIPG_EINVAL, "unknown kernel");
+  return guarded([&]() {
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      ensure_work<T>(c);
+      Work<T> &w = work_of<T>(c);
+      const int64_t N = level_ndof(c->H, l);
+      T *u = w.uL, *f = w.fL, *r = w.r;
+      check(sipg::launch_fill<T>(u, N, (T)0.25, c->stream), "fill");
+      check(sipg::launch_fill<T>(f, N, (T)0.5, c->stream), "fill");
+      check(sipg::launch_fill<T>(r, N, (T)0.75, c->stream), "fill");
+      const LevelTabs<T> &t = tabs_of<T>(c, l);
+      sipg::SchwarzLaunch<T> sa{c->mesh, t.n, t.schwarz, r, w.C, u, u};
+      check(sipg::launch_schwarz_local<T>(sa, c->stream), "schwarz");  // valid corrections in C
+      hipEvent_t e0, e1;
+      check(hipEventCreate(&e0), "event");
+      check(hipEventCreate(&e1), "event");
+      check(hipEventRecord(e0, c->stream), "event");
+      for (int i = 0; i < reps; ++i) {
+        switch (kernel) {
+          case SIPG_KERNEL_RESIDUAL: op_residual<T>(c, l, u, f, r); break;
+          case SIPG_KERNEL_SCHWARZ_SOLVE: check(sipg::launch_schwarz_local<T>(sa, c->stream), "schwarz"); break;
+          case SIPG_KERNEL_SCHWARZ_ASSEMBLE: check(sipg::launch_schwarz_assemble<T>(sa, c->stream), "assemble"); break;
+          case SIPG_KERNEL_RESTRICT: op_residual_restrict<T>(c, l, u, f, w.f[l - 1]); break;
+          case SIPG_KERNEL_PROLONG:
+            if (l == 1) op_prolong<T, double>(c, 1, c->u0, nullptr, u);
+            else op_prolong<T, T>(c, l, w.u[l - 1], nullptr, u);
+            break;
+        }
+      }
+      check(hipEventRecord(e1, c->stream), "event");
+      check(hipEventSynchronize(e1), "event");
+      float el = 0.f;
+      check(hipEventElapsedTime(&el, e0, e1), "event");
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      *ms = (double)el / reps;
+    };
+    if (bits == 64) run(double());
+    else run(float());
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_residual_history(const sipg_ctx *c, double *out, int cap, int *n) {
+  if (!c || !n) return fail(SIPG_EINVAL, "null argument");
+  *n = (int)c->hist.size();
+  if (out)
+    for (int i = 0; i < cap && i < *n; ++i) out[i] = c->hist[i];
+  return SIPG_OK;
+}
+
+int sipg_host_table(const sipg_params *p, int level, int dir, int which, double *out, int cap, int *count) {
+  if (!p || !count) return fail(SIPG_EINVAL, "null argument");
+  if (dir < 0 || dir > 2) return fail(SIPG_EINVAL, "dir must be 0, 1 or 2");
+  return guarded([&]() {
+    sipg::HierarchyHost H;
+    sipg::build_hierarchy(*p, H);
+    const int L = (int)H.lev.size() - 1;
+    const int l = level == -1 ? L : level;
+    if (l < 0 || l > L) throw std::invalid_argument("level out of range");
+    const sipg::Dir1D &D = H.lev[l].dir[dir];
+    std::vector<double> v;
+    switch (which) {
+      case SIPG_TAB_NODES: v = D.xi; break;
+      case SIPG_TAB_WEIGHTS: v = D.w; break;
+      case SIPG_TAB_DERIV: v = D.D; break;
+      case SIPG_TAB_MASS: v = D.mass; break;
+      case SIPG_TAB_LDIAG: v = D.Ld; break;
+      case SIPG_TAB_LUPPER: v = D.U; break;
+      case SIPG_TAB_OVERLAP: v = {(double)D.no}; break;
+      case SIPG_TAB_SUB_L: v = D.Ls; break;
+      case SIPG_TAB_SUB_M: v = D.Ms; break;
+      case SIPG_TAB_SUB_LAM: v = D.lam; break;
+      case SIPG_TAB_SUB_S: v = D.S; break;
+      case SIPG_TAB_SUB_W: v = D.wsub; break;
+      case SIPG_TAB_INTERP: v = H.lev[l].J; break;
+      case SIPG_TAB_COARSE_LAM: v = H.coarse.lam[dir]; break;
+      case SIPG_TAB_COARSE_S: v = H.coarse.S[dir]; break;
+      default: throw std::invalid_argument("unknown table");
+    }
+    if ((which >= SIPG_TAB_SUB_L && which <= SIPG_TAB_SUB_W) && l == 0)
+      throw std::invalid_argument("level 0 has no subdomain tables");
+    if (which == SIPG_TAB_INTERP && l == 0) throw std::invalid_argument("level 0 has no interpolation");
+    *count = (int)v.size();
+    if (out)
+      for (int i = 0; i < cap && i < (int)v.size(); ++i) out[i] = v[i];
+    return (int)SIPG_OK;
+  });
+}
+
+}  // extern "C"
