@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Benchmark of the p-multigrid solve: unknowns solved per second to a
+relative residual of 1e-10, on one MI355X.
+
+A step is one complete solve from x0 = 0 of a seeded synthetic problem (the
+right-hand side already resident in HBM): every kernel of the hot path runs in
+it (residuals, Schwarz local solves and assembly, restriction, coarse
+pseudo-inverse, prolongation, norms).  Default workload: the periodic unit
+cube with 16^3 elements at P = 8 (2,985,984 unknowns, the paper's own P = 8
+mesh of its isotropic study), overlap delta_O = 0.08 dx, V(1,1) multigrid,
+FP64.  Prints one JSON line on stdout; progress goes to stderr.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "unknowns solved/s to rel. residual 1e-10 (FP64 vs mixed); p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def schwarz_flops(m):
+    """Algorithmic flops of one subdomain's fast-diagonalization solve:
+    three forward and three backward 1D contractions (2 flops per
+    multiply-add) and one division per entry."""
+    mx, my, mz = m
+    vol = mx * my * mz
+    return 4 * vol * (mx + my + mz) + vol
+
+
+def level_geometry(s, l):
+    info = s.level_info(l)
+    n = info["order"] + 1
+    m = tuple(n + 2 * no for no in info["no"])
+    return n, m, info["ndof"]
+
+
+def cpu_baseline(wl, cycles, k, phi, amp):
+    """The FP64 oracle on the host: time two V-cycles plus their residual
+    norms of the same solve, scale to the solve's cycle count."""
+    import numpy as np
+    import oracle
+    from oracle.multigrid import _vcycle_global
+    from oracle.sipg import to_global
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        blas = 1
+    h = oracle.Hierarchy(wl.ne, wl.length, wl.P, overlap=wl.overlap, omega=wl.omega, growth=wl.growth)
+    b = oracle.fourier_rhs(k, phi, amp, h)
+    B = to_global(b, h.ne, h.top.n)
+    X = np.zeros_like(B)
+    lev = h.top
+    t0 = time.perf_counter()
+    nsample = 5
+    for _ in range(nsample):
+        float(np.linalg.norm(B - lev.A(X)))
+        X = _vcycle_global(X, B, h)
+    t_pair = (time.perf_counter() - t0) / nsample
+    t0 = time.perf_counter()
+    float(np.linalg.norm(B - lev.A(X)))
+    t_res = time.perf_counter() - t0
+    t_solve = cycles * t_pair + t_res
+    return {
+        "value": wl.ndof / t_solve,
+        "unit": "unknowns/s",
+        "cores": int(blas),
+        "kind": "oracle",
+        "sample": (f"{nsample} V-cycles (each with its residual norm) of the same {wl.name} solve in the "
+                   f"FP64 NumPy oracle on {platform.processor() or platform.machine()} "
+                   f"({os.cpu_count()} logical CPUs, BLAS threads {blas}, elementwise work single-threaded), "
+                   f"scaled to the solve's {cycles} cycles: {t_pair:.2f} s per cycle"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cube16_p8_rel")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--reps", type=int, default=20, help="launches per kernel timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this solver's build runs on a single MI355X "
+              "(the multi-GPU decomposition is described, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+    from paper_1612_04796_amd import sipg
+    from paper_1612_04796_amd.workloads import WORKLOADS, fourier_modes
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    wl = WORKLOADS[args.workload]
+    log(f"workload {wl.name}: ne={wl.ne} P={wl.P} overlap={wl.overlap} N={wl.ndof}")
+    s = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
+                    smooth_growth=wl.growth)
+    N = s.ndof()
+    k, phi, amp = fourier_modes(0, wl.kmax)
+    b = torch.zeros(N, dtype=torch.float64, device="cuda")
+    s.rhs_fourier(k, phi, amp, b)
+    x = torch.zeros_like(b)
+    solve = s.mg_solve if wl.solver == "mg" else s.pcg_solve
+
+    def step():
+        x.zero_()
+        return solve(x, b, 1e-10, 200)
+
+    for i in range(args.warmup):
+        it, rr = step()
+        log(f"warmup {i}: {it} iterations, rel. residual {rr:.2e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for i in range(args.steps):
+        it, rr = step()
+        iters.append(it)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = 1e3 * elapsed / args.steps
+    value = N * args.steps / elapsed
+    log(f"timed {args.steps} solves: {ms:.3f} ms/solve, {value:.4g} unknowns/s, iterations {iters}, "
+        f"rel. residual {rr:.2e}")
+
+    # ---- per-kernel timings on the top level (HIP events on the library stream)
+    L = s.L
+    n, m, _ = level_geometry(s, L)
+    E = wl.ne[0] * wl.ne[1] * wl.ne[2]
+    kern = {}
+    for name in ("residual", "schwarz_solve", "schwarz_assemble", "restrict", "prolong"):
+        kern[name] = s.time_kernel(name, level=L, bits=64, reps=args.reps)
+    cyc = iters[-1]
+    # launches per solve of the top-level kernels (MG: the residual of each
+    # convergence check feeds the first pre-smoothing step)
+    per_solve = {"residual": 2 * cyc + 1, "schwarz_solve": 2 * cyc, "schwarz_assemble": 2 * cyc,
+                 "restrict": cyc, "prolong": cyc}
+    if wl.solver != "mg":
+        per_solve = {"residual": 2 * cyc + 1, "schwarz_solve": 2 * cyc + 2,
+                     "schwarz_assemble": 2 * cyc + 2, "restrict": cyc + 1, "prolong": cyc + 1}
+    share = {kname: kern[kname] * per_solve[kname] for kname in kern}
+    dominant = max(share, key=share.get)
+    log("top-level kernel ms/launch: " + ", ".join(f"{kk}={vv:.4f}" for kk, vv in kern.items())
+        + f"; dominant {dominant}")
+    if dominant == "schwarz_solve":
+        work = schwarz_flops(m) * E
+        achieved = work / (kern[dominant] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None, "kernel": "schwarz_lds_kernel",
+                "work_per_launch": work, "ms_per_launch": kern[dominant]}
+    else:
+        bytes_per = {"residual": 24, "schwarz_assemble": 24, "restrict": 16 + 8 / 8, "prolong": 16 + 8 / 8}
+        work = bytes_per.get(dominant, 24) * N
+        achieved = work / (kern[dominant] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dominant,
+                "work_per_launch": work, "ms_per_launch": kern[dominant]}
+
+    # ---- flexible CG on the same workload, FP64 and FP32 preconditioner
+    detail = {"kernels_ms_per_launch": kern, "launches_per_solve": per_solve,
+              "iterations": cyc, "final_relres": rr}
+    for bits in (64, 32):
+        s2 = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
+                         smooth_growth=wl.growth, precond_bits=bits)
+        for _ in range(max(1, args.warmup)):
+            x.zero_()
+            s2.pcg_solve(x, b, 1e-10, 200)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            x.zero_()
+            it2, rr2 = s2.pcg_solve(x, b, 1e-10, 200)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        detail[f"fcg_precond_fp{bits}"] = {"unknowns_per_s": N * args.steps / el,
+                                           "ms_per_solve": 1e3 * el / args.steps,
+                                           "iterations": it2, "final_relres": rr2}
+        log(f"FCG, FP{bits} preconditioner: {1e3 * el / args.steps:.3f} ms/solve, {it2} iterations")
+        s2.close()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: periodic box {wl.length}, {wl.ne[0]}x{wl.ne[1]}x{wl.ne[2]} "
+                               f"elements, P={wl.P} GLL SIPG, overlap {wl.overlap} {wl.omega}, "
+                               f"V(1,1) {'MG' if wl.solver == 'mg' else 'MG-preconditioned flexible CG'} "
+                               f"from x0=0 to rel. residual 1e-10, seeded 20-mode Fourier load",
+                   "ne": list(wl.ne), "P": wl.P, "ndof": N, "solver": wl.solver,
+                   "overlap": wl.overlap, "omega": wl.omega},
+        "roofline": roof,
+        "detail": detail,
+    }
+    if rank == 0 and not args.no_cpu_baseline:
+        log("cpu baseline: oracle sample ...")
+        out["cpu_baseline"] = cpu_baseline(wl, cyc, k, phi, amp)
+        log(f"cpu baseline {out['cpu_baseline']['value']:.4g} unknowns/s")
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
