@@ -56,6 +56,7 @@ struct SchwarzLaunch {
   SchwarzTabs<T> tabs;
   const T *r;
   T *C;             // scratch of E * m_x*m_y*m_z values
+  const T *ilam;    // 1 / (lam_x[a] + lam_y[b] + lam_z[c]), layout [c][b][a]
   const T *u_in;
   T *u_out;
 };

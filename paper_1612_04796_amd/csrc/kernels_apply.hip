@@ -2,20 +2,26 @@
 //   A = Mz x My x Lx + Mz x Ly x Mx + Lz x My x Mx,
 // by sum factorization, and the inter-level transfers of Sec. 3.2.
 //
-// Each workgroup owns `epb` consecutive elements.  The element data is staged
-// in LDS; one thread owns one 1D line of an element per direction, keeps the
-// line in registers and applies the n x n element block of L_d (uniform table
-// entries, loaded through the scalar cache).  Face coupling to the two
-// neighbours in a direction needs, per line, the neighbour's value at the
-// shared face and its one-sided derivative there (a dot product with the
-// first or last row of D), so the neighbour line is read from global memory;
-// XCD-aware block numbering keeps those re-reads in L2.
+// Each workgroup owns EPB consecutive elements.  Thread t owns one x line,
+// one y line and one z line of one element (the same index pair in the three
+// orientations).  In a prologue every thread reads the six face-neighbour
+// lines it needs and reduces each to the two numbers the face coupling uses
+// (the neighbour value at the shared face and its one-sided derivative
+// there), so all neighbour loads of the workgroup are in flight at once.  The
+// element's own data is staged in LDS and each direction's n x n block of L_d
+// is applied with the line in registers (uniform table entries through the
+// scalar cache).  XCD-aware block numbering keeps neighbour re-reads in L2.
 //
 // With DL = D[0][:]/h, DR = D[p][:]/h the coupling of line v of element e to
 // its right neighbour line vr and left neighbour line vl is
 //   c[i] = DR[i] vr[0] - DL[i] vl[p]
 //        - [i = p] (DL . vr + mu vr[0]) + [i = 0] (DR . vl - mu vl[p]).
+//
+// Levels are 1, 2, 4, ..., 2^k < P, P, so the coarse size below a level of n
+// nodes is fixed by n: n_c = 2^floor(log2(n - 2)) + 1.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "device_common.h"
 #include "kernels.h"
@@ -26,328 +32,307 @@ namespace {
 
 enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_RESTRICT = 2 };
 
+constexpr int coarse_n(int n) {
+  int q = 1;
+  while (2 * q <= n - 2) q *= 2;
+  return n >= 3 ? q + 1 : 0;
+}
+
+template <int N>
+struct ApplyShape {
+  static constexpr int N2 = N * N, N3 = N2 * N;
+  static constexpr int EPB = (256 / N2) > 0 ? 256 / N2 : 1;
+  static constexpr int LINES = EPB * N2;
+  static constexpr int NTH0 = (LINES + 63) / 64 * 64;
+  static constexpr int NTH = NTH0 > 1024 ? 1024 : NTH0;
+  static constexpr size_t SHM = 2 * (size_t)EPB * N3;  // elements of T
+};
+
+// Face data of one line direction: neighbour value at the shared face (v) and
+// its scaled one-sided normal derivative (g), right (+) and left (-) side.
+template <typename T>
+struct FaceData {
+  T vR, gR, vL, gL;
+};
+
+template <typename T, int N>
+__device__ __forceinline__ FaceData<T> face_data(const T *__restrict__ lr, const T *__restrict__ ll, int st,
+                                                 const T *__restrict__ DL, const T *__restrict__ DR) {
+  FaceData<T> fd;
+  T gR = 0, gL = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    gR += DL[i] * lr[i * st];
+    gL += DR[i] * ll[i * st];
+  }
+  fd.vR = lr[0];
+  fd.vL = ll[(N - 1) * st];
+  fd.gR = gR;
+  fd.gL = gL;
+  return fd;
+}
+
+// (L_d v)[i] including the face coupling, for the line v in registers.
+template <typename T, int N>
+__device__ __forceinline__ T line_op(const T (&v)[N], int i, const T *__restrict__ Ld, const T *__restrict__ DL,
+                                     const T *__restrict__ DR, T mu, const FaceData<T> &fd) {
+  T acc = DR[i] * fd.vR - DL[i] * fd.vL;
+#pragma unroll
+  for (int q = 0; q < N; ++q) acc += Ld[i * N + q] * v[q];
+  if (i == N - 1) acc -= fd.gR + mu * fd.vR;
+  if (i == 0) acc += fd.gL - mu * fd.vL;
+  return acc;
+}
+
 template <typename T, int N, int MODE, bool DOT>
-__global__ void __launch_bounds__(1024)
-apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restrict__ f,
-             T *__restrict__ out, int epb, T *__restrict__ partial, const T *__restrict__ J, int nc) {
-  constexpr int N2 = N * N, N3 = N2 * N;
+__global__ void __launch_bounds__(ApplyShape<N>::NTH)
+apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restrict__ f, T *__restrict__ out,
+             T *__restrict__ partial, const T *__restrict__ J) {
+  using Sh = ApplyShape<N>;
+  constexpr int N2 = Sh::N2, N3 = Sh::N3, EPB = Sh::EPB;
+  constexpr int NC = coarse_n(N);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *su = reinterpret_cast<T *>(smem_raw);
-  T *sy = su + epb * N3;
+  T *sy = su + EPB * N3;
   __shared__ T red[16];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int e0 = blk * epb;
-  const int nloc = min(epb, g.E - e0);
-  const int tid = threadIdx.x, nth = blockDim.x;
+  const int e0 = blk * EPB;
+  const int nloc = min(EPB, g.E - e0);
+  const int t = threadIdx.x;
+  const bool active = t < nloc * N2;
+  const int le = t / N2, pq = t - le * N2;
+  const int p = pq / N, q = pq - p * N;  // x line (k=p, j=q); y line (k=p, i=q); z line (j=p, i=q)
 
-  for (int idx = tid; idx < nloc * N3; idx += nth) su[idx] = u[(size_t)e0 * N3 + idx];
+  FaceData<T> fx{}, fy{}, fz{};
+  if (active) {
+    const int e = e0 + le;
+    const int ex = e % g.ne[0], rest = e / g.ne[0];
+    const int ey = rest % g.ne[1], ez = rest / g.ne[1];
+    const T *uxr = u + (size_t)elem_index(g, wrap(ex + 1, g.ne[0]), ey, ez) * N3 + pq * N;
+    const T *uxl = u + (size_t)elem_index(g, wrap(ex - 1, g.ne[0]), ey, ez) * N3 + pq * N;
+    const T *uyr = u + (size_t)elem_index(g, ex, wrap(ey + 1, g.ne[1]), ez) * N3 + p * N2 + q;
+    const T *uyl = u + (size_t)elem_index(g, ex, wrap(ey - 1, g.ne[1]), ez) * N3 + p * N2 + q;
+    const T *uzr = u + (size_t)elem_index(g, ex, ey, wrap(ez + 1, g.ne[2])) * N3 + pq;
+    const T *uzl = u + (size_t)elem_index(g, ex, ey, wrap(ez - 1, g.ne[2])) * N3 + pq;
+    fx = face_data<T, N>(uxr, uxl, 1, tb.DL[0], tb.DR[0]);
+    fy = face_data<T, N>(uyr, uyl, N, tb.DL[1], tb.DR[1]);
+    fz = face_data<T, N>(uzr, uzl, N2, tb.DL[2], tb.DR[2]);
+  }
+  for (int idx = t; idx < nloc * N3; idx += Sh::NTH) su[idx] = u[(size_t)e0 * N3 + idx];
   __syncthreads();
-  const int nlines = nloc * N2;
 
-  // ---- x lines (le, k, j): contiguous
-  {
-    const T *__restrict__ Ld = tb.Ld[0];
-    const T *__restrict__ DL = tb.DL[0];
-    const T *__restrict__ DR = tb.DR[0];
-    const T mu = tb.mu[0];
-    for (int t = tid; t < nlines; t += nth) {
-      const int le = t / N2, kj = t - le * N2;
-      const int k = kj / N, j = kj - k * N;
-      const int e = e0 + le;
-      const int ex = e % g.ne[0], rest = e / g.ne[0];
-      const int ey = rest % g.ne[1], ez = rest / g.ne[1];
-      const T *lr = u + (size_t)elem_index(g, wrap(ex + 1, g.ne[0]), ey, ez) * N3 + kj * N;
-      const T *ll = u + (size_t)elem_index(g, wrap(ex - 1, g.ne[0]), ey, ez) * N3 + kj * N;
-      T v[N];
-      T gR = 0, gL = 0;
+  if (active) {  // x: line (k=p, j=q), contiguous
+    T *sl = su + le * N3 + pq * N;
+    T *yl = sy + le * N3 + pq * N;
+    T v[N];
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        v[i] = su[le * N3 + kj * N + i];
-        gR += DL[i] * lr[i];
-        gL += DR[i] * ll[i];
-      }
-      const T vR = lr[0], vL = ll[N - 1];
-      const T sc = tb.M[2][k] * tb.M[1][j];
+    for (int i = 0; i < N; ++i) v[i] = sl[i];
+    const T sc = tb.M[2][p] * tb.M[1][q];
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        T acc = DR[i] * vR - DL[i] * vL;
-#pragma unroll
-        for (int q = 0; q < N; ++q) acc += Ld[i * N + q] * v[q];
-        if (i == N - 1) acc -= gR + mu * vR;
-        if (i == 0) acc += gL - mu * vL;
-        sy[le * N3 + kj * N + i] = sc * acc;
-      }
-    }
+    for (int i = 0; i < N; ++i) yl[i] = sc * line_op<T, N>(v, i, tb.Ld[0], tb.DL[0], tb.DR[0], tb.mu[0], fx);
   }
   __syncthreads();
-
-  // ---- y lines (le, k, i): stride N
-  {
-    const T *__restrict__ Ld = tb.Ld[1];
-    const T *__restrict__ DL = tb.DL[1];
-    const T *__restrict__ DR = tb.DR[1];
-    const T mu = tb.mu[1];
-    for (int t = tid; t < nlines; t += nth) {
-      const int le = t / N2, ki = t - le * N2;
-      const int k = ki / N, i = ki - k * N;
-      const int e = e0 + le;
-      const int ex = e % g.ne[0], rest = e / g.ne[0];
-      const int ey = rest % g.ne[1], ez = rest / g.ne[1];
-      const int base = k * N2 + i;
-      const T *lr = u + (size_t)elem_index(g, ex, wrap(ey + 1, g.ne[1]), ez) * N3 + base;
-      const T *ll = u + (size_t)elem_index(g, ex, wrap(ey - 1, g.ne[1]), ez) * N3 + base;
-      T v[N];
-      T gR = 0, gL = 0;
+  if (active) {  // y: line (k=p, i=q), stride N
+    T *sl = su + le * N3 + p * N2 + q;
+    T *yl = sy + le * N3 + p * N2 + q;
+    T v[N];
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        v[j] = su[le * N3 + base + j * N];
-        gR += DL[j] * lr[j * N];
-        gL += DR[j] * ll[j * N];
-      }
-      const T vR = lr[0], vL = ll[(N - 1) * N];
-      const T sc = tb.M[2][k] * tb.M[0][i];
+    for (int j = 0; j < N; ++j) v[j] = sl[j * N];
+    const T sc = tb.M[2][p] * tb.M[0][q];
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        T acc = DR[j] * vR - DL[j] * vL;
-#pragma unroll
-        for (int q = 0; q < N; ++q) acc += Ld[j * N + q] * v[q];
-        if (j == N - 1) acc -= gR + mu * vR;
-        if (j == 0) acc += gL - mu * vL;
-        sy[le * N3 + base + j * N] += sc * acc;
-      }
-    }
+    for (int j = 0; j < N; ++j) yl[j * N] += sc * line_op<T, N>(v, j, tb.Ld[1], tb.DL[1], tb.DR[1], tb.mu[1], fy);
   }
   __syncthreads();
-
-  // ---- z lines (le, j, i): stride N^2; finishes the operator
   T dot = 0;
-  {
-    const T *__restrict__ Ld = tb.Ld[2];
-    const T *__restrict__ DL = tb.DL[2];
-    const T *__restrict__ DR = tb.DR[2];
-    const T mu = tb.mu[2];
-    for (int t = tid; t < nlines; t += nth) {
-      const int le = t / N2, ji = t - le * N2;
-      const int j = ji / N, i = ji - j * N;
-      const int e = e0 + le;
-      const int ex = e % g.ne[0], rest = e / g.ne[0];
-      const int ey = rest % g.ne[1], ez = rest / g.ne[1];
-      const T *lr = u + (size_t)elem_index(g, ex, ey, wrap(ez + 1, g.ne[2])) * N3 + ji;
-      const T *ll = u + (size_t)elem_index(g, ex, ey, wrap(ez - 1, g.ne[2])) * N3 + ji;
-      T v[N];
-      T gR = 0, gL = 0;
+  if (active) {  // z: line (j=p, i=q), stride N^2; completes the operator
+    T *sl = su + le * N3 + pq;
+    T *yl = sy + le * N3 + pq;
+    T v[N];
 #pragma unroll
-      for (int k = 0; k < N; ++k) {
-        v[k] = su[le * N3 + ji + k * N2];
-        gR += DL[k] * lr[k * N2];
-        gL += DR[k] * ll[k * N2];
-      }
-      const T vR = lr[0], vL = ll[(N - 1) * N2];
-      const T sc = tb.M[1][j] * tb.M[0][i];
+    for (int k = 0; k < N; ++k) v[k] = sl[k * N2];
+    const T sc = tb.M[1][p] * tb.M[0][q];
+    const size_t gbase = (size_t)(e0 + le) * N3 + pq;
 #pragma unroll
-      for (int k = 0; k < N; ++k) {
-        T acc = DR[k] * vR - DL[k] * vL;
-#pragma unroll
-        for (int q = 0; q < N; ++q) acc += Ld[k * N + q] * v[q];
-        if (k == N - 1) acc -= gR + mu * vR;
-        if (k == 0) acc += gL - mu * vL;
-        const int li = le * N3 + ji + k * N2;
-        const T y = sy[li] + sc * acc;
-        const size_t gi = (size_t)e0 * N3 + li;
-        if (MODE == MODE_APPLY) {
-          out[gi] = y;
-          if (DOT) dot += v[k] * y;
-        } else if (MODE == MODE_RESID) {
-          out[gi] = f[gi] - y;
-        } else {
-          sy[li] = f[gi] - y;
-        }
+    for (int k = 0; k < N; ++k) {
+      const T y = yl[k * N2] + sc * line_op<T, N>(v, k, tb.Ld[2], tb.DL[2], tb.DR[2], tb.mu[2], fz);
+      if (MODE == MODE_APPLY) {
+        out[gbase + k * N2] = y;
+        if (DOT) dot += v[k] * y;
+      } else if (MODE == MODE_RESID) {
+        const T r = f[gbase + k * N2] - y;
+        out[gbase + k * N2] = r;
+        if (DOT) dot += r * r;
+      } else {
+        yl[k * N2] = f[gbase + k * N2] - y;
       }
     }
   }
   if (DOT) {
-    T s = block_reduce_sum(dot, red);
-    if (tid == 0) partial[blk] = s;
+    const T s = block_reduce_sum(dot, red);
+    if (t == 0) partial[blk] = s;
   }
-  if (MODE != MODE_RESTRICT) return;
-
-  // ---- restriction f_c = (J^T x J^T x J^T) r, element by element
-  __syncthreads();
-  // x: sy[le][k][j][i] -> su[le][k][j][a]
-  for (int t = tid; t < nlines; t += nth) {
-    const int le = t / N2, kj = t - le * N2;
-    T v[N];
+  if constexpr (MODE == MODE_RESTRICT) {
+    // f_c = (J^T x J^T x J^T) r per element; J is N x NC
+    __syncthreads();
+    if (active) {  // x: sy[le][k][j][i] -> su[le][k][j][a]
+      T v[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = sy[le * N3 + kj * N + i];
-    for (int a = 0; a < nc; ++a) {
-      T acc = 0;
+      for (int i = 0; i < N; ++i) v[i] = sy[le * N3 + pq * N + i];
 #pragma unroll
-      for (int i = 0; i < N; ++i) acc += J[i * nc + a] * v[i];
-      su[le * N3 + kj * nc + a] = acc;
+      for (int a = 0; a < NC; ++a) {
+        T acc = 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc += J[i * NC + a] * v[i];
+        su[le * N3 + pq * NC + a] = acc;
+      }
     }
-  }
-  __syncthreads();
-  // y: su[le][k][j][a] -> sy[le][k][b][a]; lines (le, k, a)
-  for (int t = tid; t < nloc * N * nc; t += nth) {
-    const int le = t / (N * nc), ka = t - le * N * nc;
-    const int k = ka / nc, a = ka - k * nc;
-    T v[N];
+    __syncthreads();
+    // y: su[le][k][j][a] -> sy[le][k][b][a]; lines (le, k, a)
+    for (int L = t; L < nloc * N * NC; L += Sh::NTH) {
+      const int l2 = L / (N * NC), ka = L - l2 * N * NC;
+      const int k = ka / NC, a = ka - k * NC;
+      T v[N];
 #pragma unroll
-    for (int j = 0; j < N; ++j) v[j] = su[le * N3 + (k * N + j) * nc + a];
-    for (int b = 0; b < nc; ++b) {
-      T acc = 0;
+      for (int j = 0; j < N; ++j) v[j] = su[l2 * N3 + (k * N + j) * NC + a];
 #pragma unroll
-      for (int j = 0; j < N; ++j) acc += J[j * nc + b] * v[j];
-      sy[le * N3 + (k * nc + b) * nc + a] = acc;
+      for (int b = 0; b < NC; ++b) {
+        T acc = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) acc += J[j * NC + b] * v[j];
+        sy[l2 * N3 + (k * NC + b) * NC + a] = acc;
+      }
     }
-  }
-  __syncthreads();
-  // z: sy[le][k][b][a] -> out[e][c][b][a]; lines (le, b, a)
-  const int nc2 = nc * nc, nc3 = nc2 * nc;
-  for (int t = tid; t < nloc * nc2; t += nth) {
-    const int le = t / nc2, ba = t - le * nc2;
-    T v[N];
+    __syncthreads();
+    // z: sy[le][k][b][a] -> out[e][c][b][a]; lines (le, b, a)
+    constexpr int NC2 = NC * NC, NC3 = NC2 * NC;
+    for (int L = t; L < nloc * NC2; L += Sh::NTH) {
+      const int l2 = L / NC2, ba = L - l2 * NC2;
+      T v[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = sy[le * N3 + k * nc2 + ba];
-    for (int c = 0; c < nc; ++c) {
-      T acc = 0;
+      for (int k = 0; k < N; ++k) v[k] = sy[l2 * N3 + k * NC2 + ba];
 #pragma unroll
-      for (int k = 0; k < N; ++k) acc += J[k * nc + c] * v[k];
-      out[(size_t)(e0 + le) * nc3 + c * nc2 + ba] = acc;
+      for (int c = 0; c < NC; ++c) {
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) acc += J[k * NC + c] * v[k];
+        out[(size_t)(e0 + l2) * NC3 + c * NC2 + ba] = acc;
+      }
     }
   }
 }
 
-// u_f += (J x J x J)(u_c - mean), element by element; J is NF x nc.
+// u_f += (J x J x J)(u_c - mean), element by element; J is NF x NC.
 template <typename T, typename TC, int NF>
-__global__ void __launch_bounds__(1024)
-prolong_kernel(int E, const T *__restrict__ J, int nc, const TC *__restrict__ uc,
-               const double *__restrict__ mean, T *__restrict__ uf, int epb) {
-  constexpr int NF2 = NF * NF, NF3 = NF2 * NF;
+__global__ void __launch_bounds__(ApplyShape<NF>::NTH)
+prolong_kernel(int E, const T *__restrict__ J, const TC *__restrict__ uc, const double *__restrict__ mean,
+               T *__restrict__ uf) {
+  using Sh = ApplyShape<NF>;
+  constexpr int NC = coarse_n(NF);
+  constexpr int NF2 = NF * NF, NF3 = NF2 * NF, NC2 = NC * NC, NC3 = NC2 * NC, EPB = Sh::EPB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *s0 = reinterpret_cast<T *>(smem_raw);  // epb * NF3 each
-  T *s1 = s0 + epb * NF3;
-  T *s2 = s1 + epb * NF3;
+  T *s0 = reinterpret_cast<T *>(smem_raw);  // EPB * NC3  : coarse element
+  T *s1 = s0 + EPB * NC3;                   // EPB * NC2 * NF : after x
+  T *s2 = s1 + EPB * NC2 * NF;              // EPB * NC * NF2 : after y
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int e0 = blk * epb;
-  const int nloc = min(epb, E - e0);
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int nc2 = nc * nc, nc3 = nc2 * nc;
+  const int e0 = blk * EPB;
+  const int nloc = min(EPB, E - e0);
+  const int t = threadIdx.x;
   const T m = mean ? (T)(*mean) : (T)0;
-  for (int idx = tid; idx < nloc * nc3; idx += nth) {
-    const int le = idx / nc3, r = idx - le * nc3;
-    s0[le * NF3 + r] = (T)uc[(size_t)e0 * nc3 + idx] - m;
-  }
+  for (int idx = t; idx < nloc * NC3; idx += Sh::NTH) s0[idx] = (T)uc[(size_t)e0 * NC3 + idx] - m;
   __syncthreads();
-  // x: s0[le][c][b][a] -> s1[le][c][b][i]
-  for (int t = tid; t < nloc * nc2; t += nth) {
-    const int le = t / nc2, cb = t - le * nc2;
-    T v[NF];
+  for (int L = t; L < nloc * NC2; L += Sh::NTH) {  // x: lines (le, c, b)
+    const int le = L / NC2, cb = L - le * NC2;
+    T v[NC];
 #pragma unroll
-    for (int a = 0; a < NF; ++a) v[a] = (a < nc) ? s0[le * NF3 + cb * nc + a] : (T)0;
+    for (int a = 0; a < NC; ++a) v[a] = s0[le * NC3 + cb * NC + a];
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
       T acc = 0;
 #pragma unroll
-      for (int a = 0; a < NF; ++a)
-        if (a < nc) acc += J[i * nc + a] * v[a];
-      s1[le * NF3 + cb * NF + i] = acc;
+      for (int a = 0; a < NC; ++a) acc += J[i * NC + a] * v[a];
+      s1[le * NC2 * NF + cb * NF + i] = acc;
     }
   }
   __syncthreads();
-  // y: s1[le][c][b][i] -> s2[le][c][j][i]; lines (le, c, i)
-  for (int t = tid; t < nloc * nc * NF; t += nth) {
-    const int le = t / (nc * NF), ci = t - le * nc * NF;
+  for (int L = t; L < nloc * NC * NF; L += Sh::NTH) {  // y: lines (le, c, i)
+    const int le = L / (NC * NF), ci = L - le * NC * NF;
     const int c = ci / NF, i = ci - c * NF;
-    T v[NF];
+    T v[NC];
 #pragma unroll
-    for (int b = 0; b < NF; ++b) v[b] = (b < nc) ? s1[le * NF3 + (c * nc + b) * NF + i] : (T)0;
+    for (int b = 0; b < NC; ++b) v[b] = s1[le * NC2 * NF + (c * NC + b) * NF + i];
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
       T acc = 0;
 #pragma unroll
-      for (int b = 0; b < NF; ++b)
-        if (b < nc) acc += J[j * nc + b] * v[b];
-      s2[le * NF3 + (c * NF + j) * NF + i] = acc;
+      for (int b = 0; b < NC; ++b) acc += J[j * NC + b] * v[b];
+      s2[le * NC * NF2 + (c * NF + j) * NF + i] = acc;
     }
   }
   __syncthreads();
-  // z: s2[le][c][j][i] -> uf[e][k][j][i] += ...; lines (le, j, i)
-  for (int t = tid; t < nloc * NF2; t += nth) {
-    const int le = t / NF2, ji = t - le * NF2;
-    T v[NF];
+  for (int L = t; L < nloc * NF2; L += Sh::NTH) {  // z: lines (le, j, i)
+    const int le = L / NF2, ji = L - le * NF2;
+    T v[NC];
 #pragma unroll
-    for (int c = 0; c < NF; ++c) v[c] = (c < nc) ? s2[le * NF3 + c * NF2 + ji] : (T)0;
+    for (int c = 0; c < NC; ++c) v[c] = s2[le * NC * NF2 + c * NF2 + ji];
+    T *o = uf + (size_t)(e0 + le) * NF3 + ji;
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
       T acc = 0;
 #pragma unroll
-      for (int c = 0; c < NF; ++c)
-        if (c < nc) acc += J[k * nc + c] * v[c];
-      uf[(size_t)(e0 + le) * NF3 + k * NF2 + ji] += acc;
+      for (int c = 0; c < NC; ++c) acc += J[k * NC + c] * v[c];
+      o[k * NF2] += acc;
     }
   }
 }
 
-inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+template <typename K>
+hipError_t allow_lds(K kernel, size_t shm) {
+  if (shm <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+}
+
+template <typename T, int N, int MODE, bool DOT>
+hipError_t launch_mode(const ApplyLaunch<T> &a, hipStream_t st) {
+  using Sh = ApplyShape<N>;
+  const int nblk = (a.mesh.E + Sh::EPB - 1) / Sh::EPB;
+  const size_t shm = Sh::SHM * sizeof(T);
+  hipError_t e = allow_lds(apply_kernel<T, N, MODE, DOT>, shm);
+  if (e != hipSuccess) return e;
+  apply_kernel<T, N, MODE, DOT><<<nblk, Sh::NTH, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, a.partial, a.J);
+  return hipGetLastError();
+}
 
 template <typename T, int N>
 hipError_t launch_apply_n(const ApplyLaunch<T> &a, hipStream_t st) {
-  constexpr int N2 = N * N, N3 = N2 * N;
-  int epb = 256 / N2;
-  if (epb < 1) epb = 1;
-  if (a.mode == APPLY_RESTRICT && epb > 1) {
-    // the restriction reuses the two element buffers; nothing else to size
+  switch (a.mode) {
+    case APPLY_PLAIN:
+      return a.partial ? launch_mode<T, N, MODE_APPLY, true>(a, st) : launch_mode<T, N, MODE_APPLY, false>(a, st);
+    case APPLY_RESID:
+      return a.partial ? launch_mode<T, N, MODE_RESID, true>(a, st) : launch_mode<T, N, MODE_RESID, false>(a, st);
+    case APPLY_RESTRICT:
+      if constexpr (N >= 3) {
+        if (a.nc != coarse_n(N)) return hipErrorInvalidValue;
+        return launch_mode<T, N, MODE_RESTRICT, false>(a, st);
+      }
+      return hipErrorInvalidValue;
   }
-  const int nth = std::min(1024, round_up(epb * N2, 64));
-  const int nblk = (a.mesh.E + epb - 1) / epb;
-  const size_t shm = 2 * (size_t)epb * N3 * sizeof(T);
-  if (shm > 64 * 1024) {
-    hipError_t e = hipSuccess;
-    if (a.mode == APPLY_PLAIN && a.partial)
-      e = hipFuncSetAttribute((const void *)apply_kernel<T, N, MODE_APPLY, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    else if (a.mode == APPLY_PLAIN)
-      e = hipFuncSetAttribute((const void *)apply_kernel<T, N, MODE_APPLY, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    else if (a.mode == APPLY_RESID)
-      e = hipFuncSetAttribute((const void *)apply_kernel<T, N, MODE_RESID, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    else
-      e = hipFuncSetAttribute((const void *)apply_kernel<T, N, MODE_RESTRICT, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-  }
-  if (a.mode == APPLY_PLAIN && a.partial)
-    apply_kernel<T, N, MODE_APPLY, true><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, epb,
-                                                                 a.partial, a.J, a.nc);
-  else if (a.mode == APPLY_PLAIN)
-    apply_kernel<T, N, MODE_APPLY, false><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, epb,
-                                                                  a.partial, a.J, a.nc);
-  else if (a.mode == APPLY_RESID)
-    apply_kernel<T, N, MODE_RESID, false><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, epb,
-                                                                  a.partial, a.J, a.nc);
-  else
-    apply_kernel<T, N, MODE_RESTRICT, false><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, epb,
-                                                                     a.partial, a.J, a.nc);
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 template <typename T, typename TC, int NF>
 hipError_t launch_prolong_n(const ProlongLaunch<T, TC> &a, hipStream_t st) {
-  constexpr int NF2 = NF * NF, NF3 = NF2 * NF;
-  int epb = 256 / NF2;
-  if (epb < 1) epb = 1;
-  const int nth = std::min(1024, round_up(epb * NF2, 64));
-  const int nblk = (a.E + epb - 1) / epb;
-  const size_t shm = 3 * (size_t)epb * NF3 * sizeof(T);
-  if (shm > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)prolong_kernel<T, TC, NF>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if constexpr (NF >= 3) {
+    using Sh = ApplyShape<NF>;
+    constexpr int NC = coarse_n(NF);
+    if (a.nc != NC) return hipErrorInvalidValue;
+    const int nblk = (a.E + Sh::EPB - 1) / Sh::EPB;
+    const size_t shm = (size_t)Sh::EPB * (NC * NC * NC + NC * NC * NF + NC * NF * NF) * sizeof(T);
+    hipError_t e = allow_lds(prolong_kernel<T, TC, NF>, shm);
     if (e != hipSuccess) return e;
+    prolong_kernel<T, TC, NF><<<nblk, Sh::NTH, shm, st>>>(a.E, a.J, a.uc, a.mean, a.uf);
+    return hipGetLastError();
   }
-  prolong_kernel<T, TC, NF><<<nblk, nth, shm, st>>>(a.E, a.J, a.nc, a.uc, a.mean, a.uf, epb);
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 }  // namespace

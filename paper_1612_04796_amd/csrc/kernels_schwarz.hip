@@ -217,6 +217,220 @@ schwarz_assemble(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ C, cons
   u_out[idx] = (u_in ? u_in[idx] : (T)0) + sum;
 }
 
+// ---- fixed-size fast path ----------------------------------------------
+// Subdomain sizes known at compile time: all index arithmetic folds to
+// constants, the line arrays live in registers and the table rows are read
+// through the scalar cache.  SPB subdomains share a workgroup so that the
+// line phases fill whole wavefronts.  The forward contractions use the outer
+// product form (one LDS read feeds a whole S row), the backward ones the
+// inner product form (one WS row per output); the diagonal scaling uses the
+// precomputed 1 / (lam_x[a] + lam_y[b] + lam_z[c]) table.
+template <int MX, int MY, int MZ>
+struct FdmShape {
+  static constexpr int RX = MX | 1;
+  static constexpr int VOL = MX * MY * MZ;
+  static constexpr int TILE = MZ * MY * RX;
+  static constexpr int L1 = MY * MZ, L2 = MX * MZ, L3 = MX * MY;
+  static constexpr int LINES = L1 > L2 ? (L1 > L3 ? L1 : L3) : (L2 > L3 ? L2 : L3);
+  static constexpr int SPB = LINES >= 512 ? 1 : 512 / LINES;
+  static constexpr int NTH0 = (SPB * LINES + 63) / 64 * 64;
+  static constexpr int NTH = NTH0 > 1024 ? 1024 : NTH0;
+};
+
+template <typename T, int M>
+__device__ __forceinline__ void fwd_outer(T *base, int st, const T *__restrict__ S) {
+  T acc[M];
+#pragma unroll
+  for (int o = 0; o < M; ++o) acc[o] = 0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const T va = base[a * st];
+#pragma unroll
+    for (int o = 0; o < M; ++o) acc[o] += S[a * M + o] * va;
+  }
+#pragma unroll
+  for (int o = 0; o < M; ++o) base[o * st] = acc[o];
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void bwd_inner(T *base, int st, const T *__restrict__ WS) {
+  T v[M];
+#pragma unroll
+  for (int o = 0; o < M; ++o) v[o] = base[o * st];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    T acc = 0;
+#pragma unroll
+    for (int o = 0; o < M; ++o) acc += WS[a * M + o] * v[o];
+    base[a * st] = acc;
+  }
+}
+
+template <typename T, int N, int MX, int MY, int MZ>
+__global__ void __launch_bounds__((FdmShape<MX, MY, MZ>::NTH))
+schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ ilam, const T *__restrict__ r,
+                  T *__restrict__ C) {
+  using Sh = FdmShape<MX, MY, MZ>;
+  constexpr int RX = Sh::RX, VOL = Sh::VOL, TILE = Sh::TILE, SPB = Sh::SPB;
+  constexpr int NOX = (MX - N) / 2, NOY = (MY - N) / 2, NOZ = (MZ - N) / 2;
+  constexpr int N3 = N * N * N;
+  __shared__ T t[SPB * TILE];
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int s0 = blk * SPB;
+  const int nsub = min(SPB, g.E - s0);
+  const int tid = threadIdx.x;
+  constexpr int NTH = Sh::NTH;
+
+  // gather R_s r for the SPB subdomains
+  for (int idx = tid; idx < nsub * VOL; idx += NTH) {
+    const int q = idx / VOL, rem = idx - q * VOL;
+    const int a = rem % MX, bc = rem / MX, b = bc % MY, c = bc / MY;
+    const int s = s0 + q;
+    const int ex = s % g.ne[0], rest = s / g.ne[0];
+    const int ey = rest % g.ne[1], ez = rest / g.ne[1];
+    const int gx = a - NOX, gy = b - NOY, gz = c - NOZ;
+    const int dx = gx < 0 ? -1 : (gx >= N ? 1 : 0);
+    const int dy = gy < 0 ? -1 : (gy >= N ? 1 : 0);
+    const int dz = gz < 0 ? -1 : (gz >= N ? 1 : 0);
+    const int e = elem_index(g, wrap(ex + dx, g.ne[0]), wrap(ey + dy, g.ne[1]), wrap(ez + dz, g.ne[2]));
+    t[q * TILE + bc * RX + a] = r[(size_t)e * N3 + ((gz - dz * N) * N + (gy - dy * N)) * N + (gx - dx * N)];
+  }
+  __syncthreads();
+  // x forward: lines (q, c, b)
+  for (int L = tid; L < nsub * Sh::L1; L += NTH) {
+    const int q = L / Sh::L1, cb = L - q * Sh::L1;
+    fwd_outer<T, MX>(t + q * TILE + cb * RX, 1, tb.S[0]);
+  }
+  __syncthreads();
+  // y forward: lines (q, c, a)
+  for (int L = tid; L < nsub * Sh::L2; L += NTH) {
+    const int q = L / Sh::L2, ca = L - q * Sh::L2;
+    const int c = ca / MX, a = ca - c * MX;
+    fwd_outer<T, MY>(t + q * TILE + c * MY * RX + a, RX, tb.S[1]);
+  }
+  __syncthreads();
+  // z forward, scaling, z backward: lines (q, b, a)
+  for (int L = tid; L < nsub * Sh::L3; L += NTH) {
+    const int q = L / Sh::L3, ba = L - q * Sh::L3;
+    const int b = ba / MX, a = ba - b * MX;
+    T *base = t + q * TILE + b * RX + a;
+    constexpr int st = MY * RX;
+    const T *__restrict__ Sz = tb.S[2];
+    const T *__restrict__ WSz = tb.WS[2];
+    T acc[MZ];
+#pragma unroll
+    for (int o = 0; o < MZ; ++o) acc[o] = 0;
+#pragma unroll
+    for (int c = 0; c < MZ; ++c) {
+      const T v = base[c * st];
+#pragma unroll
+      for (int o = 0; o < MZ; ++o) acc[o] += Sz[c * MZ + o] * v;
+    }
+#pragma unroll
+    for (int o = 0; o < MZ; ++o) acc[o] *= ilam[(o * MY + b) * MX + a];
+#pragma unroll
+    for (int c = 0; c < MZ; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int o = 0; o < MZ; ++o) s += WSz[c * MZ + o] * acc[o];
+      base[c * st] = s;
+    }
+  }
+  __syncthreads();
+  // y backward
+  for (int L = tid; L < nsub * Sh::L2; L += NTH) {
+    const int q = L / Sh::L2, ca = L - q * Sh::L2;
+    const int c = ca / MX, a = ca - c * MX;
+    bwd_inner<T, MY>(t + q * TILE + c * MY * RX + a, RX, tb.WS[1]);
+  }
+  __syncthreads();
+  // x backward
+  for (int L = tid; L < nsub * Sh::L1; L += NTH) {
+    const int q = L / Sh::L1, cb = L - q * Sh::L1;
+    bwd_inner<T, MX>(t + q * TILE + cb * RX, 1, tb.WS[0]);
+  }
+  __syncthreads();
+  T *Cs = C + (size_t)s0 * VOL;
+  for (int idx = tid; idx < nsub * VOL; idx += NTH) {
+    const int q = idx / VOL, rem = idx - q * VOL;
+    const int a = rem % MX, bc = rem / MX;
+    Cs[idx] = t[q * TILE + bc * RX + a];
+  }
+}
+
+// Assembly with compile-time sizes: one thread per node (consecutive threads
+// on consecutive nodes of an element), the (up to 27) contributing
+// subdomains visited in a fixed order.
+template <typename T, int N, int MX, int MY, int MZ>
+__global__ void __launch_bounds__(256)
+schwarz_assemble_fixed(Mesh g, const T *__restrict__ C, const T *u_in, T *u_out) {
+  constexpr int N3 = N * N * N, VOL = MX * MY * MZ;
+  constexpr int NOX = (MX - N) / 2, NOY = (MY - N) / 2, NOZ = (MZ - N) / 2;
+  const int64_t idx = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (idx >= (int64_t)g.E * N3) return;
+  const int e = (int)(idx / N3), loc = (int)(idx - (int64_t)e * N3);
+  const int i = loc % N, j = (loc / N) % N, k = loc / (N * N);
+  const int ex = e % g.ne[0], rest = e / g.ne[0];
+  const int ey = rest % g.ne[1], ez = rest / g.ne[1];
+  T sum = 0;
+#pragma unroll
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int c = k - dz * N + NOZ;
+    if (c < 0 || c >= MZ) continue;
+    const int sz = wrap(ez + dz, g.ne[2]);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int b = j - dy * N + NOY;
+      if (b < 0 || b >= MY) continue;
+      const int sy = wrap(ey + dy, g.ne[1]);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int a = i - dx * N + NOX;
+        if (a < 0 || a >= MX) continue;
+        const int s = elem_index(g, wrap(ex + dx, g.ne[0]), sy, sz);
+        sum += C[(size_t)s * VOL + (c * MY + b) * MX + a];
+      }
+    }
+  }
+  u_out[idx] = (u_in ? u_in[idx] : (T)0) + sum;
+}
+
+template <typename T, int N, int MX, int MY, int MZ>
+hipError_t launch_assemble_fixed(const SchwarzLaunch<T> &a, hipStream_t st) {
+  const int64_t tot = (int64_t)a.mesh.E * N * N * N;
+  schwarz_assemble_fixed<T, N, MX, MY, MZ><<<(int)((tot + 255) / 256), 256, 0, st>>>(a.mesh, a.C, a.u_in, a.u_out);
+  return hipGetLastError();
+}
+
+template <typename T, int N, int MX, int MY, int MZ>
+hipError_t launch_fixed(const SchwarzLaunch<T> &a, hipStream_t st) {
+  using Sh = FdmShape<MX, MY, MZ>;
+  static_assert(Sh::SPB * Sh::TILE * sizeof(T) <= 160 * 1024, "subdomain tile exceeds LDS");
+  const int nblk = (a.mesh.E + Sh::SPB - 1) / Sh::SPB;
+  schwarz_fdm_fixed<T, N, MX, MY, MZ><<<nblk, Sh::NTH, 0, st>>>(a.mesh, a.tabs, a.ilam, a.r, a.C);
+  return hipGetLastError();
+}
+
+// (n, m_x, m_y, m_z) shapes with a compiled fast path: the isotropic
+// minimal and 8% overlaps of orders 2..16 and the levels of the 16:1:1
+// aspect-ratio mesh with the "max" overlap.
+#define SIPG_FDM_SHAPES(X)                                                              \
+  X(3, 5, 5, 5) X(5, 7, 7, 7) X(8, 10, 10, 10) X(8, 12, 12, 12) X(9, 11, 11, 11)        \
+  X(9, 13, 13, 13) X(17, 19, 19, 19) X(17, 23, 23, 23) X(3, 5, 9, 9) X(5, 7, 15, 15)     \
+  X(9, 13, 27, 27)
+
+template <typename T>
+hipError_t launch_fixed_if_any(const SchwarzLaunch<T> &a, hipStream_t st, bool &done) {
+  done = true;
+  const int *m = a.tabs.m;
+#define SIPG_TRY(NN, AX, AY, AZ) \
+  if (a.n == NN && m[0] == AX && m[1] == AY && m[2] == AZ) return launch_fixed<T, NN, AX, AY, AZ>(a, st);
+  SIPG_FDM_SHAPES(SIPG_TRY)
+#undef SIPG_TRY
+  done = false;
+  return hipSuccess;
+}
+
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 size_t lds_bytes(const int m[3], size_t eb) { return (size_t)m[2] * m[1] * (m[0] | 1) * eb; }
@@ -262,6 +476,11 @@ bool schwarz_fits_lds(const int m[3], size_t eb) {
 
 template <typename T>
 hipError_t launch_schwarz_local(const SchwarzLaunch<T> &a, hipStream_t st) {
+  if (a.ilam) {
+    bool done = false;
+    hipError_t e = launch_fixed_if_any<T>(a, st, done);
+    if (done) return e;
+  }
   const int *m = a.tabs.m;
   const int mmax = std::max(m[0], std::max(m[1], m[2]));
   if (schwarz_fits_lds(m, sizeof(T))) {
@@ -277,6 +496,13 @@ hipError_t launch_schwarz_local(const SchwarzLaunch<T> &a, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_schwarz_assemble(const SchwarzLaunch<T> &a, hipStream_t st) {
+  {
+    const int *m = a.tabs.m;
+#define SIPG_TRY(NN, AX, AY, AZ) \
+  if (a.n == NN && m[0] == AX && m[1] == AY && m[2] == AZ) return launch_assemble_fixed<T, NN, AX, AY, AZ>(a, st);
+    SIPG_FDM_SHAPES(SIPG_TRY)
+#undef SIPG_TRY
+  }
   const int64_t tot = (int64_t)a.mesh.E * a.n * a.n * a.n;
   schwarz_assemble<T><<<(int)((tot + 255) / 256), 256, 0, st>>>(a.mesh, a.n, a.tabs, a.C, a.u_in, a.u_out);
   return hipGetLastError();

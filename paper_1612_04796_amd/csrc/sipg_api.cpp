@@ -41,6 +41,7 @@ struct LevelTabs {
   sipg::ApplyTabs<T> apply;
   sipg::SchwarzTabs<T> schwarz;
   const T *J = nullptr;  // n x n_prev (levels >= 1)
+  const T *ilam = nullptr;  // 1 / (lam_x + lam_y + lam_z) per subdomain entry (levels >= 1)
   int n = 0, nc = 0;
   int64_t ndof = 0;
 };
@@ -171,7 +172,7 @@ void upload_tables(sipg_ctx *c) {
   const sipg::HierarchyHost &H = c->H;
   Arena A;
   struct Off {
-    size_t Ld[3], M[3], DL[3], DR[3], S[3], WS[3], lam[3], J;
+    size_t Ld[3], M[3], DL[3], DR[3], S[3], WS[3], lam[3], J, ilam;
   };
   std::vector<Off> o64(c->L + 1), o32(c->L + 1);
   auto put_level = [&](auto tag, std::vector<Off> &off) {
@@ -193,7 +194,16 @@ void upload_tables(sipg_ctx *c) {
           off[l].lam[d] = A.put<T>(D.lam);
         }
       }
-      if (l > 0) off[l].J = A.put<T>(lv.J);
+      if (l > 0) {
+        off[l].J = A.put<T>(lv.J);
+        const sipg::Dir1D &X = lv.dir[0], &Y = lv.dir[1], &Z = lv.dir[2];
+        std::vector<double> il((size_t)X.m * Y.m * Z.m);
+        for (int cz = 0; cz < Z.m; ++cz)
+          for (int by = 0; by < Y.m; ++by)
+            for (int ax = 0; ax < X.m; ++ax)
+              il[((size_t)cz * Y.m + by) * X.m + ax] = 1.0 / (X.lam[ax] + Y.lam[by] + Z.lam[cz]);
+        off[l].ilam = A.put<T>(il);
+      }
     }
   };
   put_level(double(), o64);
@@ -240,7 +250,10 @@ void upload_tables(sipg_ctx *c) {
           t.schwarz.no[d] = lv.dir[d].no;
         }
       }
-      if (l > 0) t.J = reinterpret_cast<const T *>(c->tab_dev + off[l].J);
+      if (l > 0) {
+        t.J = reinterpret_cast<const T *>(c->tab_dev + off[l].J);
+        t.ilam = reinterpret_cast<const T *>(c->tab_dev + off[l].ilam);
+      }
     }
   };
   fill(double(), o64, c->t64);
@@ -265,11 +278,20 @@ void op_apply(sipg_ctx *c, int l, const T *u, T *y, T *partial) {
   check(sipg::launch_apply<T>(a, c->stream), "apply_A");
 }
 
+// r = f - A u; with `partial`, also one partial sum of r.r per workgroup
 template <typename T>
-void op_residual(sipg_ctx *c, int l, const T *u, const T *f, T *r) {
+void op_residual(sipg_ctx *c, int l, const T *u, const T *f, T *r, T *partial = nullptr) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
-  sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, f, r, sipg::APPLY_RESID, nullptr, nullptr, 0};
+  sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, f, r, sipg::APPLY_RESID, partial, nullptr, 0};
   check(sipg::launch_apply<T>(a, c->stream), "residual");
+}
+
+// ||f - A u||^2 into scal[slot], r = f - A u (FP64, top level)
+void residual_norm2(sipg_ctx *c, const double *u, const double *f, double *r, int slot) {
+  op_residual<double>(c, c->L, u, f, r, c->partial);
+  check(sipg::launch_finalize(c->partial, sipg::apply_num_blocks(c->mesh.E, c->H.lev[c->L].n), 1.0,
+                              c->scal + slot, c->stream),
+        "residual norm");
 }
 
 template <typename T>
@@ -282,7 +304,7 @@ void op_residual_restrict(sipg_ctx *c, int l, const T *u, const T *f, T *fc) {
 template <typename T>
 void op_schwarz(sipg_ctx *c, int l, const T *r, const T *u_in, T *u_out) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
-  sipg::SchwarzLaunch<T> a{c->mesh, t.n, t.schwarz, r, work_of<T>(c).C, u_in, u_out};
+  sipg::SchwarzLaunch<T> a{c->mesh, t.n, t.schwarz, r, work_of<T>(c).C, t.ilam, u_in, u_out};
   check(sipg::launch_schwarz<T>(a, c->stream), "schwarz");
 }
 
@@ -395,8 +417,7 @@ int mg_solve_impl(sipg_ctx *c, double *u, const double *f, double rtol, int maxc
   c->hist.clear();
   double r0 = -1.0;
   for (int cyc = 0;; ++cyc) {
-    op_residual<double>(c, c->L, u, f, c->cg_r);
-    norm2(c, c->cg_r, N, sipg::FS_RR);
+    residual_norm2(c, u, f, c->cg_r, sipg::FS_RR);
     read_scalars(c);
     const double rn = std::sqrt(c->host_scal[sipg::FS_RR]);
     c->hist.push_back(rn);
@@ -417,8 +438,7 @@ int pcg_solve_impl(sipg_ctx *c, double *x, const double *b, double rtol, int max
   double *r = c->cg_r, *p = c->cg_p, *q = c->cg_q, *z = c->cg_z;
   c->hist.clear();
   if (iters) *iters = 0;
-  op_residual<double>(c, c->L, x, b, r);
-  norm2(c, r, N, sipg::FS_RR);
+  residual_norm2(c, x, b, r, sipg::FS_RR);
   read_scalars(c);
   const double r0 = std::sqrt(c->host_scal[sipg::FS_RR]);
   c->hist.push_back(r0);
@@ -446,8 +466,7 @@ int pcg_solve_impl(sipg_ctx *c, double *x, const double *b, double rtol, int max
     if (!std::isfinite(rn)) return fail(SIPG_ENOTFINITE, "residual norm is not finite");
     if (rn <= rtol * r0) {
       // confirm with the recomputed residual b - A x
-      op_residual<double>(c, c->L, x, b, q);
-      norm2(c, q, N, sipg::FS_RR);
+      residual_norm2(c, x, b, q, sipg::FS_RR);
       read_scalars(c);
       const double rt = std::sqrt(c->host_scal[sipg::FS_RR]);
       if (rt <= rtol * r0) {
@@ -771,7 +790,7 @@ int sipg_time_kernel(sipg_ctx *c, int kernel, int level, int bits, int reps, dou
       check(sipg::launch_fill<T>(f, N, (T)0.5, c->stream), "fill");
       check(sipg::launch_fill<T>(r, N, (T)0.75, c->stream), "fill");
       const LevelTabs<T> &t = tabs_of<T>(c, l);
-      sipg::SchwarzLaunch<T> sa{c->mesh, t.n, t.schwarz, r, w.C, u, u};
+      sipg::SchwarzLaunch<T> sa{c->mesh, t.n, t.schwarz, r, w.C, t.ilam, u, u};
       check(sipg::launch_schwarz_local<T>(sa, c->stream), "schwarz");  // valid corrections in C
       hipEvent_t e0, e1;
       check(hipEventCreate(&e0), "event");
