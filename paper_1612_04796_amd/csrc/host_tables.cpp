@@ -319,7 +319,10 @@ std::string validate(const sipg_params &p) {
       os << "len[" << d << "] must be positive and finite"; return os.str();
     }
   }
-  if (p.P < 1 || p.P > kMaxOrder) { os << "order P = " << p.P << " outside 1.." << kMaxOrder; return os.str(); }
+  if (p.P < 1 || (p.P > 16 && p.P != kMaxOrder)) {
+    os << "order P = " << p.P << " not supported (1..16 or 32)";
+    return os.str();
+  }
   if (!(p.penalty > 0.5) || !std::isfinite(p.penalty)) {
     os << "penalty factor must exceed 1/2 (stability threshold)"; return os.str();
   }

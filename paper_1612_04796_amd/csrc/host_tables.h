@@ -11,7 +11,7 @@
 
 namespace sipg {
 
-constexpr int kMaxOrder = 16;
+constexpr int kMaxOrder = 32;  // orders 1..16 and 32
 
 struct Dir1D {
   // one direction of one level

@@ -29,8 +29,16 @@ struct ApplyLaunch {
 template <typename T>
 hipError_t launch_apply(const ApplyLaunch<T> &a, hipStream_t st);
 
-// Number of partial sums launch_apply writes for a PLAIN launch with partials.
+// Number of partial sums launch_apply / launch_apply_large write with partials.
 int apply_num_blocks(int E, int n);
+
+// Orders whose elements do not fit in LDS (n = 33): axis-by-axis operator
+// passes from global memory.  tmp holds E*(n^3 + n^2*nc) values (restriction
+// and prolongation scratch).
+bool apply_is_large(int n);
+int apply_large_num_blocks(int E, int n);
+template <typename T>
+hipError_t launch_apply_large(const ApplyLaunch<T> &a, T *tmp, hipStream_t st);
 
 // u_f += (J x J x J)(u_c - *mean) per element (mean may be null).
 template <typename T, typename TC>
@@ -44,6 +52,8 @@ struct ProlongLaunch {
 };
 template <typename T, typename TC>
 hipError_t launch_prolong(const ProlongLaunch<T, TC> &a, hipStream_t st);
+template <typename T, typename TC>
+hipError_t launch_prolong_large(const ProlongLaunch<T, TC> &a, T *tmp, hipStream_t st);
 
 // One weighted additive Schwarz correction: C[s] = W_s A_ss^{-1} R_s r for
 // every subdomain s (m_x*m_y*m_z values per subdomain, layout [s][c][b][a]),
@@ -69,6 +79,10 @@ template <typename T>
 hipError_t launch_schwarz_assemble(const SchwarzLaunch<T> &a, hipStream_t st);
 // true if the subdomain tensor of this size is solved in LDS in one kernel
 bool schwarz_fits_lds(const int m[3], size_t elem_bytes);
+// subdomains wider than 64 nodes: plane-by-plane kernels
+bool schwarz_is_wide(const int m[3]);
+template <typename T>
+hipError_t launch_schwarz_wide(const SchwarzLaunch<T> &a, hipStream_t st);
 
 // Level-0 pseudo-inverse by global fast diagonalization; see kernels_coarse.hip.
 struct CoarseLaunch {

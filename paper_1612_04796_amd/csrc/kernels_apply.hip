@@ -338,6 +338,7 @@ hipError_t launch_prolong_n(const ProlongLaunch<T, TC> &a, hipStream_t st) {
 }  // namespace
 
 int apply_num_blocks(int E, int n) {
+  if (apply_is_large(n)) return apply_large_num_blocks(E, n);
   int epb = 256 / (n * n);
   if (epb < 1) epb = 1;
   return (E + epb - 1) / epb;

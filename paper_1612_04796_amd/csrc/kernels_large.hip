@@ -1,0 +1,329 @@
+// Kernels for elements too large to stage in LDS (order P = 32, n = 33:
+// one FP64 element is 287 KB) and for Schwarz subdomains wider than 64 nodes.
+//
+// Operator: three passes over the level, one per direction, each with one
+// thread per 1D line.  The line and the two face-neighbour lines are read from
+// global memory; the x pass writes the partial result, the y pass adds to it,
+// the z pass completes it (plain apply, residual with optional r.r partials).
+//
+// Transfers: element-local contraction along one axis of an element tensor of
+// shape (s_z, s_y, s_x), one thread per output entry; three calls give
+// (J x J x J) or its transpose.
+//
+// Schwarz for wide subdomains: the same three phases as the slab path, but on
+// 2D planes held in LDS and with one thread per output entry, processed in
+// batches of rows or columns so that every update is in place without a second
+// buffer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace sipg {
+
+namespace {
+
+template <typename T, int N, int DIR, int MODE, bool DOT>
+__global__ void __launch_bounds__(256)
+apply_axis(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restrict__ f, T *out, T *partial) {
+  constexpr int N2 = N * N, N3 = N2 * N;
+  __shared__ T red[16];
+  const int64_t gid = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  const bool active = gid < (int64_t)g.E * N2;
+  T dot = 0;
+  if (active) {
+    const int e = (int)(gid / N2), pq = (int)(gid - (int64_t)e * N2);
+    const int p = pq / N, q = pq - p * N;
+    const int ex = e % g.ne[0], rest = e / g.ne[0];
+    const int ey = rest % g.ne[1], ez = rest / g.ne[1];
+    // line base offset and stride inside an element, neighbour elements
+    int base, st, eR, eL;
+    if (DIR == 0) {
+      base = pq * N; st = 1;
+      eR = elem_index(g, wrap(ex + 1, g.ne[0]), ey, ez);
+      eL = elem_index(g, wrap(ex - 1, g.ne[0]), ey, ez);
+    } else if (DIR == 1) {
+      base = p * N2 + q; st = N;
+      eR = elem_index(g, ex, wrap(ey + 1, g.ne[1]), ez);
+      eL = elem_index(g, ex, wrap(ey - 1, g.ne[1]), ez);
+    } else {
+      base = pq; st = N2;
+      eR = elem_index(g, ex, ey, wrap(ez + 1, g.ne[2]));
+      eL = elem_index(g, ex, ey, wrap(ez - 1, g.ne[2]));
+    }
+    const T *__restrict__ Ld = tb.Ld[DIR];
+    const T *__restrict__ DL = tb.DL[DIR];
+    const T *__restrict__ DR = tb.DR[DIR];
+    const T mu = tb.mu[DIR];
+    const T *lr = u + (size_t)eR * N3 + base;
+    const T *ll = u + (size_t)eL * N3 + base;
+    const T *lv = u + (size_t)e * N3 + base;
+    T v[N];
+    T gR = 0, gL = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      v[i] = lv[i * st];
+      gR += DL[i] * lr[i * st];
+      gL += DR[i] * ll[i * st];
+    }
+    const T vR = lr[0], vL = ll[(N - 1) * st];
+    // mass factors of the two other directions
+    T sc;
+    if (DIR == 0) sc = tb.M[2][p] * tb.M[1][q];
+    else if (DIR == 1) sc = tb.M[2][p] * tb.M[0][q];
+    else sc = tb.M[1][p] * tb.M[0][q];
+    T *o = out + (size_t)e * N3 + base;
+    const T *fl = f ? f + (size_t)e * N3 + base : nullptr;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T acc = DR[i] * vR - DL[i] * vL;
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc += Ld[i * N + k] * v[k];
+      if (i == N - 1) acc -= gR + mu * vR;
+      if (i == 0) acc += gL - mu * vL;
+      acc *= sc;
+      if (DIR == 0) {
+        o[i * st] = acc;
+      } else if (DIR == 1) {
+        o[i * st] += acc;
+      } else {
+        const T y = o[i * st] + acc;
+        if (MODE == 0) {
+          o[i * st] = y;
+          if (DOT) dot += v[i] * y;
+        } else {
+          const T r = fl[i * st] - y;
+          o[i * st] = r;
+          if (DOT) dot += r * r;
+        }
+      }
+    }
+  }
+  if (DOT) {
+    const T s = block_reduce_sum(dot, red);
+    if (threadIdx.x == 0) partial[xcd_block(blockIdx.x, gridDim.x)] = s;
+  }
+}
+
+// out = contraction of each element tensor along `axis`:
+//   TRANS = false: out[..o..] = sum_i A[o * nin + i] in[..i..]      (A is nout x nin)
+//   TRANS = true : out[..o..] = sum_i A[i * nout + o] in[..i..]     (A is nin x nout)
+// in has per-element shape (sz, sy, sx) with the contracted extent nin;
+// ADD accumulates into out.
+template <typename T, typename TI, bool TRANS, bool ADD>
+__global__ void __launch_bounds__(256)
+elem_axis(int E, int sx, int sy, int sz, int axis, int nout, const T *__restrict__ A, const TI *__restrict__ in,
+          T *out) {
+  const int nin = axis == 0 ? sx : (axis == 1 ? sy : sz);
+  const int ox = axis == 0 ? nout : sx, oy = axis == 1 ? nout : sy, oz = axis == 2 ? nout : sz;
+  const int64_t ovol = (int64_t)ox * oy * oz, ivol = (int64_t)sx * sy * sz;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)E * ovol) return;
+  const int e = (int)(gid / ovol);
+  const int r = (int)(gid - (int64_t)e * ovol);
+  const int x = r % ox, y = (r / ox) % oy, z = r / (ox * oy);
+  const int o = axis == 0 ? x : (axis == 1 ? y : z);
+  const int istride = axis == 0 ? 1 : (axis == 1 ? sx : sx * sy);
+  const int ibase = axis == 0 ? (z * sy + y) * sx : (axis == 1 ? z * sy * sx + x : y * sx + x);
+  const TI *src = in + (size_t)e * ivol + ibase;
+  T acc = 0;
+  for (int i = 0; i < nin; ++i) acc += (TRANS ? A[i * nout + o] : A[o * nin + i]) * (T)src[i * istride];
+  if (ADD) out[gid] += acc;
+  else out[gid] = acc;
+}
+
+// ---- Schwarz on wide subdomains: planes in LDS, one thread per output ----
+// In-place contraction of the rows (ROWS = true: rows are contiguous runs of
+// length m, `count` of them with pitch `pitch`) or the columns (ROWS = false:
+// column j has entries P[k * pitch + j], k < m) of a plane in LDS, processed
+// in batches so that every output of a batch is computed before the batch is
+// written back.  FWD: out[o] = sum_a A[a*m + o] in[a]; else out[a] = sum_o
+// A[a*m + o] in[o].
+template <typename T, bool ROWS, bool FWD>
+__device__ void plane_contract(T *P, int pitch, int count, int m, const T *__restrict__ A) {
+  const int nth = blockDim.x, tid = threadIdx.x;
+  const int per_batch = max(1, nth / m);  // lines per batch
+  for (int l0 = 0; l0 < count; l0 += per_batch) {
+    const int nl = min(per_batch, count - l0);
+    T acc = 0;
+    const bool act = tid < nl * m;
+    const int line = l0 + tid / m, o = tid % m;
+    if (act) {
+      for (int a = 0; a < m; ++a) {
+        const T x = ROWS ? P[line * pitch + a] : P[a * pitch + line];
+        acc += (FWD ? A[a * m + o] : A[o * m + a]) * x;
+      }
+    }
+    __syncthreads();
+    if (act) {
+      if (ROWS) P[line * pitch + o] = acc;
+      else P[o * pitch + line] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T gather_node(const Mesh &g, int n, const T *__restrict__ r, int ex, int ey, int ez,
+                                         int gx, int gy, int gz) {
+  const int dx = gx < 0 ? -1 : (gx >= n ? 1 : 0);
+  const int dy = gy < 0 ? -1 : (gy >= n ? 1 : 0);
+  const int dz = gz < 0 ? -1 : (gz >= n ? 1 : 0);
+  const int e = elem_index(g, wrap(ex + dx, g.ne[0]), wrap(ey + dy, g.ne[1]), wrap(ez + dz, g.ne[2]));
+  return r[(size_t)e * n * n * n + ((gz - dz * n) * n + (gy - dy * n)) * n + (gx - dx * n)];
+}
+
+// phase 1: block (s, c): gather the z-slab, x and y forward
+template <typename T>
+__global__ void __launch_bounds__(256)
+wide_slab1(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restrict__ W) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *P = reinterpret_cast<T *>(smem_raw);
+  const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
+  const int blk = blockIdx.x;
+  const int s = blk / mz, c = blk - s * mz;
+  const int ex = s % g.ne[0], rest = s / g.ne[0];
+  const int ey = rest % g.ne[1], ez = rest / g.ne[1];
+  for (int idx = threadIdx.x; idx < mx * my; idx += blockDim.x) {
+    const int a = idx % mx, b = idx / mx;
+    P[idx] = gather_node(g, n, r, ex, ey, ez, a - tb.no[0], b - tb.no[1], c - tb.no[2]);
+  }
+  __syncthreads();
+  plane_contract<T, true, true>(P, mx, my, mx, tb.S[0]);
+  plane_contract<T, false, true>(P, mx, mx, my, tb.S[1]);
+  T *Ws = W + ((size_t)s * mz + c) * mx * my;
+  for (int idx = threadIdx.x; idx < mx * my; idx += blockDim.x) Ws[idx] = P[idx];
+}
+
+// phase 2: block (s, b): the xz plane, z forward, scaling, z backward
+template <typename T>
+__global__ void __launch_bounds__(256)
+wide_slab2(int E, SchwarzTabs<T> tb, const T *__restrict__ ilam, T *__restrict__ W) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *P = reinterpret_cast<T *>(smem_raw);
+  const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
+  const int blk = blockIdx.x;
+  const int s = blk / my, b = blk - s * my;
+  T *Ws = W + (size_t)s * mx * my * mz;
+  for (int idx = threadIdx.x; idx < mx * mz; idx += blockDim.x) {
+    const int a = idx % mx, c = idx / mx;
+    P[idx] = Ws[((size_t)c * my + b) * mx + a];
+  }
+  __syncthreads();
+  plane_contract<T, false, true>(P, mx, mx, mz, tb.S[2]);
+  for (int idx = threadIdx.x; idx < mx * mz; idx += blockDim.x) {
+    const int a = idx % mx, c = idx / mx;
+    P[idx] *= ilam[((size_t)c * my + b) * mx + a];
+  }
+  __syncthreads();
+  plane_contract<T, false, false>(P, mx, mx, mz, tb.WS[2]);
+  for (int idx = threadIdx.x; idx < mx * mz; idx += blockDim.x) {
+    const int a = idx % mx, c = idx / mx;
+    Ws[((size_t)c * my + b) * mx + a] = P[idx];
+  }
+}
+
+// phase 3: block (s, c): y and x backward
+template <typename T>
+__global__ void __launch_bounds__(256) wide_slab3(int E, SchwarzTabs<T> tb, T *__restrict__ W) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *P = reinterpret_cast<T *>(smem_raw);
+  const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
+  const int blk = blockIdx.x;
+  const int s = blk / mz, c = blk - s * mz;
+  T *Ws = W + ((size_t)s * mz + c) * mx * my;
+  for (int idx = threadIdx.x; idx < mx * my; idx += blockDim.x) P[idx] = Ws[idx];
+  __syncthreads();
+  plane_contract<T, false, false>(P, mx, mx, my, tb.WS[1]);
+  plane_contract<T, true, false>(P, mx, my, mx, tb.WS[0]);
+  for (int idx = threadIdx.x; idx < mx * my; idx += blockDim.x) Ws[idx] = P[idx];
+}
+
+inline int nblk(int64_t n) { return (int)((n + 255) / 256); }
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t shm) {
+  if (shm <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+}
+
+template <typename T, int N>
+hipError_t apply_large_n(const ApplyLaunch<T> &a, T *tmp, hipStream_t st) {
+  const int64_t lines = (int64_t)a.mesh.E * N * N;
+  const int nb = nblk(lines);
+  T *y = (a.mode == APPLY_RESTRICT) ? tmp : a.out;
+  apply_axis<T, N, 0, 0, false><<<nb, 256, 0, st>>>(a.mesh, a.tabs, a.u, nullptr, y, nullptr);
+  apply_axis<T, N, 1, 0, false><<<nb, 256, 0, st>>>(a.mesh, a.tabs, a.u, nullptr, y, nullptr);
+  if (a.mode == APPLY_PLAIN) {
+    if (a.partial) apply_axis<T, N, 2, 0, true><<<nb, 256, 0, st>>>(a.mesh, a.tabs, a.u, nullptr, y, a.partial);
+    else apply_axis<T, N, 2, 0, false><<<nb, 256, 0, st>>>(a.mesh, a.tabs, a.u, nullptr, y, nullptr);
+    return hipGetLastError();
+  }
+  if (a.partial && a.mode == APPLY_RESID)
+    apply_axis<T, N, 2, 1, true><<<nb, 256, 0, st>>>(a.mesh, a.tabs, a.u, a.f, y, a.partial);
+  else
+    apply_axis<T, N, 2, 1, false><<<nb, 256, 0, st>>>(a.mesh, a.tabs, a.u, a.f, y, nullptr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.mode == APPLY_RESID) return e;
+  // restriction of the residual in tmp: J^T along x, y, z (J is N x nc)
+  const int nc = a.nc, E = a.mesh.E;
+  T *t1 = tmp + (size_t)E * N * N * N;  // second half of the scratch
+  elem_axis<T, T, true, false><<<nblk((int64_t)E * N * N * nc), 256, 0, st>>>(E, N, N, N, 0, nc, a.J, tmp, t1);
+  elem_axis<T, T, true, false><<<nblk((int64_t)E * N * nc * nc), 256, 0, st>>>(E, nc, N, N, 1, nc, a.J, t1, tmp);
+  elem_axis<T, T, true, false><<<nblk((int64_t)E * nc * nc * nc), 256, 0, st>>>(E, nc, nc, N, 2, nc, a.J, tmp, a.out);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool apply_is_large(int n) { return n > 17; }
+
+template <typename T>
+hipError_t launch_apply_large(const ApplyLaunch<T> &a, T *tmp, hipStream_t st) {
+  if (a.n == 33) return apply_large_n<T, 33>(a, tmp, st);
+  return hipErrorInvalidValue;
+}
+
+int apply_large_num_blocks(int E, int n) { return (int)(((int64_t)E * n * n + 255) / 256); }
+
+template <typename T, typename TC>
+hipError_t launch_prolong_large(const ProlongLaunch<T, TC> &a, T *tmp, hipStream_t st) {
+  // u_f += (J x J x J) u_c with J nf x nc, through two scratch tensors
+  const int E = a.E, nf = a.nf, nc = a.nc;
+  T *t1 = tmp, *t2 = tmp + (size_t)E * nc * nc * nf;
+  elem_axis<T, TC, false, false><<<nblk((int64_t)E * nc * nc * nf), 256, 0, st>>>(E, nc, nc, nc, 0, nf, a.J, a.uc, t1);
+  elem_axis<T, T, false, false><<<nblk((int64_t)E * nc * nf * nf), 256, 0, st>>>(E, nf, nc, nc, 1, nf, a.J, t1, t2);
+  elem_axis<T, T, false, true><<<nblk((int64_t)E * nf * nf * nf), 256, 0, st>>>(E, nf, nf, nc, 2, nf, a.J, t2, a.uf);
+  return hipGetLastError();
+}
+
+bool schwarz_is_wide(const int m[3]) { return std::max(m[0], std::max(m[1], m[2])) > 64; }
+
+template <typename T>
+hipError_t launch_schwarz_wide(const SchwarzLaunch<T> &a, hipStream_t st) {
+  const int *m = a.tabs.m;
+  const size_t s13 = (size_t)m[0] * m[1] * sizeof(T), s2 = (size_t)m[0] * m[2] * sizeof(T);
+  if (std::max(s13, s2) > 150 * 1024) return hipErrorInvalidValue;
+  hipError_t e;
+  if ((e = allow_lds(wide_slab1<T>, s13)) != hipSuccess) return e;
+  if ((e = allow_lds(wide_slab2<T>, s2)) != hipSuccess) return e;
+  if ((e = allow_lds(wide_slab3<T>, s13)) != hipSuccess) return e;
+  wide_slab1<T><<<a.mesh.E * m[2], 256, s13, st>>>(a.mesh, a.n, a.tabs, a.r, a.C);
+  wide_slab2<T><<<a.mesh.E * m[1], 256, s2, st>>>(a.mesh.E, a.tabs, a.ilam, a.C);
+  wide_slab3<T><<<a.mesh.E * m[2], 256, s13, st>>>(a.mesh.E, a.tabs, a.C);
+  return hipGetLastError();
+}
+
+template hipError_t launch_apply_large<double>(const ApplyLaunch<double> &, double *, hipStream_t);
+template hipError_t launch_apply_large<float>(const ApplyLaunch<float> &, float *, hipStream_t);
+template hipError_t launch_prolong_large<double, double>(const ProlongLaunch<double, double> &, double *,
+                                                         hipStream_t);
+template hipError_t launch_prolong_large<float, float>(const ProlongLaunch<float, float> &, float *, hipStream_t);
+template hipError_t launch_prolong_large<float, double>(const ProlongLaunch<float, double> &, float *,
+                                                        hipStream_t);
+template hipError_t launch_schwarz_wide<double>(const SchwarzLaunch<double> &, hipStream_t);
+template hipError_t launch_schwarz_wide<float>(const SchwarzLaunch<float> &, hipStream_t);
+
+}  // namespace sipg

@@ -483,6 +483,7 @@ hipError_t launch_schwarz_local(const SchwarzLaunch<T> &a, hipStream_t st) {
   }
   const int *m = a.tabs.m;
   const int mmax = std::max(m[0], std::max(m[1], m[2]));
+  if (schwarz_is_wide(m)) return launch_schwarz_wide<T>(a, st);
   if (schwarz_fits_lds(m, sizeof(T))) {
     if (mmax <= 8) return launch_lds<T, 8>(a, st);
     if (mmax <= 16) return launch_lds<T, 16>(a, st);

@@ -53,6 +53,7 @@ struct Work {
   T *uL = nullptr, *fL = nullptr;
   T *r = nullptr;         // residual scratch, top-level size
   T *C = nullptr;         // Schwarz correction scratch
+  T *big = nullptr;       // scratch of the large-element (n = 33) operator and transfers
   bool ready = false;
 };
 
@@ -147,6 +148,8 @@ size_t work_bytes(const sipg::HierarchyHost &H, size_t eb) {
   for (int l = 0; l < L; ++l) b += 2 * (size_t)level_ndof(H, l) * eb;
   b += 3 * (size_t)level_ndof(H, L) * eb;  // r plus an internal top-level u, f pair
   b += (size_t)E * max_sub(H) * eb;
+  const int nt = H.lev[L].n;
+  if (sipg::apply_is_large(nt)) b += (size_t)E * ((size_t)nt * nt * nt + (size_t)nt * nt * H.lev[L - 1].n) * eb;
   return b;
 }
 
@@ -165,6 +168,11 @@ void ensure_work(sipg_ctx *c) {
   w.fL = c->alloc<T>(level_ndof(H, c->L));
   w.r = c->alloc<T>(level_ndof(H, c->L));
   w.C = c->alloc<T>((size_t)c->mesh.E * max_sub(H));
+  const int nt = H.lev[c->L].n;
+  if (sipg::apply_is_large(nt)) {
+    const int nc = H.lev[c->L - 1].n;
+    w.big = c->alloc<T>((size_t)c->mesh.E * ((size_t)nt * nt * nt + (size_t)nt * nt * nc));
+  }
   w.ready = true;
 }
 
@@ -272,10 +280,20 @@ void upload_tables(sipg_ctx *c) {
 
 // ---- level operations -----------------------------------------------------
 template <typename T>
+void run_apply(sipg_ctx *c, const sipg::ApplyLaunch<T> &a, const char *what) {
+  if (sipg::apply_is_large(a.n)) {
+    ensure_work<T>(c);
+    check(sipg::launch_apply_large<T>(a, work_of<T>(c).big, c->stream), what);
+  } else {
+    check(sipg::launch_apply<T>(a, c->stream), what);
+  }
+}
+
+template <typename T>
 void op_apply(sipg_ctx *c, int l, const T *u, T *y, T *partial) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
   sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, nullptr, y, sipg::APPLY_PLAIN, partial, nullptr, 0};
-  check(sipg::launch_apply<T>(a, c->stream), "apply_A");
+  run_apply<T>(c, a, "apply_A");
 }
 
 // r = f - A u; with `partial`, also one partial sum of r.r per workgroup
@@ -283,7 +301,7 @@ template <typename T>
 void op_residual(sipg_ctx *c, int l, const T *u, const T *f, T *r, T *partial = nullptr) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
   sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, f, r, sipg::APPLY_RESID, partial, nullptr, 0};
-  check(sipg::launch_apply<T>(a, c->stream), "residual");
+  run_apply<T>(c, a, "residual");
 }
 
 // ||f - A u||^2 into scal[slot], r = f - A u (FP64, top level)
@@ -298,7 +316,7 @@ template <typename T>
 void op_residual_restrict(sipg_ctx *c, int l, const T *u, const T *f, T *fc) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
   sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, f, fc, sipg::APPLY_RESTRICT, nullptr, t.J, t.nc};
-  check(sipg::launch_apply<T>(a, c->stream), "residual_restrict");
+  run_apply<T>(c, a, "residual_restrict");
 }
 
 template <typename T>
@@ -312,7 +330,12 @@ template <typename T, typename TC>
 void op_prolong(sipg_ctx *c, int l, const TC *uc, const double *mean, T *uf) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
   sipg::ProlongLaunch<T, TC> a{c->mesh.E, t.n, t.nc, t.J, uc, mean, uf};
-  check(sipg::launch_prolong<T, TC>(a, c->stream), "prolong");
+  if (sipg::apply_is_large(t.n)) {
+    ensure_work<T>(c);
+    check(sipg::launch_prolong_large<T, TC>(a, work_of<T>(c).big, c->stream), "prolong");
+  } else {
+    check(sipg::launch_prolong<T, TC>(a, c->stream), "prolong");
+  }
 }
 
 template <typename T>

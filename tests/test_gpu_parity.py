@@ -223,3 +223,51 @@ def test_fp32_preconditioner(ne, length, P, overlap):
     xs = oracle.exact_solution(b, h)
     assert rel(x - x.mean(), xs) <= 1e-8
     s.close()
+
+
+# ---- order 32: elements of 33^3 nodes (global-memory operator passes) and
+# subdomains up to 99 nodes wide (plane-by-plane Schwarz) -------------------
+@pytest.mark.parametrize("ne,length,overlap", [((3, 3, 4), (1.0, 1.0, 1.0), "rel"),
+                                               ((3, 4, 4), (16.0, 1.0, 1.0), "max")])
+def test_order32_operator_schwarz_transfers(ne, length, overlap):
+    announce("order32", ne, length, overlap)
+    h, s = pair(ne, length, 32, overlap=overlap)
+    L = h.L
+    n = h.ndof(L)
+    u = uniform_vector(101, n)
+    f = uniform_vector(102, n)
+    y = zeros(n)
+    s.apply_A(dev(u), y)
+    ref = oracle.apply_level(u, h, L)
+    assert rel(host(y), ref) <= TOL_OP
+    r = zeros(n)
+    s.residual(dev(u), dev(f), r)
+    assert rel(host(r), f - ref) <= TOL_OP
+    ud = dev(u)
+    s.schwarz(dev(f), ud, level=L)
+    assert rel(host(ud), u + oracle.schwarz_step_correction(f, h, L)) <= TOL_FDM
+    fc = zeros(h.ndof(L - 1))
+    s.restrict(dev(f), fc, level=L)
+    assert rel(host(fc), oracle.restrict(f, h, L)) <= TOL_OP
+    uc = uniform_vector(103, h.ndof(L - 1))
+    ud = dev(u)
+    s.prolong_add(dev(uc), ud, level=L)
+    assert rel(host(ud), u + oracle.prolong(uc, h, L)) <= TOL_OP
+    s.close()
+
+
+def test_order32_vcycle_and_fcg():
+    announce("order32 vcycle")
+    ne, length = (3, 3, 3), (1.0, 1.0, 1.0)
+    h, s = pair(ne, length, 32, overlap="rel")
+    k, phi, amp = fourier_modes(4, 3)
+    b = oracle.fourier_rhs(k, phi, amp, h)
+    z = zeros(h.ndof())
+    s.precond(dev(b), z)
+    assert rel(host(z), oracle.vcycle(np.zeros_like(b), b, h)) <= TOL_FDM
+    x = zeros(h.ndof())
+    it, rr = s.pcg_solve(x, dev(b), rtol=1e-10, maxit=40)
+    assert rr <= 1e-10
+    xh = host(x)
+    assert rel(xh - xh.mean(), oracle.exact_solution(b, h)) <= 1e-8
+    s.close()
