@@ -89,6 +89,87 @@ def cpu_baseline(wl, cycles, k, phi, amp):
     }
 
 
+def serving_run(nreq, seed, log_every=4):
+    """Serving stream: heterogeneous requests (4^3..24^3 elements, P in
+    {2,4,8,16,32}, aspect ratio 1..8, "max" overlap, FP32-preconditioned
+    FP64 flexible CG to 1e-10) with Poisson arrivals at the rate that gives
+    about 70 % utilisation.  The mean service time is measured first by
+    serving the same requests one at a time; then the stream is replayed in
+    real time into a server with 8 slots.  Latency = finish - arrival."""
+    import numpy as np
+    import torch
+    from paper_1612_04796_amd import sipg
+    from paper_1612_04796_amd.workloads import fourier_modes, serving_stream
+
+    free, _total = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    reqs = serving_stream(seed, nreq, 1.0)
+    common = dict(overlap="max", omega=0.08, precond_bits=32)
+
+    def submit(srv, r):
+        k, phi, amp = fourier_modes(r["rhs_seed"], 3)
+        return srv.submit(k, phi, amp, rtol=1e-10, maxit=200, ne=r["ne"], length=r["length"], P=r["P"], **common)
+
+    # calibration: one request at a time
+    service = []
+    with sipg.Server(budget, max_active=1) as srv:
+        ids = [submit(srv, r) for r in reqs]
+        while True:
+            a, q, _ = srv.progress(wait_ms=100)
+            if a == 0 and q == 0:
+                break
+        for rid in ids:
+            st = srv.status(rid)
+            if st["state"] != sipg.REQ_DONE:
+                raise RuntimeError(f"request failed: {st}")
+            service.append(st["t_done"] - st["t_admit"])
+    mean_s = float(np.mean(service))
+    qps = 0.7 / mean_s
+    # arrival times: the stream's exponential gaps rescaled to this rate
+    arrivals = [r["t_arrival"] / qps for r in reqs]
+    log(f"serving: {nreq} requests, mean service {1e3 * mean_s:.2f} ms alone, replay at {qps:.1f} req/s")
+    lat, ndof, iters, relres = [], [], [], []
+    with sipg.Server(budget, max_active=8) as srv:
+        t0 = time.perf_counter()
+        ids = [None] * nreq
+        sub_wall = [0.0] * nreq
+        nxt = 0
+        finished = 0
+        while finished < nreq:
+            now = time.perf_counter() - t0
+            while nxt < nreq and arrivals[nxt] <= now:
+                ids[nxt] = submit(srv, reqs[nxt])
+                sub_wall[nxt] = time.perf_counter() - t0
+                nxt += 1
+            wait = 1 if nxt < nreq else 50
+            _a, _q, c = srv.progress(wait_ms=wait)
+            finished = sum(1 for i in range(nxt) if srv.status(ids[i])["state"] in (sipg.REQ_DONE, sipg.REQ_FAILED))
+        t_end = time.perf_counter() - t0
+        for i, rid in enumerate(ids):
+            st = srv.status(rid)
+            if st["state"] != sipg.REQ_DONE or st["relres"] > 1e-10:
+                raise RuntimeError(f"request {i} did not converge: {st}")
+            # server clock: submit -> done, plus the wait between arrival and submit
+            lat.append(st["t_done"] - st["t_submit"] + (sub_wall[i] - arrivals[i]))
+            ndof.append(st["ndof"])
+            iters.append(st["iters"])
+    lat = np.array(lat)
+    return {
+        "requests": nreq,
+        "qps": qps,
+        "utilisation_target": 0.7,
+        "mean_service_alone_ms": 1e3 * mean_s,
+        "p50_latency_ms": float(1e3 * np.percentile(lat, 50)),
+        "p99_latency_ms": float(1e3 * np.percentile(lat, 99)),
+        "max_latency_ms": float(1e3 * lat.max()),
+        "unknowns_per_s": float(sum(ndof) / t_end),
+        "makespan_s": t_end,
+        "total_unknowns": int(sum(ndof)),
+        "iterations": iters,
+        "precision": "FP32 preconditioner, FP64 flexible CG",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +178,8 @@ def main():
     ap.add_argument("--workload", default="cube16_p8_rel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel timing")
+    ap.add_argument("--serving-requests", type=int, default=24,
+                    help="requests of the serving stream run after the main measurement (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this solver's build runs on a single MI355X "
@@ -197,6 +280,13 @@ def main():
                                            "iterations": it2, "final_relres": rr2}
         log(f"FCG, FP{bits} preconditioner: {1e3 * el / args.steps:.3f} ms/solve, {it2} iterations")
         s2.close()
+
+    if args.serving_requests > 0:
+        log("serving stream ...")
+        detail["serving"] = serving_run(args.serving_requests, seed=5)
+        sv = detail["serving"]
+        log(f"serving: p50 {sv['p50_latency_ms']:.2f} ms, p99 {sv['p99_latency_ms']:.2f} ms, "
+            f"{sv['unknowns_per_s']:.4g} unknowns/s over {sv['makespan_s']:.2f} s")
 
     out = {
         "metric": METRIC,

@@ -190,6 +190,57 @@ typedef enum {
  * Synchronizes. */
 int sipg_time_kernel(sipg_ctx *c, int kernel, int level, int bits, int reps, double *ms);
 
+/* Context options. */
+typedef enum {
+  SIPG_OPT_GRAPH = 0  /* value 1: capture the flexible-CG preconditioner V-cycle into a
+                         HIP graph on its first use and replay it afterwards (needs a
+                         non-NULL stream at sipg_setup; kernel nodes only) */
+} sipg_option;
+int sipg_set_option(sipg_ctx *c, int option, int value);
+
+/* ---- serving: continuous batching of heterogeneous solves ---------------
+ * A server accepts solves of any mesh, order and aspect ratio (each a
+ * sipg_params plus a Fourier right-hand side as in sipg_rhs_fourier) and runs
+ * them with the flexible CG of sipg_pcg_solve.  Requests wait in a FIFO queue
+ * and are admitted when one of max_active slots is free and their device
+ * footprint (sipg_footprint plus the solution and right-hand side vectors)
+ * fits the memory budget.  Each admitted request owns a context, a stream and
+ * a graph-captured preconditioner; its steps are enqueued as soon as its
+ * previous step completes, so admitted requests run concurrently on the
+ * device.  A request's result is bitwise the one sipg_pcg_solve gives alone.
+ * The server is not thread safe: one host thread drives it. */
+typedef struct sipg_server sipg_server;
+typedef enum { SIPG_REQ_QUEUED = 0, SIPG_REQ_ACTIVE = 1, SIPG_REQ_DONE = 2, SIPG_REQ_FAILED = 3 } sipg_req_state;
+
+/* memory_budget: device bytes the server may hold for requests (> 0). */
+int sipg_server_create(size_t memory_budget, int max_active, sipg_server **out);
+
+/* Queues a solve to rel. residual rtol within maxit iterations; k/phi/amp are
+ * HOST arrays as in sipg_rhs_fourier (copied).  *id identifies the request.
+ * SIPG_EINVAL for invalid parameters (nothing is queued). */
+int sipg_server_submit(sipg_server *s, const sipg_params *p, int nmodes, const int32_t *k, const double *phi,
+                       const double *amp, double rtol, int maxit, int64_t *id);
+
+/* Admits what fits and advances every request whose last step completed;
+ * returns once at least one request finished (done or failed), or after
+ * wait_ms milliseconds, or when nothing is left.  Outputs may be NULL. */
+int sipg_server_progress(sipg_server *s, int wait_ms, int *nactive, int *nqueued, int *ncompleted);
+
+/* State (sipg_req_state), iterations, final relative residual, times[3] =
+ * (submitted, admitted, finished) in seconds since the server was created,
+ * and unknowns of a request.  Outputs may be NULL.  For a failed request the
+ * reason is in sipg_last_error(). */
+int sipg_server_status(sipg_server *s, int64_t id, int *state, int *iters, double *relres, double times[3],
+                       int64_t *ndof);
+
+/* Copies the solution of a finished request into the DEVICE vector u (its
+ * unknowns, element-major) on hip_stream, synchronizes that stream, and frees
+ * the request's memory. */
+int sipg_server_fetch(sipg_server *s, int64_t id, double *u, void *hip_stream);
+
+/* Waits for the device and frees everything the server holds. */
+int sipg_server_destroy(sipg_server *s);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *sipg_last_error(void);
 

@@ -1,0 +1,369 @@
+// Serving loop: continuous batching of heterogeneous Poisson solves.
+//
+// Requests (any mesh, order and aspect ratio) enter a FIFO queue.  A request
+// is admitted when an active slot is free and its device footprint (context
+// plus solution and right-hand side) fits the memory budget; it then gets its
+// own context (hierarchy, tables, Krylov vectors resident in HBM), its own
+// stream and a HIP-graph-captured preconditioner V-cycle.  The loop is
+// event driven: each active request has at most one flexible-CG step in
+// flight, followed by an event; whenever a request's event has completed the
+// loop reads its scalars, decides (converged / breakdown / next step) and
+// enqueues the next step at once.  Requests therefore never wait for one
+// another: small solves finish while large ones are still running, their
+// kernels overlap on the device, and new requests are admitted as slots and
+// memory free up.  Each request's kernel sequence is exactly the one of
+// sipg_pcg_solve, so its result does not depend on what else is running.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "kernels.h"
+#include "sipg_mg.h"
+#include "solver_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum Phase { PH_START = 0, PH_ITER = 1, PH_CONFIRM = 2 };
+
+struct Request {
+  int64_t id = 0;
+  sipg_params prm{};
+  std::vector<int32_t> k;
+  std::vector<double> phi, amp;
+  double rtol = 1e-10;
+  int maxit = 100;
+  int state = SIPG_REQ_QUEUED;
+  int phase = PH_START;
+  sipg_ctx *ctx = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  double *x = nullptr, *b = nullptr;
+  size_t bytes = 0;
+  int64_t ndof = 0;
+  int iters = 0;
+  double r0 = 0.0, relres = 1.0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  std::string err;
+};
+
+}  // namespace
+
+struct sipg_server {
+  size_t budget = 0, used = 0;
+  int max_active = 1;
+  Clock::time_point t0 = Clock::now();
+  int64_t next_id = 1;
+  std::deque<Request *> queue;
+  std::vector<Request *> active;
+  std::map<int64_t, std::unique_ptr<Request>> all;
+
+  double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+namespace {
+
+int fail(int code, const std::string &msg) {
+  sipg::detail::set_error(msg);
+  return code;
+}
+
+// Memory is accounted by reservation: an admitted request reserves its
+// footprint estimate plus its two vectors (r->bytes); the solution vector stays
+// reserved until it is fetched.
+void unreserve(sipg_server *s, size_t b) {
+  b = std::min(b, s->used);
+  s->used -= b;
+}
+
+void release_compute(sipg_server *s, Request *r) {
+  if (r->ctx) {
+    sipg_destroy(r->ctx);
+    r->ctx = nullptr;
+  }
+  if (r->b) {
+    (void)hipFree(r->b);
+    r->b = nullptr;
+  }
+  if (r->bytes) {
+    const size_t keep = r->x ? (size_t)r->ndof * sizeof(double) : 0;
+    unreserve(s, r->bytes - keep);
+    r->bytes = keep;
+  }
+  if (r->ev) {
+    (void)hipEventDestroy(r->ev);
+    r->ev = nullptr;
+  }
+  if (r->stream) {
+    (void)hipStreamDestroy(r->stream);
+    r->stream = nullptr;
+  }
+}
+
+void release_all(sipg_server *s, Request *r) {
+  release_compute(s, r);
+  if (r->x) {
+    (void)hipFree(r->x);
+    r->x = nullptr;
+  }
+  unreserve(s, r->bytes);
+  r->bytes = 0;
+}
+
+void finish(sipg_server *s, Request *r, int state, const std::string &err = "") {
+  r->state = state;
+  r->t_done = s->now();
+  r->err = err;
+  if (state == SIPG_REQ_DONE) release_compute(s, r);
+  else release_all(s, r);
+}
+
+// Admits the request: context, stream, vectors, right-hand side, first step.
+bool admit(sipg_server *s, Request *r) {
+  size_t fp = 0;
+  if (sipg_footprint(&r->prm, &fp) != SIPG_OK) {
+    finish(s, r, SIPG_REQ_FAILED, sipg_last_error());
+    return true;
+  }
+  int64_t E = (int64_t)r->prm.ne[0] * r->prm.ne[1] * r->prm.ne[2];
+  int64_t n = r->prm.P + 1;
+  r->ndof = E * n * n * n;
+  const size_t need = fp + 2 * (size_t)r->ndof * sizeof(double);
+  if (s->used + need > s->budget) return false;  // wait for memory
+  s->used += need;
+  r->bytes = need;
+  r->t_admit = s->now();
+  if (hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
+    finish(s, r, SIPG_REQ_FAILED, "stream or event creation failed");
+    return true;
+  }
+  if (sipg_setup(&r->prm, r->stream, &r->ctx) != SIPG_OK) {
+    finish(s, r, SIPG_REQ_FAILED, sipg_last_error());
+    return true;
+  }
+  if (hipMalloc(&r->x, r->ndof * sizeof(double)) != hipSuccess) {
+    finish(s, r, SIPG_REQ_FAILED, "out of device memory");
+    return true;
+  }
+  if (hipMalloc(&r->b, r->ndof * sizeof(double)) != hipSuccess) {
+    finish(s, r, SIPG_REQ_FAILED, "out of device memory");
+    return true;
+  }
+  if (sipg_rhs_fourier(r->ctx, (int)r->amp.size(), r->k.data(), r->phi.data(), r->amp.data(), r->b) != SIPG_OK) {
+    finish(s, r, SIPG_REQ_FAILED, sipg_last_error());
+    return true;
+  }
+  sipg::detail::enable_graph(r->ctx, true);
+  // x = 0 (a fill kernel on the request's stream)
+  if (sipg::launch_fill<double>(r->x, r->ndof, 0.0, r->stream) != hipSuccess) {
+    finish(s, r, SIPG_REQ_FAILED, "fill failed");
+    return true;
+  }
+  sipg::detail::fcg_start(r->ctx, r->x, r->b);
+  (void)hipEventRecord(r->ev, r->stream);
+  r->state = SIPG_REQ_ACTIVE;
+  r->phase = PH_START;
+  s->active.push_back(r);
+  return true;
+}
+
+// The request's last step has completed: decide and enqueue the next one.
+// Returns false when the request left the active set.
+bool advance(sipg_server *s, Request *r) {
+  const double *hs = sipg::detail::host_scalars(r->ctx);
+  try {
+    if (r->phase == PH_START) {
+      r->r0 = std::sqrt(hs[2]);
+      if (!std::isfinite(r->r0)) {
+        finish(s, r, SIPG_REQ_FAILED, "initial residual is not finite");
+        return false;
+      }
+      if (r->r0 == 0.0) {
+        r->relres = 0.0;
+        finish(s, r, SIPG_REQ_DONE);
+        return false;
+      }
+      sipg::detail::fcg_first_precond(r->ctx);
+      sipg::detail::fcg_apply_update(r->ctx, r->x);
+      r->iters = 1;
+      r->phase = PH_ITER;
+    } else if (r->phase == PH_ITER) {
+      const double pq = hs[1], rn = std::sqrt(hs[2]);
+      if (!(pq > 0.0) || !std::isfinite(pq)) {
+        finish(s, r, SIPG_REQ_FAILED, "flexible CG breakdown");
+        return false;
+      }
+      if (!std::isfinite(rn)) {
+        finish(s, r, SIPG_REQ_FAILED, "residual norm is not finite");
+        return false;
+      }
+      r->relres = rn / r->r0;
+      if (rn <= r->rtol * r->r0) {
+        sipg::detail::fcg_confirm(r->ctx, r->x, r->b);
+        r->phase = PH_CONFIRM;
+      } else if (r->iters >= r->maxit) {
+        finish(s, r, SIPG_REQ_FAILED, "tolerance not reached");
+        return false;
+      } else {
+        sipg::detail::fcg_precond_update(r->ctx);
+        sipg::detail::fcg_apply_update(r->ctx, r->x);
+        r->iters += 1;
+      }
+    } else {  // PH_CONFIRM
+      const double rt = std::sqrt(hs[2]);
+      if (rt <= r->rtol * r->r0) {
+        r->relres = rt / r->r0;
+        finish(s, r, SIPG_REQ_DONE);
+        return false;
+      }
+      if (r->iters >= r->maxit) {
+        finish(s, r, SIPG_REQ_FAILED, "tolerance not reached");
+        return false;
+      }
+      sipg::detail::fcg_restart_from_true(r->ctx);
+      sipg::detail::fcg_precond_update(r->ctx);
+      sipg::detail::fcg_apply_update(r->ctx, r->x);
+      r->iters += 1;
+      r->phase = PH_ITER;
+    }
+  } catch (const std::exception &e) {
+    finish(s, r, SIPG_REQ_FAILED, e.what());
+    return false;
+  }
+  if (hipEventRecord(r->ev, r->stream) != hipSuccess) {
+    finish(s, r, SIPG_REQ_FAILED, "event record failed");
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sipg_server_create(size_t memory_budget, int max_active, sipg_server **out) {
+  if (!out || memory_budget == 0 || max_active < 1) return fail(SIPG_EINVAL, "need budget > 0 and max_active >= 1");
+  sipg_server *s = new (std::nothrow) sipg_server();
+  if (!s) return fail(SIPG_ENOMEM, "host allocation failed");
+  s->budget = memory_budget;
+  s->max_active = max_active;
+  *out = s;
+  return SIPG_OK;
+}
+
+int sipg_server_submit(sipg_server *s, const sipg_params *p, int nmodes, const int32_t *k, const double *phi,
+                       const double *amp, double rtol, int maxit, int64_t *id) {
+  if (!s || !p || !k || !phi || !amp || !id) return fail(SIPG_EINVAL, "null argument");
+  if (nmodes < 1 || nmodes > 64) return fail(SIPG_EINVAL, "nmodes must be in 1..64");
+  if (!(rtol > 0.0) || maxit < 1) return fail(SIPG_EINVAL, "need rtol > 0 and maxit >= 1");
+  size_t fp = 0;
+  int rc = sipg_footprint(p, &fp);  // validates the parameters
+  if (rc != SIPG_OK) return rc;
+  auto r = std::make_unique<Request>();
+  r->id = s->next_id++;
+  r->prm = *p;
+  r->k.assign(k, k + 3 * nmodes);
+  r->phi.assign(phi, phi + 3 * nmodes);
+  r->amp.assign(amp, amp + nmodes);
+  r->rtol = rtol;
+  r->maxit = maxit;
+  r->t_submit = s->now();
+  *id = r->id;
+  s->queue.push_back(r.get());
+  s->all[r->id] = std::move(r);
+  return SIPG_OK;
+}
+
+int sipg_server_progress(sipg_server *s, int wait_ms, int *nactive, int *nqueued, int *ncompleted) {
+  if (!s) return fail(SIPG_EINVAL, "null server");
+  int done = 0;
+  const double deadline = s->now() + std::max(0, wait_ms) * 1e-3;
+  for (;;) {
+    // admission, first come first served, while slots and memory allow
+    while (!s->queue.empty() && (int)s->active.size() < s->max_active) {
+      Request *r = s->queue.front();
+      if (!admit(s, r)) break;
+      s->queue.pop_front();
+      if (r->state != SIPG_REQ_ACTIVE) ++done;
+    }
+    // advance every request whose step has completed
+    for (size_t i = 0; i < s->active.size();) {
+      Request *r = s->active[i];
+      const hipError_t q = hipEventQuery(r->ev);
+      if (q == hipErrorNotReady) {
+        ++i;
+        continue;
+      }
+      bool keep = (q == hipSuccess) ? advance(s, r) : (finish(s, r, SIPG_REQ_FAILED, hipGetErrorString(q)), false);
+      if (!keep) {
+        ++done;
+        s->active.erase(s->active.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+    if (done > 0 || s->now() >= deadline || (s->active.empty() && s->queue.empty())) break;
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+  if (nactive) *nactive = (int)s->active.size();
+  if (nqueued) *nqueued = (int)s->queue.size();
+  if (ncompleted) *ncompleted = done;
+  return SIPG_OK;
+}
+
+int sipg_server_status(sipg_server *s, int64_t id, int *state, int *iters, double *relres, double times[3],
+                       int64_t *ndof) {
+  if (!s) return fail(SIPG_EINVAL, "null server");
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return fail(SIPG_EINVAL, "unknown request id");
+  const Request *r = it->second.get();
+  if (state) *state = r->state;
+  if (iters) *iters = r->iters;
+  if (relres) *relres = r->relres;
+  if (times) {
+    times[0] = r->t_submit;
+    times[1] = r->t_admit;
+    times[2] = r->t_done;
+  }
+  if (ndof) {
+    const int64_t E = (int64_t)r->prm.ne[0] * r->prm.ne[1] * r->prm.ne[2];
+    const int64_t n = r->prm.P + 1;
+    *ndof = E * n * n * n;
+  }
+  if (r->state == SIPG_REQ_FAILED) sipg::detail::set_error(r->err);
+  return SIPG_OK;
+}
+
+int sipg_server_fetch(sipg_server *s, int64_t id, double *u, void *hip_stream) {
+  if (!s || !u) return fail(SIPG_EINVAL, "null argument");
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return fail(SIPG_EINVAL, "unknown request id");
+  Request *r = it->second.get();
+  if (r->state != SIPG_REQ_DONE || !r->x) return fail(SIPG_EINVAL, "request has no result");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (hipMemcpyAsync(u, r->x, r->ndof * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(SIPG_EHIP, "result copy failed");
+  release_all(s, r);
+  return SIPG_OK;
+}
+
+int sipg_server_destroy(sipg_server *s) {
+  if (!s) return SIPG_OK;
+  (void)hipDeviceSynchronize();
+  for (auto &kv : s->all) release_all(s, kv.second.get());
+  delete s;
+  return SIPG_OK;
+}
+
+}  // extern "C"

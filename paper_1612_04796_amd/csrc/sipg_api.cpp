@@ -17,6 +17,7 @@
 #include "host_tables.h"
 #include "kernels.h"
 #include "sipg_mg.h"
+#include "solver_internal.h"
 
 namespace {
 
@@ -95,6 +96,9 @@ struct sipg_ctx {
   const double *xi_top = nullptr, *mass_top[3] = {nullptr, nullptr, nullptr};
   std::vector<double> hist;
   size_t bytes = 0;
+  bool use_graph = false;               // replay the preconditioner from a captured graph
+  hipGraphExec_t precond_graph = nullptr;
+  bool graph_failed = false;
 
   template <typename T>
   T *alloc(size_t count) {
@@ -107,6 +111,7 @@ struct sipg_ctx {
     return static_cast<T *>(p);
   }
   ~sipg_ctx() {
+    if (precond_graph) (void)hipGraphExecDestroy(precond_graph);
     for (void *p : allocs) (void)hipFree(p);
     if (host_scal) (void)hipHostFree(host_scal);
   }
@@ -401,7 +406,7 @@ void vcycle_impl(sipg_ctx *c, T *uL, const T *fL, bool zero_start, const T *r_to
 namespace {
 
 // z = B r with B one V-cycle from zero in the preconditioner precision.
-void precond_impl(sipg_ctx *c, const double *r, double *z) {
+void precond_body(sipg_ctx *c, const double *r, double *z) {
   const int64_t N = level_ndof(c->H, c->L);
   if (c->H.prm.precond_bits == 64) {
     vcycle_impl<double>(c, z, r, true, nullptr);
@@ -412,6 +417,41 @@ void precond_impl(sipg_ctx *c, const double *r, double *z) {
   check(sipg::launch_convert<float, double>(r, w.fL, N, c->stream), "precond cast");
   vcycle_impl<float>(c, w.uL, w.fL, true, nullptr);
   check(sipg::launch_convert<double, float>(w.uL, z, N, c->stream), "precond cast");
+}
+
+// The preconditioner of the flexible CG vectors (fixed pointers) is captured
+// once into a HIP graph and replayed when the context asks for it; the graph
+// holds kernel nodes only.
+void precond_impl(sipg_ctx *c, const double *r, double *z) {
+  const bool graphable = c->use_graph && !c->graph_failed && c->stream != nullptr && r == c->cg_r && z == c->cg_z;
+  if (!graphable) {
+    precond_body(c, r, z);
+    return;
+  }
+  if (!c->precond_graph) {
+    ensure_work<double>(c);
+    if (c->H.prm.precond_bits == 32) ensure_work<float>(c);
+    check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "graph capture");
+    hipGraph_t g = nullptr;
+    try {
+      precond_body(c, r, z);
+    } catch (...) {
+      (void)hipStreamEndCapture(c->stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      c->graph_failed = true;
+      throw;
+    }
+    check(hipStreamEndCapture(c->stream, &g), "graph capture");
+    hipError_t e = hipGraphInstantiate(&c->precond_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->precond_graph = nullptr;
+      c->graph_failed = true;
+      precond_body(c, r, z);
+      return;
+    }
+  }
+  check(hipGraphLaunch(c->precond_graph, c->stream), "graph launch");
 }
 
 // Device scalars -> host (synchronizes the stream).
@@ -457,28 +497,19 @@ int mg_solve_impl(sipg_ctx *c, double *u, const double *f, double rtol, int maxc
 
 int pcg_solve_impl(sipg_ctx *c, double *x, const double *b, double rtol, int maxit, int *iters,
                    double *relres) {
-  const int64_t N = level_ndof(c->H, c->L);
-  double *r = c->cg_r, *p = c->cg_p, *q = c->cg_q, *z = c->cg_z;
   c->hist.clear();
   if (iters) *iters = 0;
-  residual_norm2(c, x, b, r, sipg::FS_RR);
-  read_scalars(c);
+  sipg::detail::fcg_start(c, x, b);
+  check(hipStreamSynchronize(c->stream), "fcg");
   const double r0 = std::sqrt(c->host_scal[sipg::FS_RR]);
   c->hist.push_back(r0);
   if (!std::isfinite(r0)) return fail(SIPG_ENOTFINITE, "initial residual is not finite");
   if (relres) *relres = 0.0;
   if (r0 == 0.0) return SIPG_OK;
-  precond_impl(c, r, z);
-  dot(c, r, z, N, sipg::FS_RZ);
-  check(sipg::launch_convert<double, double>(z, p, N, c->stream), "copy");
+  sipg::detail::fcg_first_precond(c);
   for (int it = 1; it <= maxit; ++it) {
-    op_apply<double>(c, c->L, p, q, c->partial);
-    check(sipg::launch_finalize(c->partial, sipg::apply_num_blocks(c->mesh.E, c->t64[c->L].n), 1.0,
-                                c->scal + sipg::FS_PQ, c->stream),
-          "dot");
-    check(sipg::launch_fcg_xr(x, r, p, q, N, c->scal, c->partial, c->stream), "fcg update");
-    check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + sipg::FS_RR, c->stream), "dot");
-    read_scalars(c);
+    sipg::detail::fcg_apply_update(c, x);
+    check(hipStreamSynchronize(c->stream), "fcg");
     const double pq = c->host_scal[sipg::FS_PQ];
     double rn = std::sqrt(c->host_scal[sipg::FS_RR]);
     if (iters) *iters = it;
@@ -488,26 +519,20 @@ int pcg_solve_impl(sipg_ctx *c, double *x, const double *b, double rtol, int max
     }
     if (!std::isfinite(rn)) return fail(SIPG_ENOTFINITE, "residual norm is not finite");
     if (rn <= rtol * r0) {
-      // confirm with the recomputed residual b - A x
-      residual_norm2(c, x, b, q, sipg::FS_RR);
-      read_scalars(c);
+      sipg::detail::fcg_confirm(c, x, b);
+      check(hipStreamSynchronize(c->stream), "fcg");
       const double rt = std::sqrt(c->host_scal[sipg::FS_RR]);
       if (rt <= rtol * r0) {
         c->hist.push_back(rt);
         if (relres) *relres = rt / r0;
         return SIPG_OK;
       }
-      // keep iterating from the true residual; q is rebuilt below
-      check(sipg::launch_convert<double, double>(q, r, N, c->stream), "copy");
+      sipg::detail::fcg_restart_from_true(c);
       rn = rt;
-      op_apply<double>(c, c->L, p, q, nullptr);
     }
     c->hist.push_back(rn);
     if (relres) *relres = rn / r0;
-    precond_impl(c, r, z);
-    check(sipg::launch_dot2_partials<double>(z, q, r, z, N, c->partial, c->stream), "dot2");
-    check(sipg::launch_fcg_finalize2(c->partial, c->scal, c->stream), "dot2");
-    check(sipg::launch_fcg_p(p, z, N, c->scal, c->stream), "fcg update");
+    sipg::detail::fcg_precond_update(c);
   }
   return fail(SIPG_ENOCONV, "pcg_solve: tolerance not reached");
 }
@@ -534,6 +559,70 @@ int guarded(F &&fn) {
 }
 
 }  // namespace
+
+// ---- flexible CG in enqueue-only pieces (shared by sipg_pcg_solve and the
+// serving loop, so both run the same kernel sequence) ----------------------
+namespace sipg {
+namespace detail {
+
+static void copy_scalars_async(sipg_ctx *c) {
+  check(hipMemcpyAsync(c->host_scal, c->scal, sipg::FS_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                       c->stream),
+        "scalar readback");
+}
+
+void fcg_start(sipg_ctx *c, double *x, const double *b) {
+  residual_norm2(c, x, b, c->cg_r, sipg::FS_RR);
+  copy_scalars_async(c);
+}
+
+void fcg_first_precond(sipg_ctx *c) {
+  const int64_t N = level_ndof(c->H, c->L);
+  precond_impl(c, c->cg_r, c->cg_z);
+  dot(c, c->cg_r, c->cg_z, N, sipg::FS_RZ);
+  check(sipg::launch_convert<double, double>(c->cg_z, c->cg_p, N, c->stream), "copy");
+}
+
+void fcg_apply_update(sipg_ctx *c, double *x) {
+  const int64_t N = level_ndof(c->H, c->L);
+  op_apply<double>(c, c->L, c->cg_p, c->cg_q, c->partial);
+  check(sipg::launch_finalize(c->partial, sipg::apply_num_blocks(c->mesh.E, c->t64[c->L].n), 1.0,
+                              c->scal + sipg::FS_PQ, c->stream),
+        "dot");
+  check(sipg::launch_fcg_xr(x, c->cg_r, c->cg_p, c->cg_q, N, c->scal, c->partial, c->stream), "fcg update");
+  check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + sipg::FS_RR, c->stream), "dot");
+  copy_scalars_async(c);
+}
+
+void fcg_confirm(sipg_ctx *c, const double *x, const double *b) {
+  residual_norm2(c, x, b, c->cg_q, sipg::FS_RR);
+  copy_scalars_async(c);
+}
+
+void fcg_restart_from_true(sipg_ctx *c) {
+  const int64_t N = level_ndof(c->H, c->L);
+  check(sipg::launch_convert<double, double>(c->cg_q, c->cg_r, N, c->stream), "copy");
+  op_apply<double>(c, c->L, c->cg_p, c->cg_q, nullptr);
+}
+
+void fcg_precond_update(sipg_ctx *c) {
+  const int64_t N = level_ndof(c->H, c->L);
+  precond_impl(c, c->cg_r, c->cg_z);
+  check(sipg::launch_dot2_partials<double>(c->cg_z, c->cg_q, c->cg_r, c->cg_z, N, c->partial, c->stream), "dot2");
+  check(sipg::launch_fcg_finalize2(c->partial, c->scal, c->stream), "dot2");
+  check(sipg::launch_fcg_p(c->cg_p, c->cg_z, N, c->scal, c->stream), "fcg update");
+}
+
+const double *host_scalars(const sipg_ctx *c) { return c->host_scal; }
+hipStream_t ctx_stream(const sipg_ctx *c) { return c->stream; }
+void enable_graph(sipg_ctx *c, bool on) { c->use_graph = on; }
+int64_t ctx_ndof(const sipg_ctx *c) { return level_ndof(c->H, c->L); }
+size_t ctx_bytes(const sipg_ctx *c) { return c->bytes; }
+std::string last_error() { return g_err; }
+void set_error(const std::string &m) { g_err = m; }
+
+}  // namespace detail
+}  // namespace sipg
 
 extern "C" {
 
@@ -843,6 +932,13 @@ int sipg_time_kernel(sipg_ctx *c, int kernel, int level, int bits, int reps, dou
     else run(float());
     return (int)SIPG_OK;
   });
+}
+
+int sipg_set_option(sipg_ctx *c, int option, int value) {
+  if (!c) return fail(SIPG_EINVAL, "null context");
+  if (option != SIPG_OPT_GRAPH) return fail(SIPG_EINVAL, "unknown option");
+  c->use_graph = value != 0;
+  return SIPG_OK;
 }
 
 int sipg_residual_history(const sipg_ctx *c, double *out, int cap, int *n) {

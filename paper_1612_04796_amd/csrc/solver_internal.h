@@ -1,0 +1,39 @@
+// Internal interface between the solver context (sipg_api.cpp) and the serving
+// loop (serving.cpp).  Every fcg_* call only enqueues work on the context's
+// stream; the scalars it produces are copied asynchronously to the context's
+// pinned host mirror (indices FcgScalar) and are valid once the stream has
+// passed that point.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "sipg_mg.h"
+
+namespace sipg {
+namespace detail {
+
+// r = b - A x and ||r||^2 (FS_RR)
+void fcg_start(sipg_ctx *c, double *x, const double *b);
+// z = B r, rz = r.z, p = z
+void fcg_first_precond(sipg_ctx *c);
+// q = A p, p.q (FS_PQ), x += alpha p, r -= alpha q, ||r||^2 (FS_RR)
+void fcg_apply_update(sipg_ctx *c, double *x);
+// ||b - A x||^2 (FS_RR), the true residual kept in q
+void fcg_confirm(sipg_ctx *c, const double *x, const double *b);
+// r = true residual, q = A p again
+void fcg_restart_from_true(sipg_ctx *c);
+// z = B r, beta = -alpha (z.q) / rz, rz = r.z, p = z + beta p
+void fcg_precond_update(sipg_ctx *c);
+
+const double *host_scalars(const sipg_ctx *c);
+hipStream_t ctx_stream(const sipg_ctx *c);
+void enable_graph(sipg_ctx *c, bool on);
+int64_t ctx_ndof(const sipg_ctx *c);
+size_t ctx_bytes(const sipg_ctx *c);
+std::string last_error();
+void set_error(const std::string &m);
+
+}  // namespace detail
+}  // namespace sipg

@@ -26,8 +26,11 @@ EXPORTS = (
     "sipg_level_info", "sipg_rhs_fourier", "sipg_apply_A", "sipg_residual", "sipg_schwarz",
     "sipg_smooth", "sipg_restrict", "sipg_prolong_add", "sipg_coarse_solve", "sipg_vcycle",
     "sipg_precond", "sipg_mg_solve", "sipg_pcg_solve", "sipg_residual_history",
-    "sipg_last_error", "sipg_host_table", "sipg_time_kernel",
+    "sipg_last_error", "sipg_host_table", "sipg_time_kernel", "sipg_set_option",
+    "sipg_server_create", "sipg_server_submit", "sipg_server_progress", "sipg_server_status",
+    "sipg_server_fetch", "sipg_server_destroy",
 )
+REQ_QUEUED, REQ_ACTIVE, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 KERNELS = {"residual": 0, "schwarz_solve": 1, "schwarz_assemble": 2, "restrict": 3, "prolong": 4}
 
 
@@ -86,6 +89,15 @@ def lib():
             "sipg_last_error": (ctypes.c_char_p, []),
             "sipg_host_table": (c_int, [P(Params), c_int, c_int, c_int, P(c_double), c_int, P(c_int)]),
             "sipg_time_kernel": (c_int, [vp, c_int, c_int, c_int, c_int, P(c_double)]),
+            "sipg_set_option": (c_int, [vp, c_int, c_int]),
+            "sipg_server_create": (c_int, [ctypes.c_size_t, c_int, P(vp)]),
+            "sipg_server_submit": (c_int, [vp, P(Params), c_int, P(ctypes.c_int32), P(c_double), P(c_double),
+                                           c_double, c_int, P(ctypes.c_int64)]),
+            "sipg_server_progress": (c_int, [vp, c_int, P(c_int), P(c_int), P(c_int)]),
+            "sipg_server_status": (c_int, [vp, ctypes.c_int64, P(c_int), P(c_int), P(c_double), P(c_double),
+                                           P(ctypes.c_int64)]),
+            "sipg_server_fetch": (c_int, [vp, ctypes.c_int64, vp, vp]),
+            "sipg_server_destroy": (c_int, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -276,9 +288,81 @@ class Solver:
         _check(lib().sipg_time_kernel(self._h, KERNELS[kernel], level, bits, reps, ctypes.byref(ms)))
         return ms.value
 
+    def set_option(self, option, value):
+        """SIPG_OPT_GRAPH (0): replay the flexible-CG preconditioner from a
+        captured HIP graph (needs a non-default stream)."""
+        _check(lib().sipg_set_option(self._h, int(option), int(value)))
+
     def residual_history(self):
         n = ctypes.c_int()
         _check(lib().sipg_residual_history(self._h, None, 0, ctypes.byref(n)))
         buf = (ctypes.c_double * max(1, n.value))()
         _check(lib().sipg_residual_history(self._h, buf, n.value, ctypes.byref(n)))
         return list(buf[:n.value])
+
+
+class Server:
+    """Continuous-batching solve server (sipg_server_*): submit heterogeneous
+    solves, drive it with progress(), read status, fetch results."""
+
+    def __init__(self, memory_budget, max_active=8):
+        h = ctypes.c_void_p()
+        _check(lib().sipg_server_create(int(memory_budget), int(max_active), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sipg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def submit(self, k, phi, amp, rtol=1e-10, maxit=100, **params):
+        import numpy as np
+        p = make_params(**params)
+        k = np.ascontiguousarray(k, dtype=np.int32).reshape(-1)
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
+        amp = np.ascontiguousarray(amp, dtype=np.float64).reshape(-1)
+        rid = ctypes.c_int64()
+        _check(lib().sipg_server_submit(
+            self._h, ctypes.byref(p), len(amp), k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            phi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            amp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(rtol), int(maxit), ctypes.byref(rid)))
+        return rid.value
+
+    def progress(self, wait_ms=10):
+        a, q, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().sipg_server_progress(self._h, int(wait_ms), ctypes.byref(a), ctypes.byref(q), ctypes.byref(c)))
+        return a.value, q.value, c.value
+
+    def status(self, rid):
+        st, it = ctypes.c_int(), ctypes.c_int()
+        rr = ctypes.c_double()
+        t = (ctypes.c_double * 3)()
+        nd = ctypes.c_int64()
+        _check(lib().sipg_server_status(self._h, int(rid), ctypes.byref(st), ctypes.byref(it), ctypes.byref(rr),
+                                        t, ctypes.byref(nd)))
+        out = {"state": st.value, "iters": it.value, "relres": rr.value, "t_submit": t[0], "t_admit": t[1],
+               "t_done": t[2], "ndof": nd.value}
+        if st.value == REQ_FAILED:
+            out["error"] = lib().sipg_last_error().decode(errors="replace")
+        return out
+
+    def fetch(self, rid, u):
+        import torch
+        if u.dtype != torch.float64 or not u.is_cuda or not u.is_contiguous():
+            raise TypeError("u must be a contiguous float64 CUDA tensor")
+        if u.numel() != self.status(rid)["ndof"]:
+            raise ValueError("u has the wrong number of values")
+        _check(lib().sipg_server_fetch(self._h, int(rid), ctypes.c_void_p(u.data_ptr()), _stream_handle()))
+        return u

@@ -1,0 +1,119 @@
+"""Serving loop (continuous batching).  CPU part: request validation and
+server creation without a device.  GPU part: a mix of heterogeneous requests
+(different meshes, orders, aspect ratios) admitted by memory footprint and run
+concurrently; every result must equal, bitwise, the same solve run alone
+with sipg_pcg_solve (the kernels are deterministic), and must match the
+exact discrete solution of the oracle."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_04796_amd import sipg
+from paper_1612_04796_amd.workloads import fourier_modes
+
+
+def test_server_rejects_invalid_requests():
+    with pytest.raises(sipg.SipgError):
+        sipg.Server(0, 4)
+    with sipg.Server(1 << 30, 4) as srv:
+        k, phi, amp = fourier_modes(0, 3)
+        with pytest.raises(sipg.SipgError) as ei:
+            srv.submit(k, phi, amp, ne=(2, 4, 4), P=4)
+        assert ei.value.code == sipg.EINVAL
+        with pytest.raises(sipg.SipgError):
+            srv.submit(k, phi, amp, rtol=0.0, ne=(4, 4, 4), P=4)
+        with pytest.raises(sipg.SipgError):
+            srv.submit(k, phi, amp, ne=(4, 4, 4), P=20)
+
+
+MIX = [
+    dict(ne=(4, 4, 4), length=(1.0, 1.0, 1.0), P=2, overlap="max", omega=0.08),
+    dict(ne=(6, 6, 6), length=(3.0, 1.0, 1.0), P=8, overlap="max", omega=0.08),
+    dict(ne=(5, 5, 5), length=(1.0, 1.0, 1.0), P=4, overlap="max", omega=0.08),
+    dict(ne=(4, 4, 4), length=(8.0, 1.0, 1.0), P=16, overlap="max", omega=0.08),
+    dict(ne=(8, 8, 8), length=(2.0, 1.0, 1.0), P=4, overlap="max", omega=0.08),
+    dict(ne=(3, 3, 3), length=(1.0, 1.0, 1.0), P=32, overlap="max", omega=0.08),
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("bits", [32, 64])
+def test_results_alone_equal_results_in_the_mix(bits):
+    from _gpu import announce, host, rel, torch_cuda, zeros
+    torch = torch_cuda()
+    announce("serving mix", bits)
+    alone = []
+    for i, prm in enumerate(MIX):
+        k, phi, amp = fourier_modes(100 + i, 3)
+        with sipg.Solver(precond_bits=bits, **prm) as s:
+            b = zeros(s.ndof())
+            s.rhs_fourier(k, phi, amp, b)
+            x = zeros(s.ndof())
+            it, rr = s.pcg_solve(x, b, rtol=1e-10, maxit=100)
+            alone.append((host(x), it, rr))
+    with sipg.Server(64 << 30, max_active=4) as srv:
+        ids = []
+        for i, prm in enumerate(MIX):
+            k, phi, amp = fourier_modes(100 + i, 3)
+            ids.append(srv.submit(k, phi, amp, rtol=1e-10, maxit=100, precond_bits=bits, **prm))
+        seen_active = 0
+        for _ in range(100000):
+            a, q, _c = srv.progress(wait_ms=50)
+            seen_active = max(seen_active, a)
+            if a == 0 and q == 0:
+                break
+        assert seen_active >= 2          # requests really ran together
+        for i, rid in enumerate(ids):
+            st = srv.status(rid)
+            assert st["state"] == sipg.REQ_DONE, st
+            assert st["t_submit"] <= st["t_admit"] <= st["t_done"]
+            u = zeros(st["ndof"])
+            srv.fetch(rid, u)
+            xs, it, rr = alone[i]
+            assert st["iters"] == it
+            assert np.array_equal(host(u), xs), i
+            assert st["relres"] <= 1e-10
+
+
+@pytest.mark.gpu
+def test_served_solution_matches_oracle():
+    from _gpu import announce, host, rel, torch_cuda, zeros
+    torch_cuda()
+    announce("serving oracle")
+    prm = dict(ne=(4, 4, 4), length=(4.0, 1.0, 1.0), P=8, overlap="max", omega=0.08)
+    k, phi, amp = fourier_modes(7, 3)
+    h = oracle.Hierarchy(prm["ne"], prm["length"], prm["P"], overlap="max", omega=0.08)
+    b = oracle.fourier_rhs(k, phi, amp, h)
+    with sipg.Server(8 << 30, max_active=2) as srv:
+        rid = srv.submit(k, phi, amp, precond_bits=32, **prm)
+        while True:
+            a, q, _ = srv.progress(wait_ms=50)
+            if a == 0 and q == 0:
+                break
+        st = srv.status(rid)
+        assert st["state"] == sipg.REQ_DONE
+        u = zeros(st["ndof"])
+        srv.fetch(rid, u)
+    x = host(u)
+    assert rel(x - x.mean(), oracle.exact_solution(b, h)) <= 1e-8
+
+
+@pytest.mark.gpu
+def test_memory_budget_limits_admission():
+    from _gpu import announce, torch_cuda
+    torch_cuda()
+    announce("serving budget")
+    prm = dict(ne=(4, 4, 4), P=4, overlap="min")
+    one = sipg.footprint(**prm) + 2 * 8000 * 8
+    with sipg.Server(int(one * 1.5), max_active=8) as srv:
+        ids = [srv.submit(*fourier_modes(i, 3), **prm) for i in range(3)]
+        while True:
+            a, q, _ = srv.progress(wait_ms=20)
+            if a == 0 and q == 0:
+                break
+        st = [srv.status(r) for r in ids]
+        assert all(x["state"] == sipg.REQ_DONE for x in st)
+        # the budget holds one request at a time: active intervals are disjoint
+        spans = sorted((x["t_admit"], x["t_done"]) for x in st)
+        assert all(spans[i][1] <= spans[i + 1][0] for i in range(len(spans) - 1)), spans
