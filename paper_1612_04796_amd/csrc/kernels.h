@@ -40,14 +40,18 @@ int apply_large_num_blocks(int E, int n);
 template <typename T>
 hipError_t launch_apply_large(const ApplyLaunch<T> &a, T *tmp, hipStream_t st);
 
-// u_f += (J x J x J)(u_c - *mean) per element (mean may be null).
+// u_f += (J x J x J)(u_c - m) per element, where m = mean_scale * (sum of
+// the n_partials values at mean_partials) when mean_partials is not null (the
+// Euclidean mean of the level-0 solution, from the coarse solve's row sums).
 template <typename T, typename TC>
 struct ProlongLaunch {
   int E;
   int nf, nc;
   const T *J;
   const TC *uc;
-  const double *mean;
+  const double *mean_partials;
+  int n_partials;
+  double mean_scale;
   T *uf;
 };
 template <typename T, typename TC>
@@ -92,11 +96,12 @@ struct CoarseLaunch {
   const double *colsum[3];  // column sums of S
   const double *lam[3];     // eigenvalues, zero mode exactly 0
   int zero[3];              // zero-mode index per direction
-  double *t0, *t1;          // two work arrays of N0 = N[0]*N[1]*N[2] doubles
-  double *partial;          // kCoarsePartials doubles
+  double *t0;               // work array of N0 = N[0]*N[1]*N[2] doubles
+  double *partial;          // coarse_num_partials() plane sums of f0
+  double *partial_u;        // coarse_num_partials() plane sums of u0
   double *scalars;          // [0] mean of f0, [1] mean of u0
 };
-constexpr int kCoarsePartials = 256;
+int coarse_num_partials(const CoarseLaunch &c);
 template <typename TI>
 hipError_t launch_coarse(const CoarseLaunch &a, const TI *f0, double *u0, bool subtract_mean,
                          hipStream_t st);

@@ -84,12 +84,13 @@ __device__ __forceinline__ T line_op(const T (&v)[N], int i, const T *__restrict
   return acc;
 }
 
+// EPB (elements per workgroup) is chosen at launch, at most ApplyShape<N>::EPB.
 template <typename T, int N, int MODE, bool DOT>
 __global__ void __launch_bounds__(ApplyShape<N>::NTH)
 apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restrict__ f, T *__restrict__ out,
-             T *__restrict__ partial, const T *__restrict__ J) {
+             T *__restrict__ partial, const T *__restrict__ J, int EPB) {
   using Sh = ApplyShape<N>;
-  constexpr int N2 = Sh::N2, N3 = Sh::N3, EPB = Sh::EPB;
+  constexpr int N2 = Sh::N2, N3 = Sh::N3;
   constexpr int NC = coarse_n(N);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *su = reinterpret_cast<T *>(smem_raw);
@@ -118,7 +119,7 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
     fy = face_data<T, N>(uyr, uyl, N, tb.DL[1], tb.DR[1]);
     fz = face_data<T, N>(uzr, uzl, N2, tb.DL[2], tb.DR[2]);
   }
-  for (int idx = t; idx < nloc * N3; idx += Sh::NTH) su[idx] = u[(size_t)e0 * N3 + idx];
+  for (int idx = t; idx < nloc * N3; idx += blockDim.x) su[idx] = u[(size_t)e0 * N3 + idx];
   __syncthreads();
 
   if (active) {  // x: line (k=p, j=q), contiguous
@@ -188,7 +189,7 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
     }
     __syncthreads();
     // y: su[le][k][j][a] -> sy[le][k][b][a]; lines (le, k, a)
-    for (int L = t; L < nloc * N * NC; L += Sh::NTH) {
+    for (int L = t; L < nloc * N * NC; L += blockDim.x) {
       const int l2 = L / (N * NC), ka = L - l2 * N * NC;
       const int k = ka / NC, a = ka - k * NC;
       T v[N];
@@ -205,7 +206,7 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
     __syncthreads();
     // z: sy[le][k][b][a] -> out[e][c][b][a]; lines (le, b, a)
     constexpr int NC2 = NC * NC, NC3 = NC2 * NC;
-    for (int L = t; L < nloc * NC2; L += Sh::NTH) {
+    for (int L = t; L < nloc * NC2; L += blockDim.x) {
       const int l2 = L / NC2, ba = L - l2 * NC2;
       T v[N];
 #pragma unroll
@@ -224,8 +225,8 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
 // u_f += (J x J x J)(u_c - mean), element by element; J is NF x NC.
 template <typename T, typename TC, int NF>
 __global__ void __launch_bounds__(ApplyShape<NF>::NTH)
-prolong_kernel(int E, const T *__restrict__ J, const TC *__restrict__ uc, const double *__restrict__ mean,
-               T *__restrict__ uf) {
+prolong_kernel(int E, const T *__restrict__ J, const TC *__restrict__ uc, const double *__restrict__ mean_partials,
+               int n_partials, double mean_scale, T *__restrict__ uf) {
   using Sh = ApplyShape<NF>;
   constexpr int NC = coarse_n(NF);
   constexpr int NF2 = NF * NF, NF3 = NF2 * NF, NC2 = NC * NC, NC3 = NC2 * NC, EPB = Sh::EPB;
@@ -237,8 +238,18 @@ prolong_kernel(int E, const T *__restrict__ J, const TC *__restrict__ uc, const 
   const int e0 = blk * EPB;
   const int nloc = min(EPB, E - e0);
   const int t = threadIdx.x;
-  const T m = mean ? (T)(*mean) : (T)0;
-  for (int idx = t; idx < nloc * NC3; idx += Sh::NTH) s0[idx] = (T)uc[(size_t)e0 * NC3 + idx] - m;
+  __shared__ double red[16];
+  __shared__ double mean_sh;
+  if (mean_partials) {  // every workgroup reduces the same partials in the same order
+    double ms = 0.0;
+    for (int i = t; i < n_partials; i += Sh::NTH) ms += mean_partials[i];
+    ms = block_reduce_sum(ms, red);
+    if (t == 0) mean_sh = ms * mean_scale;
+    __syncthreads();
+  }
+  const double m = mean_partials ? mean_sh : 0.0;
+  for (int idx = t; idx < nloc * NC3; idx += Sh::NTH)
+    s0[idx] = (T)((double)uc[(size_t)e0 * NC3 + idx] - m);
   __syncthreads();
   for (int L = t; L < nloc * NC2; L += Sh::NTH) {  // x: lines (le, c, b)
     const int le = L / NC2, cb = L - le * NC2;
@@ -291,14 +302,24 @@ hipError_t allow_lds(K kernel, size_t shm) {
   return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
 }
 
+// elements per workgroup: the full packing when the level fills the chip,
+// one wavefront per workgroup otherwise
+int apply_epb(int E, int n) {
+  const int full = std::max(1, 256 / (n * n));
+  if ((E + full - 1) / full >= 512) return full;
+  return std::max(1, std::min(full, 64 / (n * n)));
+}
+
 template <typename T, int N, int MODE, bool DOT>
 hipError_t launch_mode(const ApplyLaunch<T> &a, hipStream_t st) {
   using Sh = ApplyShape<N>;
-  const int nblk = (a.mesh.E + Sh::EPB - 1) / Sh::EPB;
-  const size_t shm = Sh::SHM * sizeof(T);
+  const int epb = apply_epb(a.mesh.E, N);
+  const int nblk = (a.mesh.E + epb - 1) / epb;
+  const int nth = std::min(Sh::NTH, (epb * N * N + 63) / 64 * 64);
+  const size_t shm = 2 * (size_t)epb * N * N * N * sizeof(T);
   hipError_t e = allow_lds(apply_kernel<T, N, MODE, DOT>, shm);
   if (e != hipSuccess) return e;
-  apply_kernel<T, N, MODE, DOT><<<nblk, Sh::NTH, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, a.partial, a.J);
+  apply_kernel<T, N, MODE, DOT><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, a.partial, a.J, epb);
   return hipGetLastError();
 }
 
@@ -329,7 +350,8 @@ hipError_t launch_prolong_n(const ProlongLaunch<T, TC> &a, hipStream_t st) {
     const size_t shm = (size_t)Sh::EPB * (NC * NC * NC + NC * NC * NF + NC * NF * NF) * sizeof(T);
     hipError_t e = allow_lds(prolong_kernel<T, TC, NF>, shm);
     if (e != hipSuccess) return e;
-    prolong_kernel<T, TC, NF><<<nblk, Sh::NTH, shm, st>>>(a.E, a.J, a.uc, a.mean, a.uf);
+    prolong_kernel<T, TC, NF><<<nblk, Sh::NTH, shm, st>>>(a.E, a.J, a.uc, a.mean_partials, a.n_partials,
+                                                          a.mean_scale, a.uf);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
@@ -339,8 +361,7 @@ hipError_t launch_prolong_n(const ProlongLaunch<T, TC> &a, hipStream_t st) {
 
 int apply_num_blocks(int E, int n) {
   if (apply_is_large(n)) return apply_large_num_blocks(E, n);
-  int epb = 256 / (n * n);
-  if (epb < 1) epb = 1;
+  const int epb = apply_epb(E, n);
   return (E + epb - 1) / epb;
 }
 

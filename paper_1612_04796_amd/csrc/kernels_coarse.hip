@@ -8,9 +8,14 @@
 // with Lambda^+ zero on the single zero mode.  The mean of f is removed after
 // the forward transform, using the column sums cs_d of S_d:
 //   (S^T x S^T x S^T)(f - m 1) = (S^T x S^T x S^T) f - m cs_z x cs_y x cs_x.
-// The contractions run one axis per kernel over global arrays in
-// lexicographic order (z, y, x); the level-0 vector is small (8 E values), so
-// these kernels are latency-bound.
+//
+// Three kernels on 2D planes held in LDS, with the 1D eigenvector tables in
+// LDS too when they fit (lexicographic (z, y, x) order):
+//   1. per z plane: x and y forward from the element-major f_0; plane sums
+//   2. per y plane: z forward, mean correction, Lambda^+, z backward
+//   3. per z plane: y and x backward into the element-major u_0; plane sums
+// The mean of u_0 is then either removed by two small kernels or, inside the
+// V-cycle, by the prolongation, which reduces the plane sums itself.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -25,100 +30,189 @@ struct Dims {
   int ne[3];
 };
 
-// element-major index of lexicographic node (gx, gy, gz) at order 1
 __device__ __forceinline__ int64_t elem_major_p1(const Dims &d, int gx, int gy, int gz) {
   const int e = ((gz >> 1) * d.ne[1] + (gy >> 1)) * d.ne[0] + (gx >> 1);
   return (int64_t)e * 8 + ((gz & 1) * 2 + (gy & 1)) * 2 + (gx & 1);
 }
 
-// out = contraction of `in` along AXIS with A (N_axis x N_axis):
-//   FWD: out[..o..] = sum_c A[c*Na + o] in[..c..]
-//   BWD: out[..o..] = sum_c A[o*Na + c] in[..c..]
-// IN_ELEM / OUT_ELEM select element-major order for the input / output.
-template <typename TI, int AXIS, bool FWD, bool IN_ELEM, bool OUT_ELEM>
-__global__ void __launch_bounds__(256)
-coarse_axis(Dims d, const double *__restrict__ A, const TI *__restrict__ in, double *__restrict__ out) {
-  const int64_t N0 = (int64_t)d.N[0] * d.N[1] * d.N[2];
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= N0) return;
-  int x = (int)(t % d.N[0]);
-  int y = (int)((t / d.N[0]) % d.N[1]);
-  int z = (int)(t / ((int64_t)d.N[0] * d.N[1]));
-  const int Na = d.N[AXIS];
-  const int o = AXIS == 0 ? x : (AXIS == 1 ? y : z);
-  double acc = 0.0;
-  for (int c = 0; c < Na; ++c) {
-    const int xx = AXIS == 0 ? c : x, yy = AXIS == 1 ? c : y, zz = AXIS == 2 ? c : z;
-    const int64_t ii = IN_ELEM ? elem_major_p1(d, xx, yy, zz)
-                               : ((int64_t)zz * d.N[1] + yy) * d.N[0] + xx;
-    const double a = FWD ? A[c * Na + o] : A[o * Na + c];
-    acc += a * (double)in[ii];
+// In-place contraction of the lines of a 2D tile in LDS along one of its two
+// axes, one thread per output entry, all inputs read before any output is
+// written (two barriers).  The tile is P[r * pitch + q]; ALONG_ROWS contracts
+// over q (rows of length n, `count` rows), else over r (columns of length n).
+//   FWD: out[o] = sum_a A[a*n + o] in[a];  else out[o] = sum_a A[o*n + a] in[a]
+template <bool ALONG_ROWS, bool FWD>
+__device__ void tile_contract(double *P, double *W, int pitch, int count, int n, const double *A) {
+  const int tot = count * n;
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+    const int line = i / n, o = i - line * n;
+    double acc = 0.0;
+    for (int a = 0; a < n; ++a) {
+      const double x = ALONG_ROWS ? P[line * pitch + a] : P[a * pitch + line];
+      acc += (FWD ? A[a * n + o] : A[o * n + a]) * x;
+    }
+    W[i] = acc;
   }
-  out[OUT_ELEM ? elem_major_p1(d, x, y, z) : t] = acc;
+  __syncthreads();
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+    const int line = i / n, o = i - line * n;
+    if (ALONG_ROWS) P[line * pitch + o] = W[i];
+    else P[o * pitch + line] = W[i];
+  }
+  __syncthreads();
 }
 
-// z forward transform, then the mean correction and Lambda^+ scaling
+// 1. one workgroup per z plane: the (y, x) plane of f_0 and Sx, Sy in LDS;
+//    x and y forward; the plane sum of f_0 -> partial[z]
+template <typename TI>
 __global__ void __launch_bounds__(256)
-coarse_z_scale(Dims d, CoarseLaunch c, const double *__restrict__ in, double *__restrict__ out) {
-  const int64_t N0 = (int64_t)d.N[0] * d.N[1] * d.N[2];
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= N0) return;
-  const int x = (int)(t % d.N[0]);
-  const int y = (int)((t / d.N[0]) % d.N[1]);
-  const int z = (int)(t / ((int64_t)d.N[0] * d.N[1]));
-  const int Nz = d.N[2];
-  const double *Sz = c.S[2];
-  double acc = 0.0;
-  for (int k = 0; k < Nz; ++k) acc += Sz[k * Nz + z] * in[((int64_t)k * d.N[1] + y) * d.N[0] + x];
-  const double mean = c.scalars[0];
-  acc -= mean * c.colsum[2][z] * c.colsum[1][y] * c.colsum[0][x];
-  const bool zero = (x == c.zero[0] && y == c.zero[1] && z == c.zero[2]);
-  out[t] = zero ? 0.0 : acc / (c.lam[0][x] + c.lam[1][y] + c.lam[2][z]);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256)
-sum_partials(const T *__restrict__ x, int64_t n, double *__restrict__ partial) {
+coarse_plane_xy_fwd(Dims d, CoarseLaunch c, const TI *__restrict__ f0, double *__restrict__ t, bool tabs_lds) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t lo = chunk * blockIdx.x;
-  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  const int Nx = d.N[0], Ny = d.N[1];
+  double *P = reinterpret_cast<double *>(smem_raw);
+  double *W = P + Nx * Ny;
+  const double *Sx = c.S[0], *Sy = c.S[1];
+  if (tabs_lds) {
+    double *sx = W + Nx * Ny, *sy = sx + Nx * Nx;
+    for (int i = threadIdx.x; i < Nx * Nx; i += blockDim.x) sx[i] = c.S[0][i];
+    for (int i = threadIdx.x; i < Ny * Ny; i += blockDim.x) sy[i] = c.S[1][i];
+    Sx = sx;
+    Sy = sy;
+  }
+  const int z = blockIdx.x;
   double s = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += (double)x[i];
+  for (int i = threadIdx.x; i < Nx * Ny; i += blockDim.x) {
+    const int x = i % Nx, y = i / Nx;
+    const double v = (double)f0[elem_major_p1(d, x, y, z)];
+    P[i] = v;
+    s += v;
+  }
   s = block_reduce_sum(s, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (threadIdx.x == 0) c.partial[z] = s;
+  __syncthreads();
+  tile_contract<true, true>(P, W, Nx, Ny, Nx, Sx);
+  tile_contract<false, true>(P, W, Nx, Nx, Ny, Sy);
+  double *tz = t + (size_t)z * Nx * Ny;
+  for (int i = threadIdx.x; i < Nx * Ny; i += blockDim.x) tz[i] = P[i];
+}
+
+// 2. one workgroup per y plane: the (z, x) plane and Sz in LDS; z forward,
+//    mean correction (mean from the plane sums), Lambda^+, z backward
+__global__ void __launch_bounds__(256)
+coarse_plane_z(Dims d, CoarseLaunch c, double *__restrict__ t, bool tabs_lds) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  __shared__ double mean_sh;
+  const int Nx = d.N[0], Ny = d.N[1], Nz = d.N[2];
+  double *P = reinterpret_cast<double *>(smem_raw);
+  double *W = P + Nx * Nz;
+  const double *Sz = c.S[2];
+  if (tabs_lds) {
+    double *sz = W + Nx * Nz;
+    for (int i = threadIdx.x; i < Nz * Nz; i += blockDim.x) sz[i] = c.S[2][i];
+    Sz = sz;
+  }
+  const int y = blockIdx.x;
+  for (int i = threadIdx.x; i < Nx * Nz; i += blockDim.x) {
+    const int x = i % Nx, z = i / Nx;
+    P[i] = t[((size_t)z * Ny + y) * Nx + x];
+  }
+  double s = 0.0;
+  for (int i = threadIdx.x; i < Nz; i += blockDim.x) s += c.partial[i];
+  s = block_reduce_sum(s, red);
+  if (threadIdx.x == 0) mean_sh = s / ((double)Nx * Ny * Nz);
+  __syncthreads();
+  tile_contract<false, true>(P, W, Nx, Nx, Nz, Sz);
+  const double mean = mean_sh;
+  for (int i = threadIdx.x; i < Nx * Nz; i += blockDim.x) {
+    const int x = i % Nx, o = i / Nx;
+    const double v = P[i] - mean * c.colsum[2][o] * c.colsum[1][y] * c.colsum[0][x];
+    const bool zero = (x == c.zero[0] && y == c.zero[1] && o == c.zero[2]);
+    P[i] = zero ? 0.0 : v / (c.lam[0][x] + c.lam[1][y] + c.lam[2][o]);
+  }
+  __syncthreads();
+  tile_contract<false, false>(P, W, Nx, Nx, Nz, Sz);
+  for (int i = threadIdx.x; i < Nx * Nz; i += blockDim.x) {
+    const int x = i % Nx, z = i / Nx;
+    t[((size_t)z * Ny + y) * Nx + x] = P[i];
+  }
+}
+
+// 3. one workgroup per z plane: y and x backward into the element-major u_0;
+//    the plane sum of u_0 -> partial_u[z]
+__global__ void __launch_bounds__(256)
+coarse_plane_xy_bwd(Dims d, CoarseLaunch c, const double *__restrict__ t, double *__restrict__ u0, bool tabs_lds) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  const int Nx = d.N[0], Ny = d.N[1];
+  double *P = reinterpret_cast<double *>(smem_raw);
+  double *W = P + Nx * Ny;
+  const double *Sx = c.S[0], *Sy = c.S[1];
+  if (tabs_lds) {
+    double *sx = W + Nx * Ny, *sy = sx + Nx * Nx;
+    for (int i = threadIdx.x; i < Nx * Nx; i += blockDim.x) sx[i] = c.S[0][i];
+    for (int i = threadIdx.x; i < Ny * Ny; i += blockDim.x) sy[i] = c.S[1][i];
+    Sx = sx;
+    Sy = sy;
+  }
+  const int z = blockIdx.x;
+  const double *tz = t + (size_t)z * Nx * Ny;
+  for (int i = threadIdx.x; i < Nx * Ny; i += blockDim.x) P[i] = tz[i];
+  __syncthreads();
+  tile_contract<false, false>(P, W, Nx, Nx, Ny, Sy);
+  tile_contract<true, false>(P, W, Nx, Ny, Nx, Sx);
+  double s = 0.0;
+  for (int i = threadIdx.x; i < Nx * Ny; i += blockDim.x) {
+    const int x = i % Nx, y = i / Nx;
+    u0[elem_major_p1(d, x, y, z)] = P[i];
+    s += P[i];
+  }
+  s = block_reduce_sum(s, red);
+  if (threadIdx.x == 0) c.partial_u[z] = s;
+}
+
+// LDS bytes of the plane kernels: two planes, plus the 1D tables when they fit
+constexpr size_t kCoarseLds = 150 * 1024;
+size_t plane_bytes(const Dims &d, int a, int b) { return 2 * (size_t)d.N[a] * d.N[b] * sizeof(double); }
+size_t tab_bytes(const Dims &d, int a, int b) {
+  return ((size_t)d.N[a] * d.N[a] + (a == b ? 0 : (size_t)d.N[b] * d.N[b])) * sizeof(double);
 }
 
 }  // namespace
 
+int coarse_num_partials(const CoarseLaunch &c) { return c.N[2]; }
+
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t shm) {
+  if (shm <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+}
+
 template <typename TI>
-hipError_t launch_coarse(const CoarseLaunch &c, const TI *f0, double *u0, bool subtract_mean,
-                         hipStream_t st) {
+hipError_t launch_coarse(const CoarseLaunch &c, const TI *f0, double *u0, bool subtract_mean, hipStream_t st) {
   Dims d;
   for (int i = 0; i < 3; ++i) {
     d.N[i] = c.N[i];
     d.ne[i] = c.ne[i];
   }
   const int64_t N0 = (int64_t)d.N[0] * d.N[1] * d.N[2];
-  const int nb = (int)((N0 + 255) / 256);
+  size_t sxy = plane_bytes(d, 0, 1), sz = plane_bytes(d, 0, 2);
+  if (sxy > kCoarseLds || sz > kCoarseLds) return hipErrorInvalidValue;
+  const bool lds_xy = sxy + tab_bytes(d, 0, 1) <= kCoarseLds;
+  const bool lds_z = sz + tab_bytes(d, 2, 2) <= kCoarseLds;
+  if (lds_xy) sxy += tab_bytes(d, 0, 1);
+  if (lds_z) sz += tab_bytes(d, 2, 2);
   hipError_t e;
-  sum_partials<TI><<<kCoarsePartials, 256, 0, st>>>(f0, N0, c.partial);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = launch_finalize(c.partial, kCoarsePartials, 1.0 / (double)N0, c.scalars + 0, st)) != hipSuccess)
-    return e;
-  coarse_axis<TI, 0, true, true, false><<<nb, 256, 0, st>>>(d, c.S[0], f0, c.t0);
-  coarse_axis<double, 1, true, false, false><<<nb, 256, 0, st>>>(d, c.S[1], c.t0, c.t1);
-  coarse_z_scale<<<nb, 256, 0, st>>>(d, c, c.t1, c.t0);
-  coarse_axis<double, 2, false, false, false><<<nb, 256, 0, st>>>(d, c.S[2], c.t0, c.t1);
-  coarse_axis<double, 1, false, false, false><<<nb, 256, 0, st>>>(d, c.S[1], c.t1, c.t0);
-  coarse_axis<double, 0, false, false, true><<<nb, 256, 0, st>>>(d, c.S[0], c.t0, u0);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  sum_partials<double><<<kCoarsePartials, 256, 0, st>>>(u0, N0, c.partial);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = launch_finalize(c.partial, kCoarsePartials, 1.0 / (double)N0, c.scalars + 1, st)) != hipSuccess)
-    return e;
-  if (subtract_mean) return launch_sub_scalar<double>(u0, N0, c.scalars + 1, st);
-  return hipSuccess;
+  if ((e = allow_lds(coarse_plane_xy_fwd<TI>, sxy)) != hipSuccess) return e;
+  if ((e = allow_lds(coarse_plane_z, sz)) != hipSuccess) return e;
+  if ((e = allow_lds(coarse_plane_xy_bwd, sxy)) != hipSuccess) return e;
+  coarse_plane_xy_fwd<TI><<<d.N[2], 256, sxy, st>>>(d, c, f0, c.t0, lds_xy);
+  coarse_plane_z<<<d.N[1], 256, sz, st>>>(d, c, c.t0, lds_z);
+  coarse_plane_xy_bwd<<<d.N[2], 256, sxy, st>>>(d, c, c.t0, u0, lds_xy);
+  e = hipGetLastError();
+  if (e != hipSuccess || !subtract_mean) return e;
+  if ((e = launch_finalize(c.partial_u, d.N[2], 1.0 / (double)N0, c.scalars + 1, st)) != hipSuccess) return e;
+  return launch_sub_scalar<double>(u0, N0, c.scalars + 1, st);
 }
 
 template hipError_t launch_coarse<double>(const CoarseLaunch &, const double *, double *, bool, hipStream_t);

@@ -266,52 +266,74 @@ __device__ __forceinline__ void bwd_inner(T *base, int st, const T *__restrict__
   }
 }
 
+// spb: subdomains per workgroup (at most Sh::SPB).
 template <typename T, int N, int MX, int MY, int MZ>
 __global__ void __launch_bounds__((FdmShape<MX, MY, MZ>::NTH))
 schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ ilam, const T *__restrict__ r,
-                  T *__restrict__ C) {
+                  T *__restrict__ C, int spb) {
   using Sh = FdmShape<MX, MY, MZ>;
   constexpr int RX = Sh::RX, VOL = Sh::VOL, TILE = Sh::TILE, SPB = Sh::SPB;
   constexpr int NOX = (MX - N) / 2, NOY = (MY - N) / 2, NOZ = (MZ - N) / 2;
   constexpr int N3 = N * N * N;
   __shared__ T t[SPB * TILE];
+  __shared__ int nb[SPB * 27];  // the 27 elements around each subdomain's core
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int s0 = blk * SPB;
-  const int nsub = min(SPB, g.E - s0);
+  const int s0 = blk * spb;
+  const int nsub = min(spb, g.E - s0);
   const int tid = threadIdx.x;
-  constexpr int NTH = Sh::NTH;
 
-  // gather R_s r for the SPB subdomains
-  for (int idx = tid; idx < nsub * VOL; idx += NTH) {
-    const int q = idx / VOL, rem = idx - q * VOL;
-    const int a = rem % MX, bc = rem / MX, b = bc % MY, c = bc / MY;
+  for (int i = tid; i < nsub * 27; i += blockDim.x) {
+    const int q = i / 27, k = i - q * 27;
     const int s = s0 + q;
     const int ex = s % g.ne[0], rest = s / g.ne[0];
     const int ey = rest % g.ne[1], ez = rest / g.ne[1];
-    const int gx = a - NOX, gy = b - NOY, gz = c - NOZ;
-    const int dx = gx < 0 ? -1 : (gx >= N ? 1 : 0);
-    const int dy = gy < 0 ? -1 : (gy >= N ? 1 : 0);
-    const int dz = gz < 0 ? -1 : (gz >= N ? 1 : 0);
-    const int e = elem_index(g, wrap(ex + dx, g.ne[0]), wrap(ey + dy, g.ne[1]), wrap(ez + dz, g.ne[2]));
-    t[q * TILE + bc * RX + a] = r[(size_t)e * N3 + ((gz - dz * N) * N + (gy - dy * N)) * N + (gx - dx * N)];
+    nb[i] = elem_index(g, wrap(ex + k % 3 - 1, g.ne[0]), wrap(ey + (k / 3) % 3 - 1, g.ne[1]),
+                       wrap(ez + k / 9 - 1, g.ne[2]));
   }
   __syncthreads();
-  // x forward: lines (q, c, b)
-  for (int L = tid; L < nsub * Sh::L1; L += NTH) {
-    const int q = L / Sh::L1, cb = L - q * Sh::L1;
-    fwd_outer<T, MX>(t + q * TILE + cb * RX, 1, tb.S[0]);
+  // x forward: thread per row (q, c, b); the row of R_s r is three contiguous
+  // runs in the left neighbour, the core element and the right neighbour
+  if (tid < nsub * Sh::L1) {
+    const int q = tid / Sh::L1, cb = tid - q * Sh::L1;
+    const int b = cb % MY, c = cb / MY;
+    const int gy = b - NOY, gz = c - NOZ;
+    const int dy = gy < 0 ? -1 : (gy >= N ? 1 : 0), dz = gz < 0 ? -1 : (gz >= N ? 1 : 0);
+    const int j = gy - dy * N, k = gz - dz * N;
+    const int *nbq = nb + q * 27 + (dz + 1) * 9 + (dy + 1) * 3;
+    const int row = (k * N + j) * N;
+    const T *rl = r + (size_t)nbq[0] * N3 + row + (N - NOX);
+    const T *r0 = r + (size_t)nbq[1] * N3 + row;
+    const T *rr = r + (size_t)nbq[2] * N3 + row;
+    T v[MX];
+#pragma unroll
+    for (int a = 0; a < NOX; ++a) v[a] = rl[a];
+#pragma unroll
+    for (int a = 0; a < N; ++a) v[NOX + a] = r0[a];
+#pragma unroll
+    for (int a = 0; a < NOX; ++a) v[NOX + N + a] = rr[a];
+    const T *__restrict__ S = tb.S[0];
+    T acc[MX];
+#pragma unroll
+    for (int o = 0; o < MX; ++o) acc[o] = 0;
+#pragma unroll
+    for (int a = 0; a < MX; ++a)
+#pragma unroll
+      for (int o = 0; o < MX; ++o) acc[o] += S[a * MX + o] * v[a];
+    T *base = t + q * TILE + cb * RX;
+#pragma unroll
+    for (int o = 0; o < MX; ++o) base[o] = acc[o];
   }
   __syncthreads();
   // y forward: lines (q, c, a)
-  for (int L = tid; L < nsub * Sh::L2; L += NTH) {
-    const int q = L / Sh::L2, ca = L - q * Sh::L2;
+  if (tid < nsub * Sh::L2) {
+    const int q = tid / Sh::L2, ca = tid - q * Sh::L2;
     const int c = ca / MX, a = ca - c * MX;
     fwd_outer<T, MY>(t + q * TILE + c * MY * RX + a, RX, tb.S[1]);
   }
   __syncthreads();
   // z forward, scaling, z backward: lines (q, b, a)
-  for (int L = tid; L < nsub * Sh::L3; L += NTH) {
-    const int q = L / Sh::L3, ba = L - q * Sh::L3;
+  if (tid < nsub * Sh::L3) {
+    const int q = tid / Sh::L3, ba = tid - q * Sh::L3;
     const int b = ba / MX, a = ba - b * MX;
     T *base = t + q * TILE + b * RX + a;
     constexpr int st = MY * RX;
@@ -326,8 +348,9 @@ schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ ilam, const T
 #pragma unroll
       for (int o = 0; o < MZ; ++o) acc[o] += Sz[c * MZ + o] * v;
     }
+    const T *il = ilam + b * MX + a;
 #pragma unroll
-    for (int o = 0; o < MZ; ++o) acc[o] *= ilam[(o * MY + b) * MX + a];
+    for (int o = 0; o < MZ; ++o) acc[o] *= il[o * MY * MX];
 #pragma unroll
     for (int c = 0; c < MZ; ++c) {
       T s = 0;
@@ -338,23 +361,28 @@ schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ ilam, const T
   }
   __syncthreads();
   // y backward
-  for (int L = tid; L < nsub * Sh::L2; L += NTH) {
-    const int q = L / Sh::L2, ca = L - q * Sh::L2;
+  if (tid < nsub * Sh::L2) {
+    const int q = tid / Sh::L2, ca = tid - q * Sh::L2;
     const int c = ca / MX, a = ca - c * MX;
     bwd_inner<T, MY>(t + q * TILE + c * MY * RX + a, RX, tb.WS[1]);
   }
   __syncthreads();
-  // x backward
-  for (int L = tid; L < nsub * Sh::L1; L += NTH) {
-    const int q = L / Sh::L1, cb = L - q * Sh::L1;
-    bwd_inner<T, MX>(t + q * TILE + cb * RX, 1, tb.WS[0]);
-  }
-  __syncthreads();
-  T *Cs = C + (size_t)s0 * VOL;
-  for (int idx = tid; idx < nsub * VOL; idx += NTH) {
-    const int q = idx / VOL, rem = idx - q * VOL;
-    const int a = rem % MX, bc = rem / MX;
-    Cs[idx] = t[q * TILE + bc * RX + a];
+  // x backward, written straight to the correction buffer: rows (q, c, b)
+  if (tid < nsub * Sh::L1) {
+    const int q = tid / Sh::L1, cb = tid - q * Sh::L1;
+    const T *base = t + q * TILE + cb * RX;
+    T v[MX];
+#pragma unroll
+    for (int o = 0; o < MX; ++o) v[o] = base[o];
+    const T *__restrict__ WS = tb.WS[0];
+    T *out = C + (size_t)(s0 + q) * VOL + cb * MX;
+#pragma unroll
+    for (int a = 0; a < MX; ++a) {
+      T acc = 0;
+#pragma unroll
+      for (int o = 0; o < MX; ++o) acc += WS[a * MX + o] * v[o];
+      out[a] = acc;
+    }
   }
 }
 
@@ -406,8 +434,10 @@ template <typename T, int N, int MX, int MY, int MZ>
 hipError_t launch_fixed(const SchwarzLaunch<T> &a, hipStream_t st) {
   using Sh = FdmShape<MX, MY, MZ>;
   static_assert(Sh::SPB * Sh::TILE * sizeof(T) <= 160 * 1024, "subdomain tile exceeds LDS");
-  const int nblk = (a.mesh.E + Sh::SPB - 1) / Sh::SPB;
-  schwarz_fdm_fixed<T, N, MX, MY, MZ><<<nblk, Sh::NTH, 0, st>>>(a.mesh, a.tabs, a.ilam, a.r, a.C);
+  const int spb = Sh::SPB;
+  const int nblk = (a.mesh.E + spb - 1) / spb;
+  const int nth = std::min(Sh::NTH, (spb * Sh::LINES + 63) / 64 * 64);
+  schwarz_fdm_fixed<T, N, MX, MY, MZ><<<nblk, nth, 0, st>>>(a.mesh, a.tabs, a.ilam, a.r, a.C, spb);
   return hipGetLastError();
 }
 

@@ -105,7 +105,8 @@ struct sipg_ctx {
     void *p = nullptr;
     if (count == 0) count = 1;
     hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) throw std::bad_alloc();
+    if (e == hipErrorOutOfMemory) throw std::bad_alloc();
+    check(e, "hipMalloc");
     allocs.push_back(p);
     bytes += count * sizeof(T);
     return static_cast<T *>(p);
@@ -331,10 +332,15 @@ void op_schwarz(sipg_ctx *c, int l, const T *r, const T *u_in, T *u_out) {
   check(sipg::launch_schwarz<T>(a, c->stream), "schwarz");
 }
 
+// u_l += I_l u_{l-1}; with_mean: u_{l-1} is the level-0 solution whose
+// Euclidean mean (from the coarse solve's row sums) is removed on the fly
 template <typename T, typename TC>
-void op_prolong(sipg_ctx *c, int l, const TC *uc, const double *mean, T *uf) {
+void op_prolong(sipg_ctx *c, int l, const TC *uc, bool with_mean, T *uf) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
-  sipg::ProlongLaunch<T, TC> a{c->mesh.E, t.n, t.nc, t.J, uc, mean, uf};
+  const int64_t N0 = level_ndof(c->H, 0);
+  sipg::ProlongLaunch<T, TC> a{c->mesh.E, t.n, t.nc, t.J, uc,
+                               with_mean ? c->coarse.partial_u : nullptr,
+                               sipg::coarse_num_partials(c->coarse), 1.0 / (double)N0, uf};
   if (sipg::apply_is_large(t.n)) {
     ensure_work<T>(c);
     check(sipg::launch_prolong_large<T, TC>(a, work_of<T>(c).big, c->stream), "prolong");
@@ -391,8 +397,8 @@ void vcycle_impl(sipg_ctx *c, T *uL, const T *fL, bool zero_start, const T *r_to
   for (int l = 1; l <= L; ++l) {
     T *ul = (l == L) ? uL : w.u[l];
     const T *fl = (l == L) ? fL : w.f[l];
-    if (l == 1) op_prolong<T, double>(c, 1, c->u0, c->coarse.scalars + 1, ul);
-    else op_prolong<T, T>(c, l, w.u[l - 1], nullptr, ul);
+    if (l == 1) op_prolong<T, double>(c, 1, c->u0, true, ul);
+    else op_prolong<T, T>(c, l, w.u[l - 1], false, ul);
     const int ns = nsteps(H.prm.nsmooth_post, l);
     for (int s = 0; s < ns; ++s) {
       op_residual<T>(c, l, ul, fl, w.r);
@@ -473,25 +479,53 @@ void dot(sipg_ctx *c, const double *x, const double *y, int64_t n, int slot) {
   check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + slot, c->stream), "dot");
 }
 
+// MG solve.  When the convergence rate observed so far predicts that the
+// current iterate cannot have converged yet, the next V-cycle is enqueued
+// before the host reads the residual norm, so the device does not wait for the
+// host; x is backed up first and restored if the prediction was wrong (the
+// result is the same as checking first).
 int mg_solve_impl(sipg_ctx *c, double *u, const double *f, double rtol, int maxcyc, int *ncyc,
                   double *relres) {
   const int64_t N = level_ndof(c->H, c->L);
   ensure_work<double>(c);
+  double *bak = c->w64.uL;  // free during FP64 V-cycles
   c->hist.clear();
   double r0 = -1.0;
+  hipEvent_t ev = nullptr;
+  check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+  struct EvGuard {
+    hipEvent_t e;
+    ~EvGuard() { (void)hipEventDestroy(e); }
+  } guard{ev};
+  bool spec = false;
   for (int cyc = 0;; ++cyc) {
     residual_norm2(c, u, f, c->cg_r, sipg::FS_RR);
-    read_scalars(c);
+    check(hipMemcpyAsync(c->host_scal, c->scal, sipg::FS_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                         c->stream),
+          "scalar readback");
+    check(hipEventRecord(ev, c->stream), "event");
+    spec = spec && cyc < maxcyc;
+    if (spec) {
+      check(sipg::launch_convert<double, double>(u, bak, N, c->stream), "backup");
+      vcycle_impl<double>(c, u, f, false, c->cg_r);
+    }
+    check(hipEventSynchronize(ev), "residual norm");
     const double rn = std::sqrt(c->host_scal[sipg::FS_RR]);
     c->hist.push_back(rn);
-    if (!std::isfinite(rn)) return fail(SIPG_ENOTFINITE, "residual norm is not finite");
     if (r0 < 0) r0 = rn;
-    const double rel = r0 > 0 ? rn / r0 : 0.0;
     if (ncyc) *ncyc = cyc;
-    if (relres) *relres = rel;
-    if (rn <= rtol * r0) return SIPG_OK;
-    if (cyc >= maxcyc) return fail(SIPG_ENOCONV, "mg_solve: tolerance not reached");
-    vcycle_impl<double>(c, u, f, false, c->cg_r);
+    if (relres) *relres = r0 > 0 ? rn / r0 : 0.0;
+    if (!std::isfinite(rn) || rn <= rtol * r0 || cyc >= maxcyc) {
+      if (spec) check(sipg::launch_convert<double, double>(bak, u, N, c->stream), "restore");
+      check(hipStreamSynchronize(c->stream), "mg_solve");
+      if (!std::isfinite(rn)) return fail(SIPG_ENOTFINITE, "residual norm is not finite");
+      if (rn <= rtol * r0) return SIPG_OK;
+      return fail(SIPG_ENOCONV, "mg_solve: tolerance not reached");
+    }
+    if (!spec) vcycle_impl<double>(c, u, f, false, c->cg_r);
+    // speculate on the next check if the observed rate says it cannot pass
+    const size_t h = c->hist.size();
+    spec = h >= 2 && c->hist[h - 2] > 0 && rn * (rn / c->hist[h - 2]) > 10.0 * rtol * r0;
   }
 }
 
@@ -675,8 +709,8 @@ int sipg_setup(const sipg_params *p, void *hip_stream, sipg_ctx **out) {
     const int64_t N0 = level_ndof(c->H, 0), N = level_ndof(c->H, c->L);
     c->u0 = c->alloc<double>(N0);
     c->coarse.t0 = c->alloc<double>(N0);
-    c->coarse.t1 = c->alloc<double>(N0);
-    c->coarse.partial = c->alloc<double>(sipg::kCoarsePartials);
+    c->coarse.partial = c->alloc<double>(sipg::coarse_num_partials(c->coarse));
+    c->coarse.partial_u = c->alloc<double>(sipg::coarse_num_partials(c->coarse));
     c->coarse.scalars = c->alloc<double>(4);
     c->cg_r = c->alloc<double>(N);
     c->cg_p = c->alloc<double>(N);
@@ -836,7 +870,7 @@ int sipg_prolong_add(sipg_ctx *c, int level, const double *u_coarse, double *u_f
   const int l = resolve_level(c, level);
   if (l < 1) return fail(SIPG_EINVAL, "prolongation needs level >= 1");
   return guarded([&]() {
-    op_prolong<double, double>(c, l, u_coarse, nullptr, u_fine);
+    op_prolong<double, double>(c, l, u_coarse, false, u_fine);
     return (int)SIPG_OK;
   });
 }
@@ -915,8 +949,8 @@ int sipg_time_kernel(sipg_ctx *c, int kernel, int level, int bits, int reps, dou
           case SIPG_KERNEL_SCHWARZ_ASSEMBLE: check(sipg::launch_schwarz_assemble<T>(sa, c->stream), "assemble"); break;
           case SIPG_KERNEL_RESTRICT: op_residual_restrict<T>(c, l, u, f, w.f[l - 1]); break;
           case SIPG_KERNEL_PROLONG:
-            if (l == 1) op_prolong<T, double>(c, 1, c->u0, nullptr, u);
-            else op_prolong<T, T>(c, l, w.u[l - 1], nullptr, u);
+            if (l == 1) op_prolong<T, double>(c, 1, c->u0, false, u);
+            else op_prolong<T, T>(c, l, w.u[l - 1], false, u);
             break;
         }
       }

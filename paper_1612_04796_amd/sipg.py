@@ -64,6 +64,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built ({LIB_PATH}); run "
                                "python -m paper_1612_04796_amd.build")
+        # The library receives torch's device pointers and streams, so it must
+        # bind to the HIP runtime torch has loaded: load torch first, and the
+        # library's libamdhip64 dependency resolves to that same runtime
+        # instead of bringing a second one into the process.
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(LIB_PATH)
         P, c_int, c_double, vp = ctypes.POINTER, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
         sig = {

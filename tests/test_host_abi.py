@@ -112,6 +112,7 @@ BAD = [
     dict(overlap="rel", omega=1.5),     # overlap wider than the neighbour
     dict(nsmooth_pre=0, nsmooth_post=0),
     dict(precond_bits=16),
+    dict(ne=(50, 49, 4)),               # level-0 planes exceed the coarse solve's LDS
     dict(ne=(3, 3, 3), length=(16.0, 1.0, 1.0), overlap="max", omega=0.08, P=4),  # whole-neighbour overlap needs ne >= 4
 ]
 
@@ -144,3 +145,11 @@ def test_workload_generator_is_seeded():
     s2 = serving_stream(1, 20, 5.0)
     assert s1 == s2
     assert all(4 <= r["ne"][0] <= 24 and r["P"] in (2, 4, 8, 16, 32) for r in s1)
+
+
+def test_single_hip_runtime_in_process():
+    """The library shares torch's HIP runtime (one libamdhip64 mapped)."""
+    sipg.lib()
+    with open("/proc/self/maps") as f:
+        runtimes = {line.split()[-1] for line in f if "libamdhip64" in line}
+    assert len(runtimes) == 1, runtimes
