@@ -104,6 +104,20 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
   const int le = t / N2, pq = t - le * N2;
   const int p = pq / N, q = pq - p * N;  // x line (k=p, j=q); y line (k=p, i=q); z line (j=p, i=q)
 
+  // All global loads of the prologue are issued before any is consumed: the
+  // element's own values (N per thread suffice, as blockDim.x >= nloc N^2),
+  // the load vector of the z line, then the face lines.
+  T st[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const int idx = t + j * (int)blockDim.x;
+    st[j] = idx < nloc * N3 ? u[(size_t)e0 * N3 + idx] : (T)0;
+  }
+  T fl[N];
+  if (MODE != MODE_APPLY && active) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) fl[k] = f[(size_t)(e0 + le) * N3 + pq + k * N2];
+  }
   FaceData<T> fx{}, fy{}, fz{};
   if (active) {
     const int e = e0 + le;
@@ -119,7 +133,11 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
     fy = face_data<T, N>(uyr, uyl, N, tb.DL[1], tb.DR[1]);
     fz = face_data<T, N>(uzr, uzl, N2, tb.DL[2], tb.DR[2]);
   }
-  for (int idx = t; idx < nloc * N3; idx += blockDim.x) su[idx] = u[(size_t)e0 * N3 + idx];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const int idx = t + j * (int)blockDim.x;
+    if (idx < nloc * N3) su[idx] = st[j];
+  }
   __syncthreads();
 
   if (active) {  // x: line (k=p, j=q), contiguous
@@ -160,11 +178,11 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
         out[gbase + k * N2] = y;
         if (DOT) dot += v[k] * y;
       } else if (MODE == MODE_RESID) {
-        const T r = f[gbase + k * N2] - y;
+        const T r = fl[k] - y;
         out[gbase + k * N2] = r;
         if (DOT) dot += r * r;
       } else {
-        yl[k * N2] = f[gbase + k * N2] - y;
+        yl[k * N2] = fl[k] - y;
       }
     }
   }

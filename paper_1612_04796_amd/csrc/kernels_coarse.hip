@@ -18,6 +18,8 @@
 // V-cycle, by the prolongation, which reduces the plane sums itself.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -35,71 +37,90 @@ __device__ __forceinline__ int64_t elem_major_p1(const Dims &d, int gx, int gy, 
   return (int64_t)e * 8 + ((gz & 1) * 2 + (gy & 1)) * 2 + (gx & 1);
 }
 
-// In-place contraction of the lines of a 2D tile in LDS along one of its two
-// axes, one thread per output entry, all inputs read before any output is
-// written (two barriers).  The tile is P[r * pitch + q]; ALONG_ROWS contracts
-// over q (rows of length n, `count` rows), else over r (columns of length n).
+// In-place contraction of a 2D tile P[r * pitch + q] in LDS along one of its
+// axes, with a 2D workgroup (blockDim.x >= pitch, so threadIdx.x is the q
+// index).  ALONG_Q contracts the rows (over q, n = pitch), else the columns
+// (over r, n = number of rows).  All inputs are read before any output is
+// written (two barriers).
 //   FWD: out[o] = sum_a A[a*n + o] in[a];  else out[o] = sum_a A[o*n + a] in[a]
-template <bool ALONG_ROWS, bool FWD>
-__device__ void tile_contract(double *P, double *W, int pitch, int count, int n, const double *A) {
-  const int tot = count * n;
-  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-    const int line = i / n, o = i - line * n;
-    double acc = 0.0;
-    for (int a = 0; a < n; ++a) {
-      const double x = ALONG_ROWS ? P[line * pitch + a] : P[a * pitch + line];
-      acc += (FWD ? A[a * n + o] : A[o * n + a]) * x;
+template <bool ALONG_Q, bool FWD>
+__device__ void tile_contract(double *P, double *W, int pitch, int rows, const double *A) {
+  const int q = threadIdx.x;
+  const int n = ALONG_Q ? pitch : rows;
+  if (q < pitch) {
+    for (int r = threadIdx.y; r < rows; r += blockDim.y) {
+      // ALONG_Q: output (r, o = q) from row r; else output (o = r, q) from column q
+      const int o = ALONG_Q ? q : r;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int a = 0; a < n; ++a) {
+        const double x = ALONG_Q ? P[r * pitch + a] : P[a * pitch + q];
+        acc += (FWD ? A[a * n + o] : A[o * n + a]) * x;
+      }
+      W[r * pitch + q] = acc;
     }
-    W[i] = acc;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-    const int line = i / n, o = i - line * n;
-    if (ALONG_ROWS) P[line * pitch + o] = W[i];
-    else P[o * pitch + line] = W[i];
-  }
+  if (q < pitch)
+    for (int r = threadIdx.y; r < rows; r += blockDim.y) P[r * pitch + q] = W[r * pitch + q];
   __syncthreads();
 }
 
-// 1. one workgroup per z plane: the (y, x) plane of f_0 and Sx, Sy in LDS;
+__device__ __forceinline__ int flat_tid() { return threadIdx.y * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ int flat_nth() { return blockDim.x * blockDim.y; }
+
+// block_reduce_sum over a 2D workgroup (flat thread order)
+__device__ double block_sum_2d(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  const int t = flat_tid(), w = t >> 6, nw = (flat_nth() + 63) >> 6;
+  if ((t & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (t == 0)
+    for (int i = 0; i < nw; ++i) s += red[i];
+  return s;  // valid in thread 0
+}
+
+// 1. one workgroup per z plane: the (y, x) plane of f_0 (and Sx, Sy) in LDS;
 //    x and y forward; the plane sum of f_0 -> partial[z]
-template <typename TI>
-__global__ void __launch_bounds__(256)
-coarse_plane_xy_fwd(Dims d, CoarseLaunch c, const TI *__restrict__ f0, double *__restrict__ t, bool tabs_lds) {
+template <typename TI, bool TL>
+__global__ void __launch_bounds__(1024)
+coarse_plane_xy_fwd(Dims d, CoarseLaunch c, const TI *__restrict__ f0, double *__restrict__ t) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   const int Nx = d.N[0], Ny = d.N[1];
   double *P = reinterpret_cast<double *>(smem_raw);
   double *W = P + Nx * Ny;
   const double *Sx = c.S[0], *Sy = c.S[1];
-  if (tabs_lds) {
+  const int tid = flat_tid(), nth = flat_nth();
+  if (TL) {
     double *sx = W + Nx * Ny, *sy = sx + Nx * Nx;
-    for (int i = threadIdx.x; i < Nx * Nx; i += blockDim.x) sx[i] = c.S[0][i];
-    for (int i = threadIdx.x; i < Ny * Ny; i += blockDim.x) sy[i] = c.S[1][i];
+    for (int i = tid; i < Nx * Nx; i += nth) sx[i] = c.S[0][i];
+    for (int i = tid; i < Ny * Ny; i += nth) sy[i] = c.S[1][i];
     Sx = sx;
     Sy = sy;
   }
   const int z = blockIdx.x;
   double s = 0.0;
-  for (int i = threadIdx.x; i < Nx * Ny; i += blockDim.x) {
-    const int x = i % Nx, y = i / Nx;
-    const double v = (double)f0[elem_major_p1(d, x, y, z)];
-    P[i] = v;
-    s += v;
-  }
-  s = block_reduce_sum(s, red);
-  if (threadIdx.x == 0) c.partial[z] = s;
+  if (threadIdx.x < Nx)
+    for (int y = threadIdx.y; y < Ny; y += blockDim.y) {
+      const double v = (double)f0[elem_major_p1(d, threadIdx.x, y, z)];
+      P[y * Nx + threadIdx.x] = v;
+      s += v;
+    }
+  s = block_sum_2d(s, red);
+  if (tid == 0) c.partial[z] = s;
   __syncthreads();
-  tile_contract<true, true>(P, W, Nx, Ny, Nx, Sx);
-  tile_contract<false, true>(P, W, Nx, Nx, Ny, Sy);
+  tile_contract<true, true>(P, W, Nx, Ny, Sx);
+  tile_contract<false, true>(P, W, Nx, Ny, Sy);
   double *tz = t + (size_t)z * Nx * Ny;
-  for (int i = threadIdx.x; i < Nx * Ny; i += blockDim.x) tz[i] = P[i];
+  for (int i = tid; i < Nx * Ny; i += nth) tz[i] = P[i];
 }
 
-// 2. one workgroup per y plane: the (z, x) plane and Sz in LDS; z forward,
+// 2. one workgroup per y plane: the (z, x) plane (and Sz) in LDS; z forward,
 //    mean correction (mean from the plane sums), Lambda^+, z backward
-__global__ void __launch_bounds__(256)
-coarse_plane_z(Dims d, CoarseLaunch c, double *__restrict__ t, bool tabs_lds) {
+template <bool TL>
+__global__ void __launch_bounds__(1024) coarse_plane_z(Dims d, CoarseLaunch c, double *__restrict__ t) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   __shared__ double mean_sh;
@@ -107,68 +128,73 @@ coarse_plane_z(Dims d, CoarseLaunch c, double *__restrict__ t, bool tabs_lds) {
   double *P = reinterpret_cast<double *>(smem_raw);
   double *W = P + Nx * Nz;
   const double *Sz = c.S[2];
-  if (tabs_lds) {
+  const int tid = flat_tid(), nth = flat_nth();
+  if (TL) {
     double *sz = W + Nx * Nz;
-    for (int i = threadIdx.x; i < Nz * Nz; i += blockDim.x) sz[i] = c.S[2][i];
+    for (int i = tid; i < Nz * Nz; i += nth) sz[i] = c.S[2][i];
     Sz = sz;
   }
   const int y = blockIdx.x;
-  for (int i = threadIdx.x; i < Nx * Nz; i += blockDim.x) {
-    const int x = i % Nx, z = i / Nx;
-    P[i] = t[((size_t)z * Ny + y) * Nx + x];
-  }
+  if (threadIdx.x < Nx)
+    for (int z = threadIdx.y; z < Nz; z += blockDim.y) P[z * Nx + threadIdx.x] = t[((size_t)z * Ny + y) * Nx + threadIdx.x];
   double s = 0.0;
-  for (int i = threadIdx.x; i < Nz; i += blockDim.x) s += c.partial[i];
-  s = block_reduce_sum(s, red);
-  if (threadIdx.x == 0) mean_sh = s / ((double)Nx * Ny * Nz);
+  for (int i = tid; i < Nz; i += nth) s += c.partial[i];
+  s = block_sum_2d(s, red);
+  if (tid == 0) mean_sh = s / ((double)Nx * Ny * Nz);
   __syncthreads();
-  tile_contract<false, true>(P, W, Nx, Nx, Nz, Sz);
+  tile_contract<false, true>(P, W, Nx, Nz, Sz);
   const double mean = mean_sh;
-  for (int i = threadIdx.x; i < Nx * Nz; i += blockDim.x) {
-    const int x = i % Nx, o = i / Nx;
-    const double v = P[i] - mean * c.colsum[2][o] * c.colsum[1][y] * c.colsum[0][x];
-    const bool zero = (x == c.zero[0] && y == c.zero[1] && o == c.zero[2]);
-    P[i] = zero ? 0.0 : v / (c.lam[0][x] + c.lam[1][y] + c.lam[2][o]);
+  if (threadIdx.x < Nx) {
+    const int x = threadIdx.x;
+    for (int o = threadIdx.y; o < Nz; o += blockDim.y) {
+      const double v = P[o * Nx + x] - mean * c.colsum[2][o] * c.colsum[1][y] * c.colsum[0][x];
+      const bool zero = (x == c.zero[0] && y == c.zero[1] && o == c.zero[2]);
+      P[o * Nx + x] = zero ? 0.0 : v / (c.lam[0][x] + c.lam[1][y] + c.lam[2][o]);
+    }
   }
   __syncthreads();
-  tile_contract<false, false>(P, W, Nx, Nx, Nz, Sz);
-  for (int i = threadIdx.x; i < Nx * Nz; i += blockDim.x) {
-    const int x = i % Nx, z = i / Nx;
-    t[((size_t)z * Ny + y) * Nx + x] = P[i];
-  }
+  tile_contract<false, false>(P, W, Nx, Nz, Sz);
+  if (threadIdx.x < Nx)
+    for (int z = threadIdx.y; z < Nz; z += blockDim.y) t[((size_t)z * Ny + y) * Nx + threadIdx.x] = P[z * Nx + threadIdx.x];
 }
 
 // 3. one workgroup per z plane: y and x backward into the element-major u_0;
 //    the plane sum of u_0 -> partial_u[z]
-__global__ void __launch_bounds__(256)
-coarse_plane_xy_bwd(Dims d, CoarseLaunch c, const double *__restrict__ t, double *__restrict__ u0, bool tabs_lds) {
+template <bool TL>
+__global__ void __launch_bounds__(1024)
+coarse_plane_xy_bwd(Dims d, CoarseLaunch c, const double *__restrict__ t, double *__restrict__ u0) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   const int Nx = d.N[0], Ny = d.N[1];
   double *P = reinterpret_cast<double *>(smem_raw);
   double *W = P + Nx * Ny;
   const double *Sx = c.S[0], *Sy = c.S[1];
-  if (tabs_lds) {
-    double *sx = W + Nx * Ny, *sy = sx + Nx * Nx;
-    for (int i = threadIdx.x; i < Nx * Nx; i += blockDim.x) sx[i] = c.S[0][i];
-    for (int i = threadIdx.x; i < Ny * Ny; i += blockDim.x) sy[i] = c.S[1][i];
-    Sx = sx;
+  const int tid = flat_tid(), nth = flat_nth();
+  if (TL) {
+    // Sx is stored transposed so that the x backward reads it along
+    // consecutive addresses (no LDS bank conflicts)
+    double *sxt = W + Nx * Ny, *sy = sxt + Nx * Nx;
+    for (int i = tid; i < Nx * Nx; i += nth) sxt[(i % Nx) * Nx + i / Nx] = c.S[0][i];
+    for (int i = tid; i < Ny * Ny; i += nth) sy[i] = c.S[1][i];
+    Sx = sxt;
     Sy = sy;
   }
   const int z = blockIdx.x;
   const double *tz = t + (size_t)z * Nx * Ny;
-  for (int i = threadIdx.x; i < Nx * Ny; i += blockDim.x) P[i] = tz[i];
+  for (int i = tid; i < Nx * Ny; i += nth) P[i] = tz[i];
   __syncthreads();
-  tile_contract<false, false>(P, W, Nx, Nx, Ny, Sy);
-  tile_contract<true, false>(P, W, Nx, Ny, Nx, Sx);
+  tile_contract<false, false>(P, W, Nx, Ny, Sy);
+  if (TL) tile_contract<true, true>(P, W, Nx, Ny, Sx);  // (Sx^T)^T = Sx
+  else tile_contract<true, false>(P, W, Nx, Ny, Sx);
   double s = 0.0;
-  for (int i = threadIdx.x; i < Nx * Ny; i += blockDim.x) {
-    const int x = i % Nx, y = i / Nx;
-    u0[elem_major_p1(d, x, y, z)] = P[i];
-    s += P[i];
-  }
-  s = block_reduce_sum(s, red);
-  if (threadIdx.x == 0) c.partial_u[z] = s;
+  if (threadIdx.x < Nx)
+    for (int y = threadIdx.y; y < Ny; y += blockDim.y) {
+      const double v = P[y * Nx + threadIdx.x];
+      u0[elem_major_p1(d, threadIdx.x, y, z)] = v;
+      s += v;
+    }
+  s = block_sum_2d(s, red);
+  if (tid == 0) c.partial_u[z] = s;
 }
 
 // LDS bytes of the plane kernels: two planes, plus the 1D tables when they fit
@@ -203,12 +229,23 @@ hipError_t launch_coarse(const CoarseLaunch &c, const TI *f0, double *u0, bool s
   if (lds_xy) sxy += tab_bytes(d, 0, 1);
   if (lds_z) sz += tab_bytes(d, 2, 2);
   hipError_t e;
-  if ((e = allow_lds(coarse_plane_xy_fwd<TI>, sxy)) != hipSuccess) return e;
-  if ((e = allow_lds(coarse_plane_z, sz)) != hipSuccess) return e;
-  if ((e = allow_lds(coarse_plane_xy_bwd, sxy)) != hipSuccess) return e;
-  coarse_plane_xy_fwd<TI><<<d.N[2], 256, sxy, st>>>(d, c, f0, c.t0, lds_xy);
-  coarse_plane_z<<<d.N[1], 256, sz, st>>>(d, c, c.t0, lds_z);
-  coarse_plane_xy_bwd<<<d.N[2], 256, sxy, st>>>(d, c, c.t0, u0, lds_xy);
+  // 2D workgroups: x index in threadIdx.x, rows strided over threadIdx.y
+  const int bx = (d.N[0] + 63) / 64 * 64;
+  const dim3 blk(bx, std::max(1, std::min(1024 / bx, std::max(d.N[1], d.N[2]))));
+  if (lds_xy) {
+    if ((e = allow_lds(coarse_plane_xy_fwd<TI, true>, sxy)) != hipSuccess) return e;
+    if ((e = allow_lds(coarse_plane_xy_bwd<true>, sxy)) != hipSuccess) return e;
+  } else {
+    if ((e = allow_lds(coarse_plane_xy_fwd<TI, false>, sxy)) != hipSuccess) return e;
+    if ((e = allow_lds(coarse_plane_xy_bwd<false>, sxy)) != hipSuccess) return e;
+  }
+  if ((e = allow_lds(lds_z ? coarse_plane_z<true> : coarse_plane_z<false>, sz)) != hipSuccess) return e;
+  if (lds_xy) coarse_plane_xy_fwd<TI, true><<<d.N[2], blk, sxy, st>>>(d, c, f0, c.t0);
+  else coarse_plane_xy_fwd<TI, false><<<d.N[2], blk, sxy, st>>>(d, c, f0, c.t0);
+  if (lds_z) coarse_plane_z<true><<<d.N[1], blk, sz, st>>>(d, c, c.t0);
+  else coarse_plane_z<false><<<d.N[1], blk, sz, st>>>(d, c, c.t0);
+  if (lds_xy) coarse_plane_xy_bwd<true><<<d.N[2], blk, sxy, st>>>(d, c, c.t0, u0);
+  else coarse_plane_xy_bwd<false><<<d.N[2], blk, sxy, st>>>(d, c, c.t0, u0);
   e = hipGetLastError();
   if (e != hipSuccess || !subtract_mean) return e;
   if ((e = launch_finalize(c.partial_u, d.N[2], 1.0 / (double)N0, c.scalars + 1, st)) != hipSuccess) return e;

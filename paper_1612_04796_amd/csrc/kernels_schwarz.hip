@@ -386,41 +386,77 @@ schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ ilam, const T
   }
 }
 
+// Candidate subdomains of a node along one direction: its own element's
+// (offset 0) and, where the overlap reaches it, the left or right
+// neighbour's.  With an overlap below half an element (2 NO < N) a node lies
+// in at most two subdomains along the direction, else in up to three.
+template <int N, int M>
+struct AxisCands {
+  static constexpr int NO = (M - N) / 2;
+  static constexpr int K = 2 * NO < N ? 2 : 3;
+  int s[K];     // subdomain coordinate along the direction
+  int a[K];     // local index of the node in that subdomain
+  bool ok[K];
+  __device__ __forceinline__ AxisCands(int i, int ec, int ne) {
+    s[0] = ec;
+    a[0] = i + NO;
+    ok[0] = true;
+    if constexpr (K == 2) {
+      const bool left = i < NO;
+      s[1] = wrap(ec + (left ? -1 : 1), ne);
+      a[1] = left ? i + N + NO : i - N + NO;
+      ok[1] = left || i >= N - NO;
+    } else {
+      s[1] = wrap(ec - 1, ne);
+      a[1] = i + N + NO;
+      ok[1] = a[1] < M;
+      s[2] = wrap(ec + 1, ne);
+      a[2] = i - N + NO;
+      ok[2] = a[2] >= 0;
+    }
+  }
+};
+
 // Assembly with compile-time sizes: one thread per node (consecutive threads
-// on consecutive nodes of an element), the (up to 27) contributing
-// subdomains visited in a fixed order.
+// on consecutive nodes of an element).  Every candidate load is issued before
+// any is summed (invalid candidates load nothing and count zero), then the
+// contributions are added in a fixed order.
 template <typename T, int N, int MX, int MY, int MZ>
 __global__ void __launch_bounds__(256)
 schwarz_assemble_fixed(Mesh g, const T *__restrict__ C, const T *u_in, T *u_out) {
   constexpr int N3 = N * N * N, VOL = MX * MY * MZ;
-  constexpr int NOX = (MX - N) / 2, NOY = (MY - N) / 2, NOZ = (MZ - N) / 2;
   const int64_t idx = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (idx >= (int64_t)g.E * N3) return;
   const int e = (int)(idx / N3), loc = (int)(idx - (int64_t)e * N3);
   const int i = loc % N, j = (loc / N) % N, k = loc / (N * N);
   const int ex = e % g.ne[0], rest = e / g.ne[0];
   const int ey = rest % g.ne[1], ez = rest / g.ne[1];
+  const AxisCands<N, MX> cx(i, ex, g.ne[0]);
+  const AxisCands<N, MY> cy(j, ey, g.ne[1]);
+  const AxisCands<N, MZ> cz(k, ez, g.ne[2]);
+  constexpr int KX = AxisCands<N, MX>::K, KY = AxisCands<N, MY>::K, KZ = AxisCands<N, MZ>::K;
+  T v[KZ][KY][KX];
+#pragma unroll
+  for (int zc = 0; zc < KZ; ++zc)
+#pragma unroll
+    for (int yc = 0; yc < KY; ++yc)
+#pragma unroll
+      for (int xc = 0; xc < KX; ++xc) {
+        v[zc][yc][xc] = 0;
+        if (cz.ok[zc] && cy.ok[yc] && cx.ok[xc]) {
+          const int s = (cz.s[zc] * g.ne[1] + cy.s[yc]) * g.ne[0] + cx.s[xc];
+          v[zc][yc][xc] = C[(size_t)s * VOL + (cz.a[zc] * MY + cy.a[yc]) * MX + cx.a[xc]];
+        }
+      }
+  const T base = u_in ? u_in[idx] : (T)0;
   T sum = 0;
 #pragma unroll
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int c = k - dz * N + NOZ;
-    if (c < 0 || c >= MZ) continue;
-    const int sz = wrap(ez + dz, g.ne[2]);
+  for (int zc = 0; zc < KZ; ++zc)
 #pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int b = j - dy * N + NOY;
-      if (b < 0 || b >= MY) continue;
-      const int sy = wrap(ey + dy, g.ne[1]);
+    for (int yc = 0; yc < KY; ++yc)
 #pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int a = i - dx * N + NOX;
-        if (a < 0 || a >= MX) continue;
-        const int s = elem_index(g, wrap(ex + dx, g.ne[0]), sy, sz);
-        sum += C[(size_t)s * VOL + (c * MY + b) * MX + a];
-      }
-    }
-  }
-  u_out[idx] = (u_in ? u_in[idx] : (T)0) + sum;
+      for (int xc = 0; xc < KX; ++xc) sum += v[zc][yc][xc];
+  u_out[idx] = base + sum;
 }
 
 template <typename T, int N, int MX, int MY, int MZ>
