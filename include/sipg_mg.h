@@ -260,7 +260,9 @@ typedef enum {
   SIPG_TAB_SUB_W = 11,     /* 1D hat weights (m)                               */
   SIPG_TAB_INTERP = 12,    /* J (n_l x n_{l-1}) from level l-1 to level l      */
   SIPG_TAB_COARSE_LAM = 13,/* level-0 global eigenvalues (2 ne), zero mode = 0 */
-  SIPG_TAB_COARSE_S = 14   /* level-0 global eigenvectors (2ne x 2ne)          */
+  SIPG_TAB_COARSE_S = 14,  /* level-0 global eigenvectors (2ne x 2ne)          */
+  SIPG_TAB_SUB_LAM_EO = 15,/* the pairs of (L_s, M_s) split by the reversal     */
+  SIPG_TAB_SUB_S_EO = 16   /* a -> m-1-a: m - m/2 even then m/2 odd (m, m x m) */
 } sipg_table;
 
 /* Copies table `which` of direction dir (0..2) on level `level` into the HOST

@@ -51,6 +51,11 @@ struct SchwarzTabs {
   const T *lam[3];
   int m[3];
   int no[3];
+  // even-odd form of the same transforms (compile-time-shape kernel): per
+  // direction the packed forward and weighted backward half tables, and
+  // 1 / (lam_x + lam_y + lam_z) with each direction's modes in even-odd order
+  const T *EO[3];
+  const T *ilam_eo;
 };
 
 template <typename T>

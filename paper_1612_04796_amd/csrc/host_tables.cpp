@@ -78,6 +78,64 @@ void generalized_eigen(int n, const std::vector<double> &A, const std::vector<do
     for (int j = 0; j < n; ++j) S[i * n + j] = s[i] * Q[i * n + j];
 }
 
+// Eigenpairs of the symmetric pair (A, diag(Dm)) of order m split by the
+// reversal a -> m-1-a, under which both are invariant (uniform mesh,
+// overlap layers alike on both sides, GLL nodes symmetric about 0).  With
+// H = m/2, the even subspace has the orthonormal basis (e_a + e_{m-1-a})/sqrt2
+// (a < H) plus e_H when m is odd, the odd subspace (e_a - e_{m-1-a})/sqrt2.
+// The pair projected on each subspace is solved on its own, so every
+// eigenvector is exactly even or odd.  Output: even pairs first, then odd.
+void generalized_eigen_eo(int m, const std::vector<double> &A, const std::vector<double> &Dm,
+                          std::vector<double> &lam, std::vector<double> &S) {
+  const int H = m / 2, NE = m - H;
+  const double r2 = std::sqrt(0.5);
+  lam.assign(m, 0.0);
+  S.assign((size_t)m * m, 0.0);
+  for (int odd = 0; odd < 2; ++odd) {
+    const int k = odd ? H : NE;
+    // basis vector i of the subspace: entries (index, coefficient)
+    auto basis = [&](int i, int &a0, double &c0, int &a1, double &c1) {
+      if (i < H) {
+        a0 = i;
+        c0 = r2;
+        a1 = m - 1 - i;
+        c1 = odd ? -r2 : r2;
+      } else {  // centre node of an odd m (even subspace only)
+        a0 = a1 = H;
+        c0 = 1.0;
+        c1 = 0.0;
+      }
+    };
+    std::vector<double> Ak((size_t)k * k), Dk(k);
+    for (int i = 0; i < k; ++i) {
+      int ai0, ai1;
+      double ci0, ci1;
+      basis(i, ai0, ci0, ai1, ci1);
+      Dk[i] = ci0 * ci0 * Dm[ai0] + ci1 * ci1 * Dm[ai1];  // mean of the mirrored pair
+      for (int j = 0; j < k; ++j) {
+        int aj0, aj1;
+        double cj0, cj1;
+        basis(j, aj0, cj0, aj1, cj1);
+        Ak[(size_t)i * k + j] = ci0 * cj0 * A[(size_t)ai0 * m + aj0] + ci0 * cj1 * A[(size_t)ai0 * m + aj1] +
+                                ci1 * cj0 * A[(size_t)ai1 * m + aj0] + ci1 * cj1 * A[(size_t)ai1 * m + aj1];
+      }
+    }
+    std::vector<double> lk, Sk;
+    generalized_eigen(k, Ak, Dk, lk, Sk);
+    const int col0 = odd ? NE : 0;
+    for (int j = 0; j < k; ++j) {
+      lam[col0 + j] = lk[j];
+      for (int i = 0; i < k; ++i) {
+        int a0, a1;
+        double c0, c1;
+        basis(i, a0, c0, a1, c1);
+        S[(size_t)a0 * m + col0 + j] += c0 * Sk[(size_t)i * k + j];
+        if (a1 != a0) S[(size_t)a1 * m + col0 + j] += c1 * Sk[(size_t)i * k + j];
+      }
+    }
+  }
+}
+
 // Hat weights of the m = n + 2 N_O subdomain nodes: quintic step
 // S5(t) = 10t^3 - 15t^4 + 6t^5 of t = (1 + delta - |xi_H|) / (2 delta),
 // clipped to [0,1], where xi_H is xi - 2 / xi / xi + 2 in the left neighbour,
@@ -168,6 +226,7 @@ void build_dir(const sipg_params &prm, int p, int d, bool smoothed, Dir1D &D1) {
     for (int b = 0; b < m; ++b) D1.Ls[a * m + b] = Bat(n - no + a, n - no + b);
   }
   generalized_eigen(m, D1.Ls, D1.Ms, D1.lam, D1.S);
+  generalized_eigen_eo(m, D1.Ls, D1.Ms, D1.lam_eo, D1.S_eo);
   hat_weights(D1.xi, no, D1.wsub);
 }
 

@@ -28,6 +28,10 @@ struct Dir1D {
   std::vector<double> Ls, Ms;      // m x m, m
   std::vector<double> lam, S;      // m, m x m (S[a*m+j]: node a, pair j)
   std::vector<double> wsub;        // m
+  // The same eigenpairs split by the reversal symmetry a -> m-1-a of the
+  // subdomain: the m - m/2 even eigenvectors first, then the m/2 odd ones,
+  // each group ascending; columns exactly even / odd.
+  std::vector<double> lam_eo, S_eo;  // m, m x m
 };
 
 struct LevelHost {

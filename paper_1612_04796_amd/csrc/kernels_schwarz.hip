@@ -219,12 +219,12 @@ schwarz_assemble(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ C, cons
 
 // ---- fixed-size fast path ----------------------------------------------
 // Subdomain sizes known at compile time: all index arithmetic folds to
-// constants, the line arrays live in registers and the table rows are read
-// through the scalar cache.  SPB subdomains share a workgroup so that the
-// line phases fill whole wavefronts.  The forward contractions use the outer
-// product form (one LDS read feeds a whole S row), the backward ones the
-// inner product form (one WS row per output); the diagonal scaling uses the
-// precomputed 1 / (lam_x[a] + lam_y[b] + lam_z[c]) table.
+// constants, the line arrays live in registers and the (uniform) table
+// entries are read through the scalar cache.  SPB subdomains share a
+// workgroup so that the line phases fill whole wavefronts.  The 1D
+// contractions use the even-odd form below; the diagonal scaling uses the
+// precomputed 1 / (lam_x[a] + lam_y[b] + lam_z[c]) table in the same mode
+// order.
 template <int MX, int MY, int MZ>
 struct FdmShape {
   static constexpr int RX = MX | 1;
@@ -237,40 +237,72 @@ struct FdmShape {
   static constexpr int NTH = NTH0 > 1024 ? 1024 : NTH0;
 };
 
+// Even-odd 1D transforms.  The subdomain pair (L_s, M_s) and the hat weights
+// are invariant under the reversal a -> m-1-a of the m subdomain nodes
+// (uniform mesh, equal overlap on both sides, GLL nodes symmetric about 0),
+// so the eigenvectors are taken exactly even (NE = m - H of them, H = m/2)
+// or odd (H), even modes first in the spectral index.  A forward transform
+// contracts the H sums and H differences of mirrored entries (plus the
+// centre entry for odd m) with half tables; a backward transform forms the
+// even part E_a and the odd part O_a of each mirrored pair.  Per line this is
+// H NE + (m odd) NE + H^2 multiply-adds instead of m^2.  Table layout: see
+// pack_even_odd on the host.
+template <int M>
+struct Eo {
+  static constexpr int H = M / 2, NE = M - H, ODD = M & 1;
+  static constexpr int FE = 0, FC = FE + H * NE, FO = FC + ODD * NE;
+  static constexpr int BE = FO + H * H, BC = BE + H * NE, BO = BC + ODD * NE;
+};
+
 template <typename T, int M>
-__device__ __forceinline__ void fwd_outer(T *base, int st, const T *__restrict__ S) {
-  T acc[M];
+__device__ __forceinline__ void eo_fwd(const T (&v)[M], T (&y)[M], const T *__restrict__ tab) {
+  using E = Eo<M>;
+  T sm[E::H], df[E::H];
 #pragma unroll
-  for (int o = 0; o < M; ++o) acc[o] = 0;
-#pragma unroll
-  for (int a = 0; a < M; ++a) {
-    const T va = base[a * st];
-#pragma unroll
-    for (int o = 0; o < M; ++o) acc[o] += S[a * M + o] * va;
+  for (int a = 0; a < E::H; ++a) {
+    sm[a] = v[a] + v[M - 1 - a];
+    df[a] = v[a] - v[M - 1 - a];
   }
 #pragma unroll
-  for (int o = 0; o < M; ++o) base[o * st] = acc[o];
+  for (int j = 0; j < M; ++j) y[j] = 0;
+  if constexpr (E::ODD) {
+#pragma unroll
+    for (int j = 0; j < E::NE; ++j) y[j] = tab[E::FC + j] * v[E::H];
+  }
+#pragma unroll
+  for (int a = 0; a < E::H; ++a) {
+#pragma unroll
+    for (int j = 0; j < E::NE; ++j) y[j] += tab[E::FE + a * E::NE + j] * sm[a];
+#pragma unroll
+    for (int j = 0; j < E::H; ++j) y[E::NE + j] += tab[E::FO + a * E::H + j] * df[a];
+  }
 }
 
 template <typename T, int M>
-__device__ __forceinline__ void bwd_inner(T *base, int st, const T *__restrict__ WS) {
-  T v[M];
+__device__ __forceinline__ void eo_bwd(const T (&y)[M], T (&x)[M], const T *__restrict__ tab) {
+  using E = Eo<M>;
 #pragma unroll
-  for (int o = 0; o < M; ++o) v[o] = base[o * st];
+  for (int a = 0; a < E::H; ++a) {
+    T ev = 0, od = 0;
 #pragma unroll
-  for (int a = 0; a < M; ++a) {
-    T acc = 0;
+    for (int j = 0; j < E::NE; ++j) ev += tab[E::BE + a * E::NE + j] * y[j];
 #pragma unroll
-    for (int o = 0; o < M; ++o) acc += WS[a * M + o] * v[o];
-    base[a * st] = acc;
+    for (int j = 0; j < E::H; ++j) od += tab[E::BO + a * E::H + j] * y[E::NE + j];
+    x[a] = ev + od;
+    x[M - 1 - a] = ev - od;
+  }
+  if constexpr (E::ODD) {
+    T c = 0;
+#pragma unroll
+    for (int j = 0; j < E::NE; ++j) c += tab[E::BC + j] * y[j];
+    x[E::H] = c;
   }
 }
 
 // spb: subdomains per workgroup (at most Sh::SPB).
 template <typename T, int N, int MX, int MY, int MZ>
 __global__ void __launch_bounds__((FdmShape<MX, MY, MZ>::NTH))
-schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ ilam, const T *__restrict__ r,
-                  T *__restrict__ C, int spb) {
+schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restrict__ C, int spb) {
   using Sh = FdmShape<MX, MY, MZ>;
   constexpr int RX = Sh::RX, VOL = Sh::VOL, TILE = Sh::TILE, SPB = Sh::SPB;
   constexpr int NOX = (MX - N) / 2, NOY = (MY - N) / 2, NOZ = (MZ - N) / 2;
@@ -311,24 +343,24 @@ schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ ilam, const T
     for (int a = 0; a < N; ++a) v[NOX + a] = r0[a];
 #pragma unroll
     for (int a = 0; a < NOX; ++a) v[NOX + N + a] = rr[a];
-    const T *__restrict__ S = tb.S[0];
-    T acc[MX];
-#pragma unroll
-    for (int o = 0; o < MX; ++o) acc[o] = 0;
-#pragma unroll
-    for (int a = 0; a < MX; ++a)
-#pragma unroll
-      for (int o = 0; o < MX; ++o) acc[o] += S[a * MX + o] * v[a];
+    T y[MX];
+    eo_fwd<T, MX>(v, y, tb.EO[0]);
     T *base = t + q * TILE + cb * RX;
 #pragma unroll
-    for (int o = 0; o < MX; ++o) base[o] = acc[o];
+    for (int o = 0; o < MX; ++o) base[o] = y[o];
   }
   __syncthreads();
   // y forward: lines (q, c, a)
   if (tid < nsub * Sh::L2) {
     const int q = tid / Sh::L2, ca = tid - q * Sh::L2;
     const int c = ca / MX, a = ca - c * MX;
-    fwd_outer<T, MY>(t + q * TILE + c * MY * RX + a, RX, tb.S[1]);
+    T *base = t + q * TILE + c * MY * RX + a;
+    T v[MY], y[MY];
+#pragma unroll
+    for (int b = 0; b < MY; ++b) v[b] = base[b * RX];
+    eo_fwd<T, MY>(v, y, tb.EO[1]);
+#pragma unroll
+    for (int b = 0; b < MY; ++b) base[b * RX] = y[b];
   }
   __syncthreads();
   // z forward, scaling, z backward: lines (q, b, a)
@@ -337,52 +369,42 @@ schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ ilam, const T
     const int b = ba / MX, a = ba - b * MX;
     T *base = t + q * TILE + b * RX + a;
     constexpr int st = MY * RX;
-    const T *__restrict__ Sz = tb.S[2];
-    const T *__restrict__ WSz = tb.WS[2];
-    T acc[MZ];
+    T v[MZ], y[MZ];
 #pragma unroll
-    for (int o = 0; o < MZ; ++o) acc[o] = 0;
+    for (int c = 0; c < MZ; ++c) v[c] = base[c * st];
+    eo_fwd<T, MZ>(v, y, tb.EO[2]);
+    const T *il = tb.ilam_eo + b * MX + a;
 #pragma unroll
-    for (int c = 0; c < MZ; ++c) {
-      const T v = base[c * st];
+    for (int o = 0; o < MZ; ++o) y[o] *= il[o * MY * MX];
+    eo_bwd<T, MZ>(y, v, tb.EO[2]);
 #pragma unroll
-      for (int o = 0; o < MZ; ++o) acc[o] += Sz[c * MZ + o] * v;
-    }
-    const T *il = ilam + b * MX + a;
-#pragma unroll
-    for (int o = 0; o < MZ; ++o) acc[o] *= il[o * MY * MX];
-#pragma unroll
-    for (int c = 0; c < MZ; ++c) {
-      T s = 0;
-#pragma unroll
-      for (int o = 0; o < MZ; ++o) s += WSz[c * MZ + o] * acc[o];
-      base[c * st] = s;
-    }
+    for (int c = 0; c < MZ; ++c) base[c * st] = v[c];
   }
   __syncthreads();
   // y backward
   if (tid < nsub * Sh::L2) {
     const int q = tid / Sh::L2, ca = tid - q * Sh::L2;
     const int c = ca / MX, a = ca - c * MX;
-    bwd_inner<T, MY>(t + q * TILE + c * MY * RX + a, RX, tb.WS[1]);
+    T *base = t + q * TILE + c * MY * RX + a;
+    T y[MY], v[MY];
+#pragma unroll
+    for (int b = 0; b < MY; ++b) y[b] = base[b * RX];
+    eo_bwd<T, MY>(y, v, tb.EO[1]);
+#pragma unroll
+    for (int b = 0; b < MY; ++b) base[b * RX] = v[b];
   }
   __syncthreads();
   // x backward, written straight to the correction buffer: rows (q, c, b)
   if (tid < nsub * Sh::L1) {
     const int q = tid / Sh::L1, cb = tid - q * Sh::L1;
     const T *base = t + q * TILE + cb * RX;
-    T v[MX];
+    T y[MX], v[MX];
 #pragma unroll
-    for (int o = 0; o < MX; ++o) v[o] = base[o];
-    const T *__restrict__ WS = tb.WS[0];
+    for (int o = 0; o < MX; ++o) y[o] = base[o];
+    eo_bwd<T, MX>(y, v, tb.EO[0]);
     T *out = C + (size_t)(s0 + q) * VOL + cb * MX;
 #pragma unroll
-    for (int a = 0; a < MX; ++a) {
-      T acc = 0;
-#pragma unroll
-      for (int o = 0; o < MX; ++o) acc += WS[a * MX + o] * v[o];
-      out[a] = acc;
-    }
+    for (int a = 0; a < MX; ++a) out[a] = v[a];
   }
 }
 
@@ -473,7 +495,7 @@ hipError_t launch_fixed(const SchwarzLaunch<T> &a, hipStream_t st) {
   const int spb = Sh::SPB;
   const int nblk = (a.mesh.E + spb - 1) / spb;
   const int nth = std::min(Sh::NTH, (spb * Sh::LINES + 63) / 64 * 64);
-  schwarz_fdm_fixed<T, N, MX, MY, MZ><<<nblk, nth, 0, st>>>(a.mesh, a.tabs, a.ilam, a.r, a.C, spb);
+  schwarz_fdm_fixed<T, N, MX, MY, MZ><<<nblk, nth, 0, st>>>(a.mesh, a.tabs, a.r, a.C, spb);
   return hipGetLastError();
 }
 
@@ -542,7 +564,7 @@ bool schwarz_fits_lds(const int m[3], size_t eb) {
 
 template <typename T>
 hipError_t launch_schwarz_local(const SchwarzLaunch<T> &a, hipStream_t st) {
-  if (a.ilam) {
+  if (a.tabs.ilam_eo) {
     bool done = false;
     hipError_t e = launch_fixed_if_any<T>(a, st, done);
     if (done) return e;

@@ -182,11 +182,36 @@ void ensure_work(sipg_ctx *c) {
   w.ready = true;
 }
 
+// Even-odd half tables of one direction, in the layout the compile-time-shape
+// Schwarz kernel reads (H = m/2, NE = m - H even modes, NO = H odd modes):
+//   forward  FE[a][j] = S[a][j] (a < H, j < NE),  FC[j] = S[H][j] (m odd),
+//            FO[a][j] = S[a][NE + j] (a < H, j < H)
+//   backward BE, BC, BO: the same entries times the hat weight w[a]
+// with S the even-odd eigenvectors (even modes first).  The forward transform
+// then contracts sums and differences of mirrored entries; the backward one
+// forms E_a (even part) and O_a (odd part), x[a] = E_a + O_a and
+// x[m-1-a] = E_a - O_a (the weights are symmetric).
+std::vector<double> pack_even_odd(const sipg::Dir1D &D) {
+  const int m = D.m, H = m / 2, NE = m - H, odd = m & 1;
+  std::vector<double> t;
+  t.reserve(2 * ((size_t)H * NE + (size_t)odd * NE + (size_t)H * H));
+  for (int pass = 0; pass < 2; ++pass) {
+    auto wt = [&](int a) { return pass ? D.wsub[a] : 1.0; };
+    for (int a = 0; a < H; ++a)
+      for (int j = 0; j < NE; ++j) t.push_back(wt(a) * D.S_eo[(size_t)a * m + j]);
+    if (odd)
+      for (int j = 0; j < NE; ++j) t.push_back(wt(H) * D.S_eo[(size_t)H * m + j]);
+    for (int a = 0; a < H; ++a)
+      for (int j = 0; j < H; ++j) t.push_back(wt(a) * D.S_eo[(size_t)a * m + NE + j]);
+  }
+  return t;
+}
+
 void upload_tables(sipg_ctx *c) {
   const sipg::HierarchyHost &H = c->H;
   Arena A;
   struct Off {
-    size_t Ld[3], M[3], DL[3], DR[3], S[3], WS[3], lam[3], J, ilam;
+    size_t Ld[3], M[3], DL[3], DR[3], S[3], WS[3], lam[3], EO[3], J, ilam, ilam_eo;
   };
   std::vector<Off> o64(c->L + 1), o32(c->L + 1);
   auto put_level = [&](auto tag, std::vector<Off> &off) {
@@ -206,6 +231,7 @@ void upload_tables(sipg_ctx *c) {
           off[l].S[d] = A.put<T>(D.S);
           off[l].WS[d] = A.put<T>(WS);
           off[l].lam[d] = A.put<T>(D.lam);
+          off[l].EO[d] = A.put<T>(pack_even_odd(D));
         }
       }
       if (l > 0) {
@@ -217,6 +243,11 @@ void upload_tables(sipg_ctx *c) {
             for (int ax = 0; ax < X.m; ++ax)
               il[((size_t)cz * Y.m + by) * X.m + ax] = 1.0 / (X.lam[ax] + Y.lam[by] + Z.lam[cz]);
         off[l].ilam = A.put<T>(il);
+        for (int cz = 0; cz < Z.m; ++cz)
+          for (int by = 0; by < Y.m; ++by)
+            for (int ax = 0; ax < X.m; ++ax)
+              il[((size_t)cz * Y.m + by) * X.m + ax] = 1.0 / (X.lam_eo[ax] + Y.lam_eo[by] + Z.lam_eo[cz]);
+        off[l].ilam_eo = A.put<T>(il);
       }
     }
   };
@@ -260,6 +291,7 @@ void upload_tables(sipg_ctx *c) {
           t.schwarz.S[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].S[d]);
           t.schwarz.WS[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].WS[d]);
           t.schwarz.lam[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].lam[d]);
+          t.schwarz.EO[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].EO[d]);
           t.schwarz.m[d] = lv.dir[d].m;
           t.schwarz.no[d] = lv.dir[d].no;
         }
@@ -267,6 +299,7 @@ void upload_tables(sipg_ctx *c) {
       if (l > 0) {
         t.J = reinterpret_cast<const T *>(c->tab_dev + off[l].J);
         t.ilam = reinterpret_cast<const T *>(c->tab_dev + off[l].ilam);
+        t.schwarz.ilam_eo = reinterpret_cast<const T *>(c->tab_dev + off[l].ilam_eo);
       }
     }
   };
@@ -1010,9 +1043,12 @@ int sipg_host_table(const sipg_params *p, int level, int dir, int which, double 
       case SIPG_TAB_INTERP: v = H.lev[l].J; break;
       case SIPG_TAB_COARSE_LAM: v = H.coarse.lam[dir]; break;
       case SIPG_TAB_COARSE_S: v = H.coarse.S[dir]; break;
+      case SIPG_TAB_SUB_LAM_EO: v = D.lam_eo; break;
+      case SIPG_TAB_SUB_S_EO: v = D.S_eo; break;
       default: throw std::invalid_argument("unknown table");
     }
-    if ((which >= SIPG_TAB_SUB_L && which <= SIPG_TAB_SUB_W) && l == 0)
+    if (((which >= SIPG_TAB_SUB_L && which <= SIPG_TAB_SUB_W) || which == SIPG_TAB_SUB_LAM_EO ||
+         which == SIPG_TAB_SUB_S_EO) && l == 0)
       throw std::invalid_argument("level 0 has no subdomain tables");
     if (which == SIPG_TAB_INTERP && l == 0) throw std::invalid_argument("level 0 has no interpolation");
     *count = (int)v.size();

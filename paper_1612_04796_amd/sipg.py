@@ -17,7 +17,7 @@ OVERLAP = {"min": 0, "rel": 1, "max": 2}
 TABLES = {
     "nodes": 0, "weights": 1, "deriv": 2, "mass": 3, "ldiag": 4, "lupper": 5, "overlap": 6,
     "sub_l": 7, "sub_m": 8, "sub_lam": 9, "sub_s": 10, "sub_w": 11, "interp": 12,
-    "coarse_lam": 13, "coarse_s": 14,
+    "coarse_lam": 13, "coarse_s": 14, "sub_lam_eo": 15, "sub_s_eo": 16,
 }
 
 # every entry point the header declares

@@ -153,3 +153,32 @@ def test_single_hip_runtime_in_process():
     with open("/proc/self/maps") as f:
         runtimes = {line.split()[-1] for line in f if "libamdhip64" in line}
     assert len(runtimes) == 1, runtimes
+
+
+@pytest.mark.parametrize("kw", [CASES[1], CASES[2], CASES[3]])
+def test_host_even_odd_eigenpairs(kw):
+    """The even-odd eigenpairs the compile-time-shape Schwarz kernel uses,
+    against the oracle's restricted pair (L_s, M_s): the pair is
+    reversal-symmetric, every column is exactly even (the first m - m/2) or
+    odd, the generalized eigen-equation and M-orthonormality hold, and the
+    inverse operator S diag(1/lam) S^T is the oracle's."""
+    h = _hier(kw)
+    for l in range(1, len(h.levels)):
+        for d in range(3):
+            tab = h.levels[l].tabs[d]
+            m = tab.m
+            Ls, Ms = tab.Ls, tab.Ms
+            lam = _t(l, d, "sub_lam_eo", kw)
+            S = _t(l, d, "sub_s_eo", kw).reshape(m, m)
+            R = np.eye(m)[::-1]
+            ne = m - m // 2
+            scale = np.abs(Ls).max()
+            assert np.abs(R @ Ls @ R - Ls).max() <= 1e-14 * scale
+            assert np.allclose(Ms[::-1], Ms, rtol=1e-15)
+            assert np.array_equal(R @ S[:, :ne], S[:, :ne])
+            assert np.array_equal(R @ S[:, ne:], -S[:, ne:])
+            assert np.abs(Ls @ S - (Ms[:, None] * S) * lam[None, :]).max() <= 1e-12 * scale
+            assert np.abs(S.T @ (Ms[:, None] * S) - np.eye(m)).max() <= 1e-12
+            inv_c = S @ np.diag(1 / lam) @ S.T
+            inv_o = tab.S @ np.diag(1 / tab.lam) @ tab.S.T
+            assert np.abs(inv_c - inv_o).max() <= 1e-10 * np.abs(inv_o).max()
