@@ -233,7 +233,11 @@ struct FdmShape {
   static constexpr int L1 = MY * MZ, L2 = MX * MZ, L3 = MX * MY;
   static constexpr int LINES = L1 > L2 ? (L1 > L3 ? L1 : L3) : (L2 > L3 ? L2 : L3);
   static constexpr int SPB = LINES >= 512 ? 1 : 512 / LINES;
-  static constexpr int NTH0 = (SPB * LINES + 63) / 64 * 64;
+  static constexpr int MMAX = MX > MY ? (MX > MZ ? MX : MZ) : (MY > MZ ? MY : MZ);
+  // lines per thread in every phase (more lines per thread share each table
+  // entry but lower the occupancy, which costs more: measured slower)
+  static constexpr int LPT = 1;
+  static constexpr int NTH0 = ((SPB * LINES + LPT - 1) / LPT + 63) / 64 * 64;
   static constexpr int NTH = NTH0 > 1024 ? 1024 : NTH0;
 };
 
@@ -246,7 +250,8 @@ struct FdmShape {
 // centre entry for odd m) with half tables; a backward transform forms the
 // even part E_a and the odd part O_a of each mirrored pair.  Per line this is
 // H NE + (m odd) NE + H^2 multiply-adds instead of m^2.  Table layout: see
-// pack_even_odd on the host.
+// pack_even_odd on the host.  K lines are transformed together, so that every
+// table entry (uniform, from the scalar cache) feeds K multiply-adds.
 template <int M>
 struct Eo {
   static constexpr int H = M / 2, NE = M - H, ODD = M & 1;
@@ -254,57 +259,95 @@ struct Eo {
   static constexpr int BE = FO + H * H, BC = BE + H * NE, BO = BC + ODD * NE;
 };
 
-template <typename T, int M>
-__device__ __forceinline__ void eo_fwd(const T (&v)[M], T (&y)[M], const T *__restrict__ tab) {
+template <typename T, int M, int K>
+__device__ __forceinline__ void eo_fwd(const T (&v)[K][M], T (&y)[K][M], const T *__restrict__ tab) {
   using E = Eo<M>;
-  T sm[E::H], df[E::H];
+  T sm[K][E::H], df[K][E::H];
 #pragma unroll
-  for (int a = 0; a < E::H; ++a) {
-    sm[a] = v[a] + v[M - 1 - a];
-    df[a] = v[a] - v[M - 1 - a];
-  }
+  for (int l = 0; l < K; ++l)
 #pragma unroll
-  for (int j = 0; j < M; ++j) y[j] = 0;
+    for (int a = 0; a < E::H; ++a) {
+      sm[l][a] = v[l][a] + v[l][M - 1 - a];
+      df[l][a] = v[l][a] - v[l][M - 1 - a];
+    }
+#pragma unroll
+  for (int l = 0; l < K; ++l)
+#pragma unroll
+    for (int j = 0; j < M; ++j) y[l][j] = 0;
   if constexpr (E::ODD) {
 #pragma unroll
-    for (int j = 0; j < E::NE; ++j) y[j] = tab[E::FC + j] * v[E::H];
+    for (int j = 0; j < E::NE; ++j) {
+      const T c = tab[E::FC + j];
+#pragma unroll
+      for (int l = 0; l < K; ++l) y[l][j] = c * v[l][E::H];
+    }
   }
 #pragma unroll
   for (int a = 0; a < E::H; ++a) {
 #pragma unroll
-    for (int j = 0; j < E::NE; ++j) y[j] += tab[E::FE + a * E::NE + j] * sm[a];
+    for (int j = 0; j < E::NE; ++j) {
+      const T c = tab[E::FE + a * E::NE + j];
 #pragma unroll
-    for (int j = 0; j < E::H; ++j) y[E::NE + j] += tab[E::FO + a * E::H + j] * df[a];
+      for (int l = 0; l < K; ++l) y[l][j] += c * sm[l][a];
+    }
+#pragma unroll
+    for (int j = 0; j < E::H; ++j) {
+      const T c = tab[E::FO + a * E::H + j];
+#pragma unroll
+      for (int l = 0; l < K; ++l) y[l][E::NE + j] += c * df[l][a];
+    }
   }
 }
 
-template <typename T, int M>
-__device__ __forceinline__ void eo_bwd(const T (&y)[M], T (&x)[M], const T *__restrict__ tab) {
+template <typename T, int M, int K>
+__device__ __forceinline__ void eo_bwd(const T (&y)[K][M], T (&x)[K][M], const T *__restrict__ tab) {
   using E = Eo<M>;
 #pragma unroll
   for (int a = 0; a < E::H; ++a) {
-    T ev = 0, od = 0;
+    T ev[K], od[K];
 #pragma unroll
-    for (int j = 0; j < E::NE; ++j) ev += tab[E::BE + a * E::NE + j] * y[j];
+    for (int l = 0; l < K; ++l) ev[l] = od[l] = 0;
 #pragma unroll
-    for (int j = 0; j < E::H; ++j) od += tab[E::BO + a * E::H + j] * y[E::NE + j];
-    x[a] = ev + od;
-    x[M - 1 - a] = ev - od;
+    for (int j = 0; j < E::NE; ++j) {
+      const T c = tab[E::BE + a * E::NE + j];
+#pragma unroll
+      for (int l = 0; l < K; ++l) ev[l] += c * y[l][j];
+    }
+#pragma unroll
+    for (int j = 0; j < E::H; ++j) {
+      const T c = tab[E::BO + a * E::H + j];
+#pragma unroll
+      for (int l = 0; l < K; ++l) od[l] += c * y[l][E::NE + j];
+    }
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+      x[l][a] = ev[l] + od[l];
+      x[l][M - 1 - a] = ev[l] - od[l];
+    }
   }
   if constexpr (E::ODD) {
-    T c = 0;
+    T cs[K];
 #pragma unroll
-    for (int j = 0; j < E::NE; ++j) c += tab[E::BC + j] * y[j];
-    x[E::H] = c;
+    for (int l = 0; l < K; ++l) cs[l] = 0;
+#pragma unroll
+    for (int j = 0; j < E::NE; ++j) {
+      const T c = tab[E::BC + j];
+#pragma unroll
+      for (int l = 0; l < K; ++l) cs[l] += c * y[l][j];
+    }
+#pragma unroll
+    for (int l = 0; l < K; ++l) x[l][E::H] = cs[l];
   }
 }
 
-// spb: subdomains per workgroup (at most Sh::SPB).
+// spb: subdomains per workgroup (at most Sh::SPB).  In every phase thread t
+// owns lines t, t + blockDim.x, ... (Sh::LPT of them), reads them from the
+// tile and writes them back in place; lines of one phase are disjoint.
 template <typename T, int N, int MX, int MY, int MZ>
 __global__ void __launch_bounds__((FdmShape<MX, MY, MZ>::NTH))
 schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restrict__ C, int spb) {
   using Sh = FdmShape<MX, MY, MZ>;
-  constexpr int RX = Sh::RX, VOL = Sh::VOL, TILE = Sh::TILE, SPB = Sh::SPB;
+  constexpr int RX = Sh::RX, VOL = Sh::VOL, TILE = Sh::TILE, SPB = Sh::SPB, K = Sh::LPT;
   constexpr int NOX = (MX - N) / 2, NOY = (MY - N) / 2, NOZ = (MZ - N) / 2;
   constexpr int N3 = N * N * N;
   __shared__ T t[SPB * TILE];
@@ -312,9 +355,9 @@ schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restr
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int s0 = blk * spb;
   const int nsub = min(spb, g.E - s0);
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, nth = blockDim.x;
 
-  for (int i = tid; i < nsub * 27; i += blockDim.x) {
+  for (int i = tid; i < nsub * 27; i += nth) {
     const int q = i / 27, k = i - q * 27;
     const int s = s0 + q;
     const int ex = s % g.ne[0], rest = s / g.ne[0];
@@ -323,88 +366,180 @@ schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restr
                        wrap(ez + k / 9 - 1, g.ne[2]));
   }
   __syncthreads();
-  // x forward: thread per row (q, c, b); the row of R_s r is three contiguous
-  // runs in the left neighbour, the core element and the right neighbour
-  if (tid < nsub * Sh::L1) {
-    const int q = tid / Sh::L1, cb = tid - q * Sh::L1;
-    const int b = cb % MY, c = cb / MY;
-    const int gy = b - NOY, gz = c - NOZ;
-    const int dy = gy < 0 ? -1 : (gy >= N ? 1 : 0), dz = gz < 0 ? -1 : (gz >= N ? 1 : 0);
-    const int j = gy - dy * N, k = gz - dz * N;
-    const int *nbq = nb + q * 27 + (dz + 1) * 9 + (dy + 1) * 3;
-    const int row = (k * N + j) * N;
-    const T *rl = r + (size_t)nbq[0] * N3 + row + (N - NOX);
-    const T *r0 = r + (size_t)nbq[1] * N3 + row;
-    const T *rr = r + (size_t)nbq[2] * N3 + row;
-    T v[MX];
+  // x forward: rows (q, c, b); the row of R_s r is three contiguous runs in
+  // the left neighbour, the core element and the right neighbour
+  {
+    const int nl = nsub * Sh::L1;
+    T v[K][MX], y[K][MX];
 #pragma unroll
-    for (int a = 0; a < NOX; ++a) v[a] = rl[a];
+    for (int l = 0; l < K; ++l) {
+      const int li = tid + l * nth;
 #pragma unroll
-    for (int a = 0; a < N; ++a) v[NOX + a] = r0[a];
+      for (int a = 0; a < MX; ++a) v[l][a] = 0;
+      if (li < nl) {
+        const int q = li / Sh::L1, cb = li - q * Sh::L1;
+        const int b = cb % MY, c = cb / MY;
+        const int gy = b - NOY, gz = c - NOZ;
+        const int dy = gy < 0 ? -1 : (gy >= N ? 1 : 0), dz = gz < 0 ? -1 : (gz >= N ? 1 : 0);
+        const int j = gy - dy * N, k = gz - dz * N;
+        const int *nbq = nb + q * 27 + (dz + 1) * 9 + (dy + 1) * 3;
+        const int row = (k * N + j) * N;
+        const T *rl = r + (size_t)nbq[0] * N3 + row + (N - NOX);
+        const T *r0 = r + (size_t)nbq[1] * N3 + row;
+        const T *rr = r + (size_t)nbq[2] * N3 + row;
 #pragma unroll
-    for (int a = 0; a < NOX; ++a) v[NOX + N + a] = rr[a];
-    T y[MX];
-    eo_fwd<T, MX>(v, y, tb.EO[0]);
-    T *base = t + q * TILE + cb * RX;
+        for (int a = 0; a < NOX; ++a) v[l][a] = rl[a];
 #pragma unroll
-    for (int o = 0; o < MX; ++o) base[o] = y[o];
+        for (int a = 0; a < N; ++a) v[l][NOX + a] = r0[a];
+#pragma unroll
+        for (int a = 0; a < NOX; ++a) v[l][NOX + N + a] = rr[a];
+      }
+    }
+    eo_fwd<T, MX, K>(v, y, tb.EO[0]);
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+      const int li = tid + l * nth;
+      if (li < nl) {
+        const int q = li / Sh::L1, cb = li - q * Sh::L1;
+        T *base = t + q * TILE + cb * RX;
+#pragma unroll
+        for (int o = 0; o < MX; ++o) base[o] = y[l][o];
+      }
+    }
   }
   __syncthreads();
   // y forward: lines (q, c, a)
-  if (tid < nsub * Sh::L2) {
-    const int q = tid / Sh::L2, ca = tid - q * Sh::L2;
-    const int c = ca / MX, a = ca - c * MX;
-    T *base = t + q * TILE + c * MY * RX + a;
-    T v[MY], y[MY];
+  {
+    const int nl = nsub * Sh::L2;
+    T v[K][MY], y[K][MY];
 #pragma unroll
-    for (int b = 0; b < MY; ++b) v[b] = base[b * RX];
-    eo_fwd<T, MY>(v, y, tb.EO[1]);
+    for (int l = 0; l < K; ++l) {
+      // surplus lanes read the last line (their results are not stored)
+      const int li = min(tid + l * nth, nl - 1);
+      const int q = li / Sh::L2, ca = li - q * Sh::L2;
+      const int c = ca / MX, a = ca - c * MX;
+      const T *base = t + q * TILE + c * MY * RX + a;
 #pragma unroll
-    for (int b = 0; b < MY; ++b) base[b * RX] = y[b];
+      for (int b = 0; b < MY; ++b) v[l][b] = base[b * RX];
+    }
+    eo_fwd<T, MY, K>(v, y, tb.EO[1]);
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+      const int li = tid + l * nth;
+      if (li < nl) {
+        const int q = li / Sh::L2, ca = li - q * Sh::L2;
+        const int c = ca / MX, a = ca - c * MX;
+        T *base = t + q * TILE + c * MY * RX + a;
+#pragma unroll
+        for (int b = 0; b < MY; ++b) base[b * RX] = y[l][b];
+      }
+    }
   }
   __syncthreads();
   // z forward, scaling, z backward: lines (q, b, a)
-  if (tid < nsub * Sh::L3) {
-    const int q = tid / Sh::L3, ba = tid - q * Sh::L3;
-    const int b = ba / MX, a = ba - b * MX;
-    T *base = t + q * TILE + b * RX + a;
+  {
+    const int nl = nsub * Sh::L3;
     constexpr int st = MY * RX;
-    T v[MZ], y[MZ];
+    T v[K][MZ], y[K][MZ];
 #pragma unroll
-    for (int c = 0; c < MZ; ++c) v[c] = base[c * st];
-    eo_fwd<T, MZ>(v, y, tb.EO[2]);
-    const T *il = tb.ilam_eo + b * MX + a;
+    for (int l = 0; l < K; ++l) {
+      const int li = min(tid + l * nth, nl - 1);
+      const int q = li / Sh::L3, ba = li - q * Sh::L3;
+      const int b = ba / MX, a = ba - b * MX;
+      const T *base = t + q * TILE + b * RX + a;
 #pragma unroll
-    for (int o = 0; o < MZ; ++o) y[o] *= il[o * MY * MX];
-    eo_bwd<T, MZ>(y, v, tb.EO[2]);
+      for (int c = 0; c < MZ; ++c) v[l][c] = base[c * st];
+    }
+    eo_fwd<T, MZ, K>(v, y, tb.EO[2]);
 #pragma unroll
-    for (int c = 0; c < MZ; ++c) base[c * st] = v[c];
+    for (int l = 0; l < K; ++l) {
+      const int li = min(tid + l * nth, nl - 1);
+      const int q = li / Sh::L3, ba = li - q * Sh::L3;
+      const T *il = tb.ilam_eo + ba;
+#pragma unroll
+      for (int o = 0; o < MZ; ++o) y[l][o] *= il[o * MY * MX];
+    }
+    eo_bwd<T, MZ, K>(y, v, tb.EO[2]);
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+      const int li = tid + l * nth;
+      if (li < nl) {
+        const int q = li / Sh::L3, ba = li - q * Sh::L3;
+        const int b = ba / MX, a = ba - b * MX;
+        T *base = t + q * TILE + b * RX + a;
+#pragma unroll
+        for (int c = 0; c < MZ; ++c) base[c * st] = v[l][c];
+      }
+    }
   }
   __syncthreads();
   // y backward
-  if (tid < nsub * Sh::L2) {
-    const int q = tid / Sh::L2, ca = tid - q * Sh::L2;
-    const int c = ca / MX, a = ca - c * MX;
-    T *base = t + q * TILE + c * MY * RX + a;
-    T y[MY], v[MY];
+  {
+    const int nl = nsub * Sh::L2;
+    T y[K][MY], v[K][MY];
 #pragma unroll
-    for (int b = 0; b < MY; ++b) y[b] = base[b * RX];
-    eo_bwd<T, MY>(y, v, tb.EO[1]);
+    for (int l = 0; l < K; ++l) {
+      const int li = min(tid + l * nth, nl - 1);
+      const int q = li / Sh::L2, ca = li - q * Sh::L2;
+      const int c = ca / MX, a = ca - c * MX;
+      const T *base = t + q * TILE + c * MY * RX + a;
 #pragma unroll
-    for (int b = 0; b < MY; ++b) base[b * RX] = v[b];
+      for (int b = 0; b < MY; ++b) y[l][b] = base[b * RX];
+    }
+    eo_bwd<T, MY, K>(y, v, tb.EO[1]);
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+      const int li = tid + l * nth;
+      if (li < nl) {
+        const int q = li / Sh::L2, ca = li - q * Sh::L2;
+        const int c = ca / MX, a = ca - c * MX;
+        T *base = t + q * TILE + c * MY * RX + a;
+#pragma unroll
+        for (int b = 0; b < MY; ++b) base[b * RX] = v[l][b];
+      }
+    }
   }
   __syncthreads();
-  // x backward, written straight to the correction buffer: rows (q, c, b)
-  if (tid < nsub * Sh::L1) {
-    const int q = tid / Sh::L1, cb = tid - q * Sh::L1;
-    const T *base = t + q * TILE + cb * RX;
-    T y[MX], v[MX];
+  // x backward: rows (q, c, b), in place
+  {
+    const int nl = nsub * Sh::L1;
+    T y[K][MX], v[K][MX];
 #pragma unroll
-    for (int o = 0; o < MX; ++o) y[o] = base[o];
-    eo_bwd<T, MX>(y, v, tb.EO[0]);
-    T *out = C + (size_t)(s0 + q) * VOL + cb * MX;
+    for (int l = 0; l < K; ++l) {
+      const int li = min(tid + l * nth, nl - 1);
+      const int q = li / Sh::L1, cb = li - q * Sh::L1;
+      const T *base = t + q * TILE + cb * RX;
 #pragma unroll
-    for (int a = 0; a < MX; ++a) out[a] = v[a];
+      for (int o = 0; o < MX; ++o) y[l][o] = base[o];
+    }
+    eo_bwd<T, MX, K>(y, v, tb.EO[0]);
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+      const int li = tid + l * nth;
+      if (li < nl) {
+        const int q = li / Sh::L1, cb = li - q * Sh::L1;
+        T *base = t + q * TILE + cb * RX;
+#pragma unroll
+        for (int a = 0; a < MX; ++a) base[a] = v[l][a];
+      }
+    }
+  }
+  __syncthreads();
+  // the corrections of the workgroup's subdomains are one contiguous run of
+  // C: store it with consecutive lanes on consecutive addresses (a row per
+  // lane would scatter every store over 64 cache lines)
+  {
+    T *out = C + (size_t)s0 * VOL;
+    const int tot = nsub * VOL;
+    for (int i = tid; i < tot; i += nth) {
+      if constexpr (RX == MX) {
+        out[i] = t[i + (i / VOL) * (TILE - VOL)];
+      } else {
+        const int q = i / VOL, rem = i - q * VOL;
+        const int row = rem / MX, a = rem - row * MX;
+        out[i] = t[q * TILE + row * RX + a];
+      }
+    }
   }
 }
 
@@ -494,7 +629,7 @@ hipError_t launch_fixed(const SchwarzLaunch<T> &a, hipStream_t st) {
   static_assert(Sh::SPB * Sh::TILE * sizeof(T) <= 160 * 1024, "subdomain tile exceeds LDS");
   const int spb = Sh::SPB;
   const int nblk = (a.mesh.E + spb - 1) / spb;
-  const int nth = std::min(Sh::NTH, (spb * Sh::LINES + 63) / 64 * 64);
+  const int nth = std::min(Sh::NTH, ((spb * Sh::LINES + Sh::LPT - 1) / Sh::LPT + 63) / 64 * 64);
   schwarz_fdm_fixed<T, N, MX, MY, MZ><<<nblk, nth, 0, st>>>(a.mesh, a.tabs, a.r, a.C, spb);
   return hipGetLastError();
 }
