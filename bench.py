@@ -34,6 +34,35 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "schwarz_fdm_fixed_cube16_p8_pmc_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1612_04796_amd", "csrc", f)
+                  for f in ("kernels_schwarz.hip", "device_common.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for a plain copy of known size), or None when that summary was taken on
+    another version of the kernel's source."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            fields = dict(l.split(":", 1) for l in f.read().splitlines() if l.startswith(("source_sha256", "traffic_bytes")))
+    except OSError:
+        return None
+    if fields.get("source_sha256", "").strip() != kernel_source_hash():
+        return None
+    return float(fields["traffic_bytes_per_launch"].strip())
+
+
 def schwarz_flops(m):
     """Algorithmic flops of one subdomain's fast-diagonalization solve:
     three forward and three backward 1D contractions (2 flops per
@@ -249,7 +278,9 @@ def main():
         work = schwarz_flops(m) * E
         achieved = work / (kern[dominant] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None, "kernel": "schwarz_lds_kernel",
+                "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+                "traffic": pmc_traffic() if (n, m) == (9, (13, 13, 13)) else None,
+                "kernel": f"schwarz_fdm_fixed<double, {n}, {m[0]}, {m[1]}, {m[2]}>",
                 "work_per_launch": work, "ms_per_launch": kern[dominant]}
     else:
         bytes_per = {"residual": 24, "schwarz_assemble": 24, "restrict": 16 + 8 / 8, "prolong": 16 + 8 / 8}
