@@ -48,6 +48,7 @@ template <typename T>
 struct SchwarzTabs {
   const T *S[3];
   const T *WS[3];
+  const T *WST[3];  // (W S)^T: WST[o*m + a] = WS[a*m + o]
   const T *lam[3];
   int m[3];
   int no[3];

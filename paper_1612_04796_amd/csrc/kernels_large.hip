@@ -139,10 +139,11 @@ elem_axis(int E, int sx, int sy, int sz, int axis, int nout, const T *__restrict
 // length m, `count` of them with pitch `pitch`) or the columns (ROWS = false:
 // column j has entries P[k * pitch + j], k < m) of a plane in LDS, processed
 // in batches so that every output of a batch is computed before the batch is
-// written back.  FWD: out[o] = sum_a A[a*m + o] in[a]; else out[a] = sum_o
-// A[a*m + o] in[o].
-template <typename T, bool ROWS, bool FWD>
-__device__ void plane_contract(T *P, int pitch, int count, int m, const T *__restrict__ A) {
+// written back: out[o] = sum_a At[a*m + o] in[a], so consecutive lanes (o)
+// read consecutive table entries (S for a forward, (W S)^T for a backward
+// contraction; in LDS when it fits).
+template <typename T, bool ROWS>
+__device__ void plane_contract(T *P, int pitch, int count, int m, const T *__restrict__ At) {
   const int nth = blockDim.x, tid = threadIdx.x;
   const int per_batch = max(1, nth / m);  // lines per batch
   for (int l0 = 0; l0 < count; l0 += per_batch) {
@@ -151,9 +152,10 @@ __device__ void plane_contract(T *P, int pitch, int count, int m, const T *__res
     const bool act = tid < nl * m;
     const int line = l0 + tid / m, o = tid % m;
     if (act) {
+#pragma unroll 8
       for (int a = 0; a < m; ++a) {
         const T x = ROWS ? P[line * pitch + a] : P[a * pitch + line];
-        acc += (FWD ? A[a * m + o] : A[o * m + a]) * x;
+        acc += At[a * m + o] * x;
       }
     }
     __syncthreads();
@@ -162,6 +164,38 @@ __device__ void plane_contract(T *P, int pitch, int count, int m, const T *__res
       else P[o * pitch + line] = acc;
     }
     __syncthreads();
+  }
+}
+
+// The tables a wide kernel contracts with: copied into LDS after the plane
+// (TL) or read from global memory.
+template <typename T, bool TL>
+__device__ __forceinline__ const T *stage_table(T *lds, const T *__restrict__ g, int count) {
+  if constexpr (TL) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) lds[i] = g[i];
+    return lds;
+  } else {
+    return g;
+  }
+}
+
+// for (i = tid; i < tot; i += nth) put(i, get(i)), with the loads of kGB
+// consecutive iterations issued before any of their values is used
+constexpr int kGB = 8;
+template <typename T, typename Get, typename Put>
+__device__ __forceinline__ void batched_copy(int tot, int tid, int nth, Get get, Put put) {
+  for (int i0 = tid; i0 < tot; i0 += kGB * nth) {
+    T val[kGB];
+#pragma unroll
+    for (int u = 0; u < kGB; ++u) {
+      const int i = i0 + u * nth;
+      val[u] = i < tot ? get(i) : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kGB; ++u) {
+      const int i = i0 + u * nth;
+      if (i < tot) put(i, val[u]);
+    }
   }
 }
 
@@ -176,69 +210,80 @@ __device__ __forceinline__ T gather_node(const Mesh &g, int n, const T *__restri
 }
 
 // phase 1: block (s, c): gather the z-slab, x and y forward
-template <typename T>
+template <typename T, bool TL>
 __global__ void __launch_bounds__(256)
 wide_slab1(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restrict__ W) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *P = reinterpret_cast<T *>(smem_raw);
   const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
+  const T *Ax = stage_table<T, TL>(P + mx * my, tb.S[0], mx * mx);
+  const T *Ay = stage_table<T, TL>(P + mx * my + mx * mx, tb.S[1], my * my);
   const int blk = blockIdx.x;
   const int s = blk / mz, c = blk - s * mz;
   const int ex = s % g.ne[0], rest = s / g.ne[0];
   const int ey = rest % g.ne[1], ez = rest / g.ne[1];
-  for (int idx = threadIdx.x; idx < mx * my; idx += blockDim.x) {
-    const int a = idx % mx, b = idx / mx;
-    P[idx] = gather_node(g, n, r, ex, ey, ez, a - tb.no[0], b - tb.no[1], c - tb.no[2]);
-  }
+  batched_copy<T>(
+      mx * my, threadIdx.x, blockDim.x,
+      [&](int idx) {
+        const int a = idx % mx, b = idx / mx;
+        return gather_node(g, n, r, ex, ey, ez, a - tb.no[0], b - tb.no[1], c - tb.no[2]);
+      },
+      [&](int idx, T v) { P[idx] = v; });
   __syncthreads();
-  plane_contract<T, true, true>(P, mx, my, mx, tb.S[0]);
-  plane_contract<T, false, true>(P, mx, mx, my, tb.S[1]);
+  plane_contract<T, true>(P, mx, my, mx, Ax);
+  plane_contract<T, false>(P, mx, mx, my, Ay);
   T *Ws = W + ((size_t)s * mz + c) * mx * my;
-  for (int idx = threadIdx.x; idx < mx * my; idx += blockDim.x) Ws[idx] = P[idx];
+  batched_copy<T>(
+      mx * my, threadIdx.x, blockDim.x, [&](int idx) { return P[idx]; }, [&](int idx, T v) { Ws[idx] = v; });
 }
 
 // phase 2: block (s, b): the xz plane, z forward, scaling, z backward
-template <typename T>
+template <typename T, bool TL>
 __global__ void __launch_bounds__(256)
 wide_slab2(int E, SchwarzTabs<T> tb, const T *__restrict__ ilam, T *__restrict__ W) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *P = reinterpret_cast<T *>(smem_raw);
   const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
+  const T *Af = stage_table<T, TL>(P + mx * mz, tb.S[2], mz * mz);
+  const T *Ab = stage_table<T, TL>(P + mx * mz + mz * mz, tb.WST[2], mz * mz);
   const int blk = blockIdx.x;
   const int s = blk / my, b = blk - s * my;
   T *Ws = W + (size_t)s * mx * my * mz;
-  for (int idx = threadIdx.x; idx < mx * mz; idx += blockDim.x) {
-    const int a = idx % mx, c = idx / mx;
-    P[idx] = Ws[((size_t)c * my + b) * mx + a];
-  }
+  batched_copy<T>(
+      mx * mz, threadIdx.x, blockDim.x,
+      [&](int idx) { return Ws[((size_t)(idx / mx) * my + b) * mx + idx % mx]; },
+      [&](int idx, T v) { P[idx] = v; });
   __syncthreads();
-  plane_contract<T, false, true>(P, mx, mx, mz, tb.S[2]);
-  for (int idx = threadIdx.x; idx < mx * mz; idx += blockDim.x) {
-    const int a = idx % mx, c = idx / mx;
-    P[idx] *= ilam[((size_t)c * my + b) * mx + a];
-  }
+  plane_contract<T, false>(P, mx, mx, mz, Af);
+  batched_copy<T>(
+      mx * mz, threadIdx.x, blockDim.x,
+      [&](int idx) { return ilam[((size_t)(idx / mx) * my + b) * mx + idx % mx]; },
+      [&](int idx, T v) { P[idx] *= v; });
   __syncthreads();
-  plane_contract<T, false, false>(P, mx, mx, mz, tb.WS[2]);
-  for (int idx = threadIdx.x; idx < mx * mz; idx += blockDim.x) {
-    const int a = idx % mx, c = idx / mx;
-    Ws[((size_t)c * my + b) * mx + a] = P[idx];
-  }
+  plane_contract<T, false>(P, mx, mx, mz, Ab);
+  batched_copy<T>(
+      mx * mz, threadIdx.x, blockDim.x, [&](int idx) { return P[idx]; },
+      [&](int idx, T v) { Ws[((size_t)(idx / mx) * my + b) * mx + idx % mx] = v; });
 }
 
 // phase 3: block (s, c): y and x backward
-template <typename T>
+template <typename T, bool TL>
 __global__ void __launch_bounds__(256) wide_slab3(int E, SchwarzTabs<T> tb, T *__restrict__ W) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *P = reinterpret_cast<T *>(smem_raw);
   const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
+  const T *Ay = stage_table<T, TL>(P + mx * my, tb.WST[1], my * my);
+  const T *Ax = stage_table<T, TL>(P + mx * my + my * my, tb.WST[0], mx * mx);
   const int blk = blockIdx.x;
   const int s = blk / mz, c = blk - s * mz;
   T *Ws = W + ((size_t)s * mz + c) * mx * my;
-  for (int idx = threadIdx.x; idx < mx * my; idx += blockDim.x) P[idx] = Ws[idx];
+  batched_copy<T>(
+      mx * my, threadIdx.x, blockDim.x, [&](int idx) { return Ws[idx]; }, [&](int idx, T v) { P[idx] = v; });
   __syncthreads();
-  plane_contract<T, false, false>(P, mx, mx, my, tb.WS[1]);
-  plane_contract<T, true, false>(P, mx, my, mx, tb.WS[0]);
-  for (int idx = threadIdx.x; idx < mx * my; idx += blockDim.x) Ws[idx] = P[idx];
+  plane_contract<T, false>(P, mx, mx, my, Ay);
+  plane_contract<T, true>(P, mx, my, mx, Ax);
+  batched_copy<T>(
+      mx * my, threadIdx.x, blockDim.x, [&](int idx) { return P[idx]; }, [&](int idx, T v) { Ws[idx] = v; });
 }
 
 inline int nblk(int64_t n) { return (int)((n + 255) / 256); }
@@ -301,19 +346,30 @@ hipError_t launch_prolong_large(const ProlongLaunch<T, TC> &a, T *tmp, hipStream
 
 bool schwarz_is_wide(const int m[3]) { return std::max(m[0], std::max(m[1], m[2])) > 64; }
 
+template <typename T, bool TL>
+hipError_t launch_wide_tl(const SchwarzLaunch<T> &a, size_t s13, size_t s2, hipStream_t st) {
+  hipError_t e;
+  if ((e = allow_lds(wide_slab1<T, TL>, s13)) != hipSuccess) return e;
+  if ((e = allow_lds(wide_slab2<T, TL>, s2)) != hipSuccess) return e;
+  if ((e = allow_lds(wide_slab3<T, TL>, s13)) != hipSuccess) return e;
+  const int *m = a.tabs.m;
+  wide_slab1<T, TL><<<a.mesh.E * m[2], 256, s13, st>>>(a.mesh, a.n, a.tabs, a.r, a.C);
+  wide_slab2<T, TL><<<a.mesh.E * m[1], 256, s2, st>>>(a.mesh.E, a.tabs, a.ilam, a.C);
+  wide_slab3<T, TL><<<a.mesh.E * m[2], 256, s13, st>>>(a.mesh.E, a.tabs, a.C);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_schwarz_wide(const SchwarzLaunch<T> &a, hipStream_t st) {
   const int *m = a.tabs.m;
-  const size_t s13 = (size_t)m[0] * m[1] * sizeof(T), s2 = (size_t)m[0] * m[2] * sizeof(T);
-  if (std::max(s13, s2) > 150 * 1024) return hipErrorInvalidValue;
-  hipError_t e;
-  if ((e = allow_lds(wide_slab1<T>, s13)) != hipSuccess) return e;
-  if ((e = allow_lds(wide_slab2<T>, s2)) != hipSuccess) return e;
-  if ((e = allow_lds(wide_slab3<T>, s13)) != hipSuccess) return e;
-  wide_slab1<T><<<a.mesh.E * m[2], 256, s13, st>>>(a.mesh, a.n, a.tabs, a.r, a.C);
-  wide_slab2<T><<<a.mesh.E * m[1], 256, s2, st>>>(a.mesh.E, a.tabs, a.ilam, a.C);
-  wide_slab3<T><<<a.mesh.E * m[2], 256, s13, st>>>(a.mesh.E, a.tabs, a.C);
-  return hipGetLastError();
+  const size_t e = sizeof(T);
+  const size_t p13 = (size_t)m[0] * m[1] * e, p2 = (size_t)m[0] * m[2] * e;
+  if (std::max(p13, p2) > 150 * 1024) return hipErrorInvalidValue;
+  // with the tables: x and y (phases 1 and 3), z forward and backward (phase 2)
+  const size_t t13 = p13 + ((size_t)m[0] * m[0] + (size_t)m[1] * m[1]) * e;
+  const size_t t2 = p2 + 2 * (size_t)m[2] * m[2] * e;
+  if (std::max(t13, t2) <= 150 * 1024) return launch_wide_tl<T, true>(a, t13, t2, st);
+  return launch_wide_tl<T, false>(a, p13, p2, st);
 }
 
 template hipError_t launch_apply_large<double>(const ApplyLaunch<double> &, double *, hipStream_t);

@@ -5,12 +5,12 @@
 //
 // Phase 1 computes, for every element-centred subdomain, its weighted local
 // correction C[s] (m_x*m_y*m_z values, layout [c][b][a], x fastest) from the
-// gathered residual.  When the subdomain tensor fits LDS this is one
-// workgroup per subdomain: gather, three forward contractions, scaling, three
-// backward contractions, all in LDS with one thread per 1D line.  Larger
-// subdomains (the enlarged overlap of anisotropic meshes) use three kernels:
-// (x,y) forward per z-slab in LDS, z forward/scale/backward per line in
-// global memory, (y,x) backward per z-slab in LDS.
+// gathered residual.  Common shapes have a compile-time kernel (even-odd
+// transforms, several subdomains per workgroup).  Otherwise, when the
+// subdomain tensor fits LDS this is one workgroup per subdomain: gather,
+// three forward contractions, scaling, three backward contractions, all in
+// LDS with one thread per 1D line.  Larger subdomains (the enlarged overlap
+// of anisotropic meshes) use the three plane kernels of kernels_large.hip.
 //
 // Phase 2 (assembly) adds to every node the corrections of the (up to 27)
 // subdomains that contain it, in a fixed order, so the result is bitwise
@@ -78,6 +78,26 @@ __device__ __forceinline__ T gather_r(const Mesh &g, int n, const T *__restrict_
   return r[(size_t)e * n * n * n + ((gz - dz * n) * n + (gy - dy * n)) * n + (gx - dx * n)];
 }
 
+// for (i = tid; i < tot; i += nth) put(i, get(i)), with the loads of kGB
+// consecutive iterations issued before any of their values is used
+constexpr int kGB = 8;
+template <typename T, typename Get, typename Put>
+__device__ __forceinline__ void batched_copy(int tot, int tid, int nth, Get get, Put put) {
+  for (int i0 = tid; i0 < tot; i0 += kGB * nth) {
+    T val[kGB];
+#pragma unroll
+    for (int u = 0; u < kGB; ++u) {
+      const int i = i0 + u * nth;
+      val[u] = i < tot ? get(i) : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kGB; ++u) {
+      const int i = i0 + u * nth;
+      if (i < tot) put(i, val[u]);
+    }
+  }
+}
+
 template <typename T, int MB>
 __global__ void __launch_bounds__(512)
 schwarz_lds_kernel(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restrict__ C) {
@@ -90,10 +110,13 @@ schwarz_lds_kernel(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ r, T 
   const int ey = rest % g.ne[1], ez = rest / g.ne[1];
   const int tid = threadIdx.x, nth = blockDim.x;
   const int mxy = mx * my, mxyz = mxy * mz;
-  for (int idx = tid; idx < mxyz; idx += nth) {
-    const int a = idx % mx, bc = idx / mx, b = bc % my, c = bc / my;
-    t[bc * RX + a] = gather_r(g, n, r, ex, ey, ez, a - tb.no[0], b - tb.no[1], c - tb.no[2]);
-  }
+  batched_copy<T>(
+      mxyz, tid, nth,
+      [&](int idx) {
+        const int a = idx % mx, bc = idx / mx, b = bc % my, c = bc / my;
+        return gather_r(g, n, r, ex, ey, ez, a - tb.no[0], b - tb.no[1], c - tb.no[2]);
+      },
+      [&](int idx, T v) { t[(idx / mx) * RX + idx % mx] = v; });
   __syncthreads();
   for (int L = tid; L < my * mz; L += nth) line_fwd<T, MB>(t + L * RX, 1, mx, tb.S[0]);
   __syncthreads();
@@ -115,73 +138,9 @@ schwarz_lds_kernel(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ r, T 
   for (int L = tid; L < my * mz; L += nth) line_bwd<T, MB>(t + L * RX, 1, mx, tb.WS[0]);
   __syncthreads();
   T *Cs = C + (size_t)s * mxyz;
-  for (int idx = tid; idx < mxyz; idx += nth) {
-    const int a = idx % mx, bc = idx / mx;
-    Cs[idx] = t[bc * RX + a];
-  }
-}
-
-// slab phase 1: block (s, c): gather the z-slab c of subdomain s, x and y forward
-template <typename T, int MB>
-__global__ void __launch_bounds__(256)
-schwarz_slab1(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restrict__ W) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *t = reinterpret_cast<T *>(smem_raw);
-  const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
-  const int RX = mx | 1;
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int s = blk / mz, c = blk - s * mz;
-  const int ex = s % g.ne[0], rest = s / g.ne[0];
-  const int ey = rest % g.ne[1], ez = rest / g.ne[1];
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int mxy = mx * my;
-  for (int idx = tid; idx < mxy; idx += nth) {
-    const int a = idx % mx, b = idx / mx;
-    t[b * RX + a] = gather_r(g, n, r, ex, ey, ez, a - tb.no[0], b - tb.no[1], c - tb.no[2]);
-  }
-  __syncthreads();
-  for (int L = tid; L < my; L += nth) line_fwd<T, MB>(t + L * RX, 1, mx, tb.S[0]);
-  __syncthreads();
-  for (int L = tid; L < mx; L += nth) line_fwd<T, MB>(t + L, RX, my, tb.S[1]);
-  __syncthreads();
-  T *Ws = W + ((size_t)s * mz + c) * mxy;
-  for (int idx = tid; idx < mxy; idx += nth) Ws[idx] = t[(idx / mx) * RX + idx % mx];
-}
-
-// slab phase 2: one thread per z line (s, b, a) in global memory
-template <typename T, int MB>
-__global__ void __launch_bounds__(256)
-schwarz_slab2(int E, SchwarzTabs<T> tb, T *__restrict__ W) {
-  const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
-  const int mxy = mx * my;
-  const int64_t t = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)E * mxy) return;
-  const int s = (int)(t / mxy), ab = (int)(t - (int64_t)s * mxy);
-  const int a = ab % mx, b = ab / mx;
-  line_z<T, MB>(W + (size_t)s * mxy * mz + ab, mxy, mz, tb.S[2], tb.WS[2], tb.lam[2],
-                tb.lam[0][a] + tb.lam[1][b]);
-}
-
-// slab phase 3: block (s, c): y and x backward on the z-slab, in place
-template <typename T, int MB>
-__global__ void __launch_bounds__(256)
-schwarz_slab3(int E, SchwarzTabs<T> tb, T *__restrict__ W) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *t = reinterpret_cast<T *>(smem_raw);
-  const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
-  const int RX = mx | 1;
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int s = blk / mz, c = blk - s * mz;
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int mxy = mx * my;
-  T *Ws = W + ((size_t)s * mz + c) * mxy;
-  for (int idx = tid; idx < mxy; idx += nth) t[(idx / mx) * RX + idx % mx] = Ws[idx];
-  __syncthreads();
-  for (int L = tid; L < mx; L += nth) line_bwd<T, MB>(t + L, RX, my, tb.WS[1]);
-  __syncthreads();
-  for (int L = tid; L < my; L += nth) line_bwd<T, MB>(t + L * RX, 1, mx, tb.WS[0]);
-  __syncthreads();
-  for (int idx = tid; idx < mxy; idx += nth) Ws[idx] = t[(idx / mx) * RX + idx % mx];
+  batched_copy<T>(
+      mxyz, tid, nth, [&](int idx) { return t[(idx / mx) * RX + idx % mx]; },
+      [&](int idx, T v) { Cs[idx] = v; });
 }
 
 // u_out = u_in + sum over the subdomains containing the node, fixed order
@@ -197,24 +156,34 @@ schwarz_assemble(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ C, cons
   const int ey = rest % g.ne[1], ez = rest / g.ne[1];
   const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
   const size_t mxyz = (size_t)mx * my * mz;
-  T sum = 0;
+  // all candidate loads are issued before any is summed (a load consumed
+  // inside its branch would wait before the next is issued)
+  T v[27];
+#pragma unroll
   for (int dz = -1; dz <= 1; ++dz) {
     const int c = k - dz * n + tb.no[2];
-    if (c < 0 || c >= mz) continue;
     const int sz = wrap(ez + dz, g.ne[2]);
+#pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
       const int b = j - dy * n + tb.no[1];
-      if (b < 0 || b >= my) continue;
       const int sy = wrap(ey + dy, g.ne[1]);
+#pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         const int a = i - dx * n + tb.no[0];
-        if (a < 0 || a >= mx) continue;
-        const int sx = wrap(ex + dx, g.ne[0]);
-        sum += C[(size_t)elem_index(g, sx, sy, sz) * mxyz + (c * my + b) * mx + a];
+        const int q = (dz + 1) * 9 + (dy + 1) * 3 + dx + 1;
+        v[q] = 0;
+        if (c >= 0 && c < mz && b >= 0 && b < my && a >= 0 && a < mx) {
+          const int sx = wrap(ex + dx, g.ne[0]);
+          v[q] = C[(size_t)elem_index(g, sx, sy, sz) * mxyz + (c * my + b) * mx + a];
+        }
       }
     }
   }
-  u_out[idx] = (u_in ? u_in[idx] : (T)0) + sum;
+  const T base = u_in ? u_in[idx] : (T)0;
+  T sum = 0;
+#pragma unroll
+  for (int q = 0; q < 27; ++q) sum += v[q];
+  u_out[idx] = base + sum;
 }
 
 // ---- fixed-size fast path ----------------------------------------------
@@ -675,22 +644,6 @@ hipError_t launch_lds(const SchwarzLaunch<T> &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename T, int MB>
-hipError_t launch_slab(const SchwarzLaunch<T> &a, hipStream_t st) {
-  const int *m = a.tabs.m;
-  const size_t shm = (size_t)m[1] * (m[0] | 1) * sizeof(T);
-  const int nslab = a.mesh.E * m[2];
-  schwarz_slab1<T, MB><<<nslab, 256, shm, st>>>(a.mesh, a.n, a.tabs, a.r, a.C);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t nl = (int64_t)a.mesh.E * m[0] * m[1];
-  schwarz_slab2<T, MB><<<(int)((nl + 255) / 256), 256, 0, st>>>(a.mesh.E, a.tabs, a.C);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  schwarz_slab3<T, MB><<<nslab, 256, shm, st>>>(a.mesh.E, a.tabs, a.C);
-  return hipGetLastError();
-}
-
 }  // namespace
 
 bool schwarz_fits_lds(const int m[3], size_t eb) {
@@ -706,16 +659,13 @@ hipError_t launch_schwarz_local(const SchwarzLaunch<T> &a, hipStream_t st) {
   }
   const int *m = a.tabs.m;
   const int mmax = std::max(m[0], std::max(m[1], m[2]));
-  if (schwarz_is_wide(m)) return launch_schwarz_wide<T>(a, st);
   if (schwarz_fits_lds(m, sizeof(T))) {
     if (mmax <= 8) return launch_lds<T, 8>(a, st);
     if (mmax <= 16) return launch_lds<T, 16>(a, st);
     if (mmax <= 24) return launch_lds<T, 24>(a, st);
     return launch_lds<T, 32>(a, st);
   }
-  if (mmax <= 32) return launch_slab<T, 32>(a, st);
-  if (mmax <= 64) return launch_slab<T, 64>(a, st);
-  return hipErrorInvalidValue;
+  return launch_schwarz_wide<T>(a, st);
 }
 
 template <typename T>

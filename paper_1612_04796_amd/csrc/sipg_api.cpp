@@ -211,7 +211,7 @@ void upload_tables(sipg_ctx *c) {
   const sipg::HierarchyHost &H = c->H;
   Arena A;
   struct Off {
-    size_t Ld[3], M[3], DL[3], DR[3], S[3], WS[3], lam[3], EO[3], J, ilam, ilam_eo;
+    size_t Ld[3], M[3], DL[3], DR[3], S[3], WS[3], WST[3], lam[3], EO[3], J, ilam, ilam_eo;
   };
   std::vector<Off> o64(c->L + 1), o32(c->L + 1);
   auto put_level = [&](auto tag, std::vector<Off> &off) {
@@ -228,8 +228,12 @@ void upload_tables(sipg_ctx *c) {
           std::vector<double> WS(D.S);
           for (int a = 0; a < D.m; ++a)
             for (int j = 0; j < D.m; ++j) WS[a * D.m + j] *= D.wsub[a];
+          std::vector<double> WST(WS.size());
+          for (int a = 0; a < D.m; ++a)
+            for (int j = 0; j < D.m; ++j) WST[j * D.m + a] = WS[a * D.m + j];
           off[l].S[d] = A.put<T>(D.S);
           off[l].WS[d] = A.put<T>(WS);
+          off[l].WST[d] = A.put<T>(WST);
           off[l].lam[d] = A.put<T>(D.lam);
           off[l].EO[d] = A.put<T>(pack_even_odd(D));
         }
@@ -292,6 +296,7 @@ void upload_tables(sipg_ctx *c) {
           t.schwarz.WS[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].WS[d]);
           t.schwarz.lam[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].lam[d]);
           t.schwarz.EO[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].EO[d]);
+          t.schwarz.WST[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].WST[d]);
           t.schwarz.m[d] = lv.dir[d].m;
           t.schwarz.no[d] = lv.dir[d].no;
         }

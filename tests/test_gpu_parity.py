@@ -59,7 +59,7 @@ SCHWARZ = [
     ((5, 5, 5), (1.0, 1.0, 1.0), 8, "rel"),
     ((4, 3, 5), (2.0, 1.0, 0.5), 7, "rel"),
     ((4, 4, 4), (16.0, 1.0, 1.0), 4, "max"),     # full-neighbour overlap in y and z
-    ((3, 4, 4), (16.0, 1.0, 1.0), 16, "max"),    # large subdomains: the slab path
+    ((3, 4, 4), (16.0, 1.0, 1.0), 16, "max"),    # large subdomains: the plane kernels
     ((3, 3, 3), (1.0, 1.0, 1.0), 16, "rel"),
 ]
 
