@@ -201,7 +201,9 @@ struct FdmShape {
   static constexpr int TILE = MZ * MY * RX;
   static constexpr int L1 = MY * MZ, L2 = MX * MZ, L3 = MX * MY;
   static constexpr int LINES = L1 > L2 ? (L1 > L3 ? L1 : L3) : (L2 > L3 ? L2 : L3);
-  static constexpr int SPB = LINES >= 512 ? 1 : 512 / LINES;
+  // subdomains per workgroup: small workgroups (about three wavefronts)
+  // interleave best on a CU (measured against 2, 3 and 6 at m = 13)
+  static constexpr int SPB = LINES >= 192 ? 1 : 192 / LINES;
   static constexpr int MMAX = MX > MY ? (MX > MZ ? MX : MZ) : (MY > MZ ? MY : MZ);
   // lines per thread in every phase (more lines per thread share each table
   // entry but lower the occupancy, which costs more: measured slower)
@@ -515,51 +517,83 @@ schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restr
 // Candidate subdomains of a node along one direction: its own element's
 // (offset 0) and, where the overlap reaches it, the left or right
 // neighbour's.  With an overlap below half an element (2 NO < N) a node lies
-// in at most two subdomains along the direction, else in up to three.
+// in at most two subdomains along the direction, else in up to three.  The
+// candidates are kept as element-index steps (periodic wrap included), so
+// the subdomain index is the node's element index plus three steps.
 template <int N, int M>
 struct AxisCands {
   static constexpr int NO = (M - N) / 2;
   static constexpr int K = 2 * NO < N ? 2 : 3;
-  int s[K];     // subdomain coordinate along the direction
+  int step[K];  // element-index step to the candidate subdomain
   int a[K];     // local index of the node in that subdomain
   bool ok[K];
-  __device__ __forceinline__ AxisCands(int i, int ec, int ne) {
-    s[0] = ec;
+  // i: node index in the element; ec, ne: element coordinate and count along
+  // the direction; st: element-index stride of the direction
+  __device__ __forceinline__ AxisCands(int i, int ec, int ne, int st) {
+    const int sm = ec > 0 ? -st : (ne - 1) * st;       // to the left neighbour
+    const int sp = ec < ne - 1 ? st : -(ne - 1) * st;  // to the right neighbour
+    step[0] = 0;
     a[0] = i + NO;
     ok[0] = true;
     if constexpr (K == 2) {
       const bool left = i < NO;
-      s[1] = wrap(ec + (left ? -1 : 1), ne);
+      step[1] = left ? sm : sp;
       a[1] = left ? i + N + NO : i - N + NO;
       ok[1] = left || i >= N - NO;
     } else {
-      s[1] = wrap(ec - 1, ne);
+      step[1] = sm;
       a[1] = i + N + NO;
       ok[1] = a[1] < M;
-      s[2] = wrap(ec + 1, ne);
+      step[2] = sp;
       a[2] = i - N + NO;
       ok[2] = a[2] >= 0;
     }
   }
 };
 
-// Assembly with compile-time sizes: one thread per node (consecutive threads
-// on consecutive nodes of an element).  Every candidate load is issued before
-// any is summed (invalid candidates load nothing and count zero), then the
-// contributions are added in a fixed order.
+// Assembly with compile-time sizes: one thread per node, each workgroup
+// whole elements (EPB of them; for n >= 7 one, so the element, its
+// coordinates and its neighbour steps are uniform and live in scalar
+// registers) when an element has at most 1024 nodes, else 256 nodes per
+// workgroup.  Every candidate load is issued before any is summed (invalid
+// candidates load nothing and count zero), then the contributions are added
+// in a fixed order.  Offsets are 32-bit: the launcher checks that the
+// correction buffer has fewer than 2^31 entries.  (The index arithmetic is
+// what bounds this kernel: per node it once took about 200 vector
+// instructions, and FP32 ran no faster than FP64.)
+template <int N>
+struct AsmShape {
+  static constexpr int N3 = N * N * N;
+  static constexpr bool WHOLE = N3 <= 1024;
+  static constexpr int EPB = N3 >= 256 ? 1 : 256 / N3;
+  static constexpr int NTH = WHOLE ? (EPB * N3 + 63) / 64 * 64 : 256;
+};
+
 template <typename T, int N, int MX, int MY, int MZ>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(AsmShape<N>::NTH)
 schwarz_assemble_fixed(Mesh g, const T *__restrict__ C, const T *u_in, T *u_out) {
-  constexpr int N3 = N * N * N, VOL = MX * MY * MZ;
-  const int64_t idx = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (idx >= (int64_t)g.E * N3) return;
-  const int e = (int)(idx / N3), loc = (int)(idx - (int64_t)e * N3);
+  using Sh = AsmShape<N>;
+  constexpr int N3 = Sh::N3, VOL = MX * MY * MZ;
+  const int tid = threadIdx.x;
+  int e, loc;
+  if constexpr (Sh::WHOLE) {
+    const int le = tid / N3;
+    loc = tid - le * N3;
+    e = xcd_block(blockIdx.x, gridDim.x) * Sh::EPB + le;
+    if (le >= Sh::EPB || e >= g.E) return;
+  } else {
+    const int gi = xcd_block(blockIdx.x, gridDim.x) * Sh::NTH + tid;
+    if (gi >= g.E * N3) return;
+    e = gi / N3;
+    loc = gi - e * N3;
+  }
+  const int idx = e * N3 + loc;
   const int i = loc % N, j = (loc / N) % N, k = loc / (N * N);
   const int ex = e % g.ne[0], rest = e / g.ne[0];
   const int ey = rest % g.ne[1], ez = rest / g.ne[1];
-  const AxisCands<N, MX> cx(i, ex, g.ne[0]);
-  const AxisCands<N, MY> cy(j, ey, g.ne[1]);
-  const AxisCands<N, MZ> cz(k, ez, g.ne[2]);
+  const AxisCands<N, MX> cx(i, ex, g.ne[0], 1);
+  const AxisCands<N, MY> cy(j, ey, g.ne[1], g.ne[0]);
+  const AxisCands<N, MZ> cz(k, ez, g.ne[2], g.ne[0] * g.ne[1]);
   constexpr int KX = AxisCands<N, MX>::K, KY = AxisCands<N, MY>::K, KZ = AxisCands<N, MZ>::K;
   T v[KZ][KY][KX];
 #pragma unroll
@@ -570,8 +604,8 @@ schwarz_assemble_fixed(Mesh g, const T *__restrict__ C, const T *u_in, T *u_out)
       for (int xc = 0; xc < KX; ++xc) {
         v[zc][yc][xc] = 0;
         if (cz.ok[zc] && cy.ok[yc] && cx.ok[xc]) {
-          const int s = (cz.s[zc] * g.ne[1] + cy.s[yc]) * g.ne[0] + cx.s[xc];
-          v[zc][yc][xc] = C[(size_t)s * VOL + (cz.a[zc] * MY + cy.a[yc]) * MX + cx.a[xc]];
+          const int sub = e + cz.step[zc] + cy.step[yc] + cx.step[xc];
+          v[zc][yc][xc] = C[sub * VOL + (cz.a[zc] * MY + cy.a[yc]) * MX + cx.a[xc]];
         }
       }
   const T base = u_in ? u_in[idx] : (T)0;
@@ -587,8 +621,11 @@ schwarz_assemble_fixed(Mesh g, const T *__restrict__ C, const T *u_in, T *u_out)
 
 template <typename T, int N, int MX, int MY, int MZ>
 hipError_t launch_assemble_fixed(const SchwarzLaunch<T> &a, hipStream_t st) {
-  const int64_t tot = (int64_t)a.mesh.E * N * N * N;
-  schwarz_assemble_fixed<T, N, MX, MY, MZ><<<(int)((tot + 255) / 256), 256, 0, st>>>(a.mesh, a.C, a.u_in, a.u_out);
+  using Sh = AsmShape<N>;
+  if ((int64_t)a.mesh.E * MX * MY * MZ >= (int64_t)1 << 31) return hipErrorInvalidValue;
+  const int nblk = Sh::WHOLE ? (a.mesh.E + Sh::EPB - 1) / Sh::EPB
+                             : (int)(((int64_t)a.mesh.E * Sh::N3 + Sh::NTH - 1) / Sh::NTH);
+  schwarz_assemble_fixed<T, N, MX, MY, MZ><<<nblk, Sh::NTH, 0, st>>>(a.mesh, a.C, a.u_in, a.u_out);
   return hipGetLastError();
 }
 
@@ -672,8 +709,11 @@ template <typename T>
 hipError_t launch_schwarz_assemble(const SchwarzLaunch<T> &a, hipStream_t st) {
   {
     const int *m = a.tabs.m;
-#define SIPG_TRY(NN, AX, AY, AZ) \
-  if (a.n == NN && m[0] == AX && m[1] == AY && m[2] == AZ) return launch_assemble_fixed<T, NN, AX, AY, AZ>(a, st);
+    // the compile-time kernels use 32-bit offsets into the corrections
+    const bool small = (int64_t)a.mesh.E * m[0] * m[1] * m[2] < ((int64_t)1 << 31);
+#define SIPG_TRY(NN, AX, AY, AZ)                                                  \
+  if (small && a.n == NN && m[0] == AX && m[1] == AY && m[2] == AZ)             \
+    return launch_assemble_fixed<T, NN, AX, AY, AZ>(a, st);
     SIPG_FDM_SHAPES(SIPG_TRY)
 #undef SIPG_TRY
   }
