@@ -109,14 +109,10 @@ hipError_t launch_coarse(const CoarseLaunch &a, const TI *f0, double *u0, bool s
 // ---- vector kernels (kernels_vec.hip) -------------------------------------
 constexpr int kDotBlocks = 1024;
 // partial[b] = sum over block b of x[i]*y[i] (fixed partition, deterministic)
-template <typename T>
-hipError_t launch_dot_partials(const T *x, const T *y, int64_t n, double *partial, hipStream_t st);
+template <typename TX, typename TY>
+hipError_t launch_dot_partials(const TX *x, const TY *y, int64_t n, double *partial, hipStream_t st);
 // out[0] = scale * sum_{b<np} partial[b], reduced in a fixed order by one block
 hipError_t launch_finalize(const double *partial, int np, double scale, double *out, hipStream_t st);
-// two dot products at once: partial[b] = x.y, partial[kDotBlocks+b] = z.w
-template <typename T>
-hipError_t launch_dot2_partials(const T *x, const T *y, const T *z, const T *w, int64_t n,
-                                double *partial, hipStream_t st);
 // partial[b] = sum over block b of x[i], kDotBlocks blocks
 template <typename T>
 hipError_t launch_sum_partials(const T *x, int64_t n, double *partial, hipStream_t st);
@@ -130,13 +126,23 @@ hipError_t launch_fill(T *x, int64_t n, T v, hipStream_t st);
 
 // Flexible CG scalars live in device memory: see kernels_vec.hip.
 enum FcgScalar { FS_RZ = 0, FS_PQ = 1, FS_RR = 2, FS_ZQ = 3, FS_RZNEW = 4, FS_ALPHA = 5, FS_BETA = 6, FS_COUNT = 8 };
-// x += alpha p; r -= alpha q; partial = r.r   (alpha = s[RZ] / s[PQ])
-hipError_t launch_fcg_xr(double *x, double *r, const double *p, const double *q, int64_t n,
-                         double *s, double *partial, hipStream_t st);
-// beta = -alpha s[ZQ] / s[RZ]; s[RZ] = s[RZNEW]; p = z + beta p
-hipError_t launch_fcg_p(double *p, const double *z, int64_t n, double *s, hipStream_t st);
-// s[ZQ] and s[RZNEW] from the dot2 partials
+// One flexible-CG iteration is split so that no vector is read twice where
+// it can be avoided:
+//   r -= alpha q, partial = r.r, r32 = (float) r when given   (alpha = s[RZ] / s[PQ])
+hipError_t launch_fcg_r(double *r, const double *q, int64_t n, double *s, double *partial, float *r32,
+                        hipStream_t st);
+//   partial = z.q and r.z (z in the preconditioner's precision)
+template <typename TZ>
+hipError_t launch_fcg_dot2(const TZ *z, const double *q, const double *r, int64_t n, double *partial,
+                           hipStream_t st);
+//   s[ZQ], s[RZNEW] from those partials; beta = -alpha s[ZQ] / s[RZ]; s[RZ] = s[RZNEW]
 hipError_t launch_fcg_finalize2(const double *partial, double *s, hipStream_t st);
+//   x += alpha p (deferred from the residual update, when update_x); p = z + beta p
+template <typename TZ>
+hipError_t launch_fcg_xp(double *x, double *p, const TZ *z, int64_t n, const double *s, bool update_x,
+                         hipStream_t st);
+//   x += alpha p (before a convergence check of the true residual)
+hipError_t launch_fcg_x(double *x, const double *p, int64_t n, const double *s, hipStream_t st);
 
 // Fourier right-hand side: b = M f(nodes) (before mean removal)
 struct RhsLaunch {

@@ -19,14 +19,28 @@ __device__ __forceinline__ void chunk_of(int64_t n, int64_t &lo, int64_t &hi) {
   hi = lo + chunk < n ? lo + chunk : n;
 }
 
-template <typename T>
+// Streaming loops issue the loads of kUnroll iterations before using any,
+// and accumulate in a fixed order (deterministic).
+constexpr int kUnroll = 4;
+
+template <typename TX, typename TY>
 __global__ void __launch_bounds__(256)
-dot_partials(const T *__restrict__ x, const T *__restrict__ y, int64_t n, double *__restrict__ partial) {
+dot_partials(const TX *__restrict__ x, const TY *__restrict__ y, int64_t n, double *__restrict__ partial) {
   __shared__ double red[16];
   int64_t lo, hi;
   chunk_of(n, lo, hi);
   double s = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += (double)x[i] * (double)y[i];
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kUnroll * blockDim.x) {
+    double a[kUnroll], b[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = i0 + u * blockDim.x;
+      a[u] = i < hi ? (double)x[i] : 0.0;
+      b[u] = i < hi ? (double)y[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) s += a[u] * b[u];
+  }
   s = block_reduce_sum(s, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
@@ -41,27 +55,6 @@ sum_partials_kernel(const T *__restrict__ x, int64_t n, double *__restrict__ par
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += (double)x[i];
   s = block_reduce_sum(s, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256)
-dot2_partials(const T *__restrict__ x, const T *__restrict__ y, const T *__restrict__ z,
-              const T *__restrict__ w, int64_t n, double *__restrict__ partial) {
-  __shared__ double red[16];
-  int64_t lo, hi;
-  chunk_of(n, lo, hi);
-  double s = 0.0, t = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    s += (double)x[i] * (double)y[i];
-    t += (double)z[i] * (double)w[i];
-  }
-  s = block_reduce_sum(s, red);
-  __syncthreads();
-  t = block_reduce_sum(t, red);
-  if (threadIdx.x == 0) {
-    partial[blockIdx.x] = s;
-    partial[gridDim.x + blockIdx.x] = t;
-  }
 }
 
 __global__ void __launch_bounds__(1024)
@@ -91,27 +84,6 @@ __global__ void __launch_bounds__(256) fill_kernel(T *__restrict__ x, int64_t n,
   if (i < n) x[i] = v;
 }
 
-__global__ void __launch_bounds__(256)
-fcg_xr_kernel(double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
-              const double *__restrict__ q, int64_t n, double *s, double *__restrict__ partial) {
-  __shared__ double red[16];
-  const double alpha = s[FS_RZ] / s[FS_PQ];
-  int64_t lo, hi;
-  chunk_of(n, lo, hi);
-  double acc = 0.0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    acc += ri * ri;
-  }
-  acc = block_reduce_sum(acc, red);
-  if (threadIdx.x == 0) {
-    partial[blockIdx.x] = acc;
-    if (blockIdx.x == 0) s[FS_ALPHA] = alpha;
-  }
-}
-
 __global__ void __launch_bounds__(1024) fcg_finalize2_kernel(const double *__restrict__ partial, double *s) {
   __shared__ double red[16];
   double a = 0.0, b = 0.0;
@@ -131,10 +103,92 @@ __global__ void __launch_bounds__(1024) fcg_finalize2_kernel(const double *__res
   }
 }
 
+// alpha = s[RZ] / s[PQ]; r -= alpha q; partial = r.r; r32 = (float) r when
+// given (the input of a single-precision preconditioner)
 __global__ void __launch_bounds__(256)
-fcg_p_kernel(double *__restrict__ p, const double *__restrict__ z, int64_t n, const double *__restrict__ s) {
+fcg_r_kernel(double *__restrict__ r, const double *__restrict__ q, int64_t n, double *s,
+             double *__restrict__ partial, float *__restrict__ r32) {
+  __shared__ double red[16];
+  const double alpha = s[FS_RZ] / s[FS_PQ];
+  int64_t lo, hi;
+  chunk_of(n, lo, hi);
+  double acc = 0.0;
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kUnroll * blockDim.x) {
+    double rv[kUnroll], qv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = i0 + u * blockDim.x;
+      rv[u] = i < hi ? r[i] : 0.0;
+      qv[u] = i < hi ? q[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = i0 + u * blockDim.x;
+      const double ri = rv[u] - alpha * qv[u];
+      acc += ri * ri;
+      if (i < hi) {
+        r[i] = ri;
+        if (r32) r32[i] = (float)ri;
+      }
+    }
+  }
+  acc = block_reduce_sum(acc, red);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = acc;
+    if (blockIdx.x == 0) s[FS_ALPHA] = alpha;
+  }
+}
+
+// partial[b] = z.q, partial[kDotBlocks + b] = r.z over block b
+template <typename TZ>
+__global__ void __launch_bounds__(256)
+fcg_dot2_kernel(const TZ *__restrict__ z, const double *__restrict__ q, const double *__restrict__ r, int64_t n,
+                double *__restrict__ partial) {
+  __shared__ double red[16];
+  int64_t lo, hi;
+  chunk_of(n, lo, hi);
+  double a = 0.0, b = 0.0;
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kUnroll * blockDim.x) {
+    double zv[kUnroll], qv[kUnroll], rv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = i0 + u * blockDim.x;
+      zv[u] = i < hi ? (double)z[i] : 0.0;
+      qv[u] = i < hi ? q[i] : 0.0;
+      rv[u] = i < hi ? r[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      a += zv[u] * qv[u];
+      b += rv[u] * zv[u];
+    }
+  }
+  a = block_reduce_sum(a, red);
+  __syncthreads();
+  b = block_reduce_sum(b, red);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = a;
+    partial[gridDim.x + blockIdx.x] = b;
+  }
+}
+
+// x += alpha p (when update_x); p = z + beta p
+template <typename TZ>
+__global__ void __launch_bounds__(256)
+fcg_xp_kernel(double *__restrict__ x, double *__restrict__ p, const TZ *__restrict__ z, int64_t n,
+              const double *__restrict__ s, int update_x) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = z[i] + s[FS_BETA] * p[i];
+  if (i >= n) return;
+  const double pi = p[i];
+  if (update_x) x[i] += s[FS_ALPHA] * pi;
+  p[i] = (double)z[i] + s[FS_BETA] * pi;
+}
+
+// x += alpha p
+__global__ void __launch_bounds__(256)
+fcg_x_kernel(double *__restrict__ x, const double *__restrict__ p, int64_t n, const double *__restrict__ s) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += s[FS_ALPHA] * p[i];
 }
 
 __global__ void __launch_bounds__(256) rhs_kernel(RhsLaunch a, double *__restrict__ b) {
@@ -162,22 +216,15 @@ inline int nblocks(int64_t n) { return (int)((n + 255) / 256); }
 
 }  // namespace
 
-template <typename T>
-hipError_t launch_dot_partials(const T *x, const T *y, int64_t n, double *partial, hipStream_t st) {
-  dot_partials<T><<<kDotBlocks, 256, 0, st>>>(x, y, n, partial);
+template <typename TX, typename TY>
+hipError_t launch_dot_partials(const TX *x, const TY *y, int64_t n, double *partial, hipStream_t st) {
+  dot_partials<TX, TY><<<kDotBlocks, 256, 0, st>>>(x, y, n, partial);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_sum_partials(const T *x, int64_t n, double *partial, hipStream_t st) {
   sum_partials_kernel<T><<<kDotBlocks, 256, 0, st>>>(x, n, partial);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_dot2_partials(const T *x, const T *y, const T *z, const T *w, int64_t n,
-                                double *partial, hipStream_t st) {
-  dot2_partials<T><<<kDotBlocks, 256, 0, st>>>(x, y, z, w, n, partial);
   return hipGetLastError();
 }
 
@@ -207,9 +254,9 @@ hipError_t launch_fill(T *x, int64_t n, T v, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_fcg_xr(double *x, double *r, const double *p, const double *q, int64_t n, double *s,
-                         double *partial, hipStream_t st) {
-  fcg_xr_kernel<<<kDotBlocks, 256, 0, st>>>(x, r, p, q, n, s, partial);
+hipError_t launch_fcg_r(double *r, const double *q, int64_t n, double *s, double *partial, float *r32,
+                        hipStream_t st) {
+  fcg_r_kernel<<<kDotBlocks, 256, 0, st>>>(r, q, n, s, partial, r32);
   return hipGetLastError();
 }
 
@@ -218,8 +265,22 @@ hipError_t launch_fcg_finalize2(const double *partial, double *s, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch_fcg_p(double *p, const double *z, int64_t n, double *s, hipStream_t st) {
-  fcg_p_kernel<<<nblocks(n), 256, 0, st>>>(p, z, n, s);
+template <typename TZ>
+hipError_t launch_fcg_dot2(const TZ *z, const double *q, const double *r, int64_t n, double *partial,
+                           hipStream_t st) {
+  fcg_dot2_kernel<TZ><<<kDotBlocks, 256, 0, st>>>(z, q, r, n, partial);
+  return hipGetLastError();
+}
+
+template <typename TZ>
+hipError_t launch_fcg_xp(double *x, double *p, const TZ *z, int64_t n, const double *s, bool update_x,
+                         hipStream_t st) {
+  fcg_xp_kernel<TZ><<<nblocks(n), 256, 0, st>>>(x, p, z, n, s, update_x ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_x(double *x, const double *p, int64_t n, const double *s, hipStream_t st) {
+  fcg_x_kernel<<<nblocks(n), 256, 0, st>>>(x, p, n, s);
   return hipGetLastError();
 }
 
@@ -229,10 +290,18 @@ hipError_t launch_rhs(const RhsLaunch &a, double *b, hipStream_t st) {
   return hipGetLastError();
 }
 
-template hipError_t launch_dot_partials<double>(const double *, const double *, int64_t, double *, hipStream_t);
-template hipError_t launch_dot_partials<float>(const float *, const float *, int64_t, double *, hipStream_t);
-template hipError_t launch_dot2_partials<double>(const double *, const double *, const double *,
-                                                 const double *, int64_t, double *, hipStream_t);
+template hipError_t launch_dot_partials<double, double>(const double *, const double *, int64_t, double *,
+                                                        hipStream_t);
+template hipError_t launch_dot_partials<double, float>(const double *, const float *, int64_t, double *,
+                                                       hipStream_t);
+template hipError_t launch_fcg_dot2<double>(const double *, const double *, const double *, int64_t, double *,
+                                            hipStream_t);
+template hipError_t launch_fcg_dot2<float>(const float *, const double *, const double *, int64_t, double *,
+                                           hipStream_t);
+template hipError_t launch_fcg_xp<double>(double *, double *, const double *, int64_t, const double *, bool,
+                                          hipStream_t);
+template hipError_t launch_fcg_xp<float>(double *, double *, const float *, int64_t, const double *, bool,
+                                         hipStream_t);
 template hipError_t launch_sub_scalar<double>(double *, int64_t, const double *, hipStream_t);
 template hipError_t launch_sub_scalar<float>(float *, int64_t, const double *, hipStream_t);
 template hipError_t launch_sum_partials<double>(const double *, int64_t, double *, hipStream_t);

@@ -194,7 +194,7 @@ bool advance(sipg_server *s, Request *r) {
         return false;
       }
       sipg::detail::fcg_first_precond(r->ctx);
-      sipg::detail::fcg_apply_update(r->ctx, r->x);
+      sipg::detail::fcg_apply_update(r->ctx);
       r->iters = 1;
       r->phase = PH_ITER;
     } else if (r->phase == PH_ITER) {
@@ -215,8 +215,8 @@ bool advance(sipg_server *s, Request *r) {
         finish(s, r, SIPG_REQ_FAILED, "tolerance not reached");
         return false;
       } else {
-        sipg::detail::fcg_precond_update(r->ctx);
-        sipg::detail::fcg_apply_update(r->ctx, r->x);
+        sipg::detail::fcg_precond_update(r->ctx, r->x);
+        sipg::detail::fcg_apply_update(r->ctx);
         r->iters += 1;
       }
     } else {  // PH_CONFIRM
@@ -231,8 +231,8 @@ bool advance(sipg_server *s, Request *r) {
         return false;
       }
       sipg::detail::fcg_restart_from_true(r->ctx);
-      sipg::detail::fcg_precond_update(r->ctx);
-      sipg::detail::fcg_apply_update(r->ctx, r->x);
+      sipg::detail::fcg_precond_update(r->ctx, r->x);
+      sipg::detail::fcg_apply_update(r->ctx);
       r->iters += 1;
       r->phase = PH_ITER;
     }

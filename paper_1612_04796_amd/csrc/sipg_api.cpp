@@ -99,6 +99,7 @@ struct sipg_ctx {
   bool use_graph = false;               // replay the preconditioner from a captured graph
   hipGraphExec_t precond_graph = nullptr;
   bool graph_failed = false;
+  bool x_pending = false;  // flexible CG: x += alpha p not yet applied
 
   template <typename T>
   T *alloc(size_t count) {
@@ -463,22 +464,33 @@ void precond_body(sipg_ctx *c, const double *r, double *z) {
   check(sipg::launch_convert<double, float>(w.uL, z, N, c->stream), "precond cast");
 }
 
-// The preconditioner of the flexible CG vectors (fixed pointers) is captured
-// once into a HIP graph and replayed when the context asks for it; the graph
-// holds kernel nodes only.
-void precond_impl(sipg_ctx *c, const double *r, double *z) {
-  const bool graphable = c->use_graph && !c->graph_failed && c->stream != nullptr && r == c->cg_r && z == c->cg_z;
+void precond_impl(sipg_ctx *c, const double *r, double *z) { precond_body(c, r, z); }
+
+// The preconditioner inside the flexible CG: one V-cycle from zero on the
+// context's own vectors.  FP64: from cg_r into cg_z.  FP32: from the single
+// precision copy of r (w32.fL, written by the residual update) into w32.uL,
+// which the CG kernels read directly, so no conversion passes are needed.
+void fcg_precond_body(sipg_ctx *c) {
+  if (c->H.prm.precond_bits == 64) vcycle_impl<double>(c, c->cg_z, c->cg_r, true, nullptr);
+  else vcycle_impl<float>(c, c->w32.uL, c->w32.fL, true, nullptr);
+}
+
+// Captured once into a HIP graph (kernel nodes only) and replayed when the
+// context asks for it.
+void fcg_precond(sipg_ctx *c) {
+  const bool graphable = c->use_graph && !c->graph_failed && c->stream != nullptr;
   if (!graphable) {
-    precond_body(c, r, z);
+    fcg_precond_body(c);
     return;
   }
   if (!c->precond_graph) {
+    // every work buffer exists before the capture (no allocation inside it)
     ensure_work<double>(c);
     if (c->H.prm.precond_bits == 32) ensure_work<float>(c);
     check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "graph capture");
     hipGraph_t g = nullptr;
     try {
-      precond_body(c, r, z);
+      fcg_precond_body(c);
     } catch (...) {
       (void)hipStreamEndCapture(c->stream, &g);
       if (g) (void)hipGraphDestroy(g);
@@ -491,7 +503,7 @@ void precond_impl(sipg_ctx *c, const double *r, double *z) {
     if (e != hipSuccess) {
       c->precond_graph = nullptr;
       c->graph_failed = true;
-      precond_body(c, r, z);
+      fcg_precond_body(c);
       return;
     }
   }
@@ -508,12 +520,12 @@ void read_scalars(sipg_ctx *c) {
 
 // ||x||^2 into scal[slot]
 void norm2(sipg_ctx *c, const double *x, int64_t n, int slot) {
-  check(sipg::launch_dot_partials<double>(x, x, n, c->partial, c->stream), "dot");
+  check(sipg::launch_dot_partials<double, double>(x, x, n, c->partial, c->stream), "dot");
   check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + slot, c->stream), "dot");
 }
 
 void dot(sipg_ctx *c, const double *x, const double *y, int64_t n, int slot) {
-  check(sipg::launch_dot_partials<double>(x, y, n, c->partial, c->stream), "dot");
+  check(sipg::launch_dot_partials<double, double>(x, y, n, c->partial, c->stream), "dot");
   check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + slot, c->stream), "dot");
 }
 
@@ -580,7 +592,7 @@ int pcg_solve_impl(sipg_ctx *c, double *x, const double *b, double rtol, int max
   if (r0 == 0.0) return SIPG_OK;
   sipg::detail::fcg_first_precond(c);
   for (int it = 1; it <= maxit; ++it) {
-    sipg::detail::fcg_apply_update(c, x);
+    sipg::detail::fcg_apply_update(c);
     check(hipStreamSynchronize(c->stream), "fcg");
     const double pq = c->host_scal[sipg::FS_PQ];
     double rn = std::sqrt(c->host_scal[sipg::FS_RR]);
@@ -604,7 +616,7 @@ int pcg_solve_impl(sipg_ctx *c, double *x, const double *b, double rtol, int max
     }
     c->hist.push_back(rn);
     if (relres) *relres = rn / r0;
-    sipg::detail::fcg_precond_update(c);
+    sipg::detail::fcg_precond_update(c, x);
   }
   return fail(SIPG_ENOCONV, "pcg_solve: tolerance not reached");
 }
@@ -650,23 +662,40 @@ void fcg_start(sipg_ctx *c, double *x, const double *b) {
 
 void fcg_first_precond(sipg_ctx *c) {
   const int64_t N = level_ndof(c->H, c->L);
-  precond_impl(c, c->cg_r, c->cg_z);
-  dot(c, c->cg_r, c->cg_z, N, sipg::FS_RZ);
-  check(sipg::launch_convert<double, double>(c->cg_z, c->cg_p, N, c->stream), "copy");
+  const bool single = c->H.prm.precond_bits == 32;
+  if (single) {
+    ensure_work<float>(c);
+    check(sipg::launch_convert<float, double>(c->cg_r, c->w32.fL, N, c->stream), "precond cast");
+  }
+  fcg_precond(c);
+  if (single) {
+    check(sipg::launch_dot_partials<double, float>(c->cg_r, c->w32.uL, N, c->partial, c->stream), "dot");
+    check(sipg::launch_convert<double, float>(c->w32.uL, c->cg_p, N, c->stream), "copy");
+  } else {
+    check(sipg::launch_dot_partials<double, double>(c->cg_r, c->cg_z, N, c->partial, c->stream), "dot");
+    check(sipg::launch_convert<double, double>(c->cg_z, c->cg_p, N, c->stream), "copy");
+  }
+  check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + sipg::FS_RZ, c->stream), "dot");
+  c->x_pending = false;
 }
 
-void fcg_apply_update(sipg_ctx *c, double *x) {
+void fcg_apply_update(sipg_ctx *c) {
   const int64_t N = level_ndof(c->H, c->L);
   op_apply<double>(c, c->L, c->cg_p, c->cg_q, c->partial);
   check(sipg::launch_finalize(c->partial, sipg::apply_num_blocks(c->mesh.E, c->t64[c->L].n), 1.0,
                               c->scal + sipg::FS_PQ, c->stream),
         "dot");
-  check(sipg::launch_fcg_xr(x, c->cg_r, c->cg_p, c->cg_q, N, c->scal, c->partial, c->stream), "fcg update");
+  float *r32 = c->H.prm.precond_bits == 32 ? c->w32.fL : nullptr;
+  check(sipg::launch_fcg_r(c->cg_r, c->cg_q, N, c->scal, c->partial, r32, c->stream), "fcg update");
   check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + sipg::FS_RR, c->stream), "dot");
+  c->x_pending = true;
   copy_scalars_async(c);
 }
 
-void fcg_confirm(sipg_ctx *c, const double *x, const double *b) {
+void fcg_confirm(sipg_ctx *c, double *x, const double *b) {
+  const int64_t N = level_ndof(c->H, c->L);
+  if (c->x_pending) check(sipg::launch_fcg_x(x, c->cg_p, N, c->scal, c->stream), "fcg update");
+  c->x_pending = false;
   residual_norm2(c, x, b, c->cg_q, sipg::FS_RR);
   copy_scalars_async(c);
 }
@@ -674,15 +703,24 @@ void fcg_confirm(sipg_ctx *c, const double *x, const double *b) {
 void fcg_restart_from_true(sipg_ctx *c) {
   const int64_t N = level_ndof(c->H, c->L);
   check(sipg::launch_convert<double, double>(c->cg_q, c->cg_r, N, c->stream), "copy");
+  if (c->H.prm.precond_bits == 32)
+    check(sipg::launch_convert<float, double>(c->cg_r, c->w32.fL, N, c->stream), "precond cast");
   op_apply<double>(c, c->L, c->cg_p, c->cg_q, nullptr);
 }
 
-void fcg_precond_update(sipg_ctx *c) {
+void fcg_precond_update(sipg_ctx *c, double *x) {
   const int64_t N = level_ndof(c->H, c->L);
-  precond_impl(c, c->cg_r, c->cg_z);
-  check(sipg::launch_dot2_partials<double>(c->cg_z, c->cg_q, c->cg_r, c->cg_z, N, c->partial, c->stream), "dot2");
-  check(sipg::launch_fcg_finalize2(c->partial, c->scal, c->stream), "dot2");
-  check(sipg::launch_fcg_p(c->cg_p, c->cg_z, N, c->scal, c->stream), "fcg update");
+  fcg_precond(c);
+  if (c->H.prm.precond_bits == 32) {
+    check(sipg::launch_fcg_dot2<float>(c->w32.uL, c->cg_q, c->cg_r, N, c->partial, c->stream), "dot2");
+    check(sipg::launch_fcg_finalize2(c->partial, c->scal, c->stream), "dot2");
+    check(sipg::launch_fcg_xp<float>(x, c->cg_p, c->w32.uL, N, c->scal, c->x_pending, c->stream), "fcg update");
+  } else {
+    check(sipg::launch_fcg_dot2<double>(c->cg_z, c->cg_q, c->cg_r, N, c->partial, c->stream), "dot2");
+    check(sipg::launch_fcg_finalize2(c->partial, c->scal, c->stream), "dot2");
+    check(sipg::launch_fcg_xp<double>(x, c->cg_p, c->cg_z, N, c->scal, c->x_pending, c->stream), "fcg update");
+  }
+  c->x_pending = false;
 }
 
 const double *host_scalars(const sipg_ctx *c) { return c->host_scal; }

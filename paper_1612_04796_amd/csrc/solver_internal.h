@@ -18,14 +18,15 @@ namespace detail {
 void fcg_start(sipg_ctx *c, double *x, const double *b);
 // z = B r, rz = r.z, p = z
 void fcg_first_precond(sipg_ctx *c);
-// q = A p, p.q (FS_PQ), x += alpha p, r -= alpha q, ||r||^2 (FS_RR)
-void fcg_apply_update(sipg_ctx *c, double *x);
-// ||b - A x||^2 (FS_RR), the true residual kept in q
-void fcg_confirm(sipg_ctx *c, const double *x, const double *b);
+// q = A p, p.q (FS_PQ), r -= alpha q, ||r||^2 (FS_RR); the update
+// x += alpha p is deferred to the next call that is given x
+void fcg_apply_update(sipg_ctx *c);
+// x += alpha p if pending, then ||b - A x||^2 (FS_RR), the true residual kept in q
+void fcg_confirm(sipg_ctx *c, double *x, const double *b);
 // r = true residual, q = A p again
 void fcg_restart_from_true(sipg_ctx *c);
-// z = B r, beta = -alpha (z.q) / rz, rz = r.z, p = z + beta p
-void fcg_precond_update(sipg_ctx *c);
+// z = B r, beta = -alpha (z.q) / rz, rz = r.z, x += alpha p if pending, p = z + beta p
+void fcg_precond_update(sipg_ctx *c, double *x);
 
 const double *host_scalars(const sipg_ctx *c);
 hipStream_t ctx_stream(const sipg_ctx *c);
