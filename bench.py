@@ -118,6 +118,30 @@ def cpu_baseline(wl, cycles, k, phi, amp):
     }
 
 
+def fcg_timing(wl, bits, b, steps, warmup):
+    """Flexible CG from x0 = 0 to 1e-10 on workload wl with the given
+    preconditioner precision: mean wall time over `steps` solves."""
+    import torch
+    from paper_1612_04796_amd import sipg
+    s = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
+                    smooth_growth=wl.growth, precond_bits=bits)
+    x = torch.zeros_like(b)
+    for _ in range(max(1, warmup)):
+        x.zero_()
+        s.pcg_solve(x, b, 1e-10, 200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x.zero_()
+        it, rr = s.pcg_solve(x, b, 1e-10, 200)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s.close()
+    log(f"FCG {wl.name}, FP{bits} preconditioner: {1e3 * el / steps:.3f} ms/solve, {it} iterations")
+    return {"unknowns_per_s": wl.ndof * steps / el, "ms_per_solve": 1e3 * el / steps,
+            "iterations": it, "final_relres": rr}
+
+
 def serving_run(nreq, seed, log_every=4):
     """Serving stream: heterogeneous requests (4^3..24^3 elements, P in
     {2,4,8,16,32}, aspect ratio 1..8, "max" overlap, FP32-preconditioned
@@ -206,6 +230,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cube16_p8_rel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the 32^3, P=7 mixed-precision solves")
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel timing")
     ap.add_argument("--serving-requests", type=int, default=24,
                     help="requests of the serving stream run after the main measurement (0 = skip)")
@@ -294,23 +319,25 @@ def main():
     detail = {"kernels_ms_per_launch": kern, "launches_per_solve": per_solve,
               "iterations": cyc, "final_relres": rr}
     for bits in (64, 32):
-        s2 = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
-                         smooth_growth=wl.growth, precond_bits=bits)
-        for _ in range(max(1, args.warmup)):
-            x.zero_()
-            s2.pcg_solve(x, b, 1e-10, 200)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            x.zero_()
-            it2, rr2 = s2.pcg_solve(x, b, 1e-10, 200)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        detail[f"fcg_precond_fp{bits}"] = {"unknowns_per_s": N * args.steps / el,
-                                           "ms_per_solve": 1e3 * el / args.steps,
-                                           "iterations": it2, "final_relres": rr2}
-        log(f"FCG, FP{bits} preconditioner: {1e3 * el / args.steps:.3f} ms/solve, {it2} iterations")
-        s2.close()
+        detail[f"fcg_precond_fp{bits}"] = fcg_timing(wl, bits, b, args.steps, args.warmup)
+    # ---- mixed precision at the 32^3, P = 7 workload (16.8M unknowns)
+    if not args.no_mixed:
+        wl4 = WORKLOADS["cube32_p7_rel"]
+        s4 = sipg.Solver(ne=wl4.ne, length=wl4.length, P=wl4.P, overlap=wl4.overlap, omega=wl4.omega,
+                         smooth_growth=wl4.growth)
+        b4 = torch.zeros(s4.ndof(), dtype=torch.float64, device="cuda")
+        k4, phi4, amp4 = fourier_modes(0, wl4.kmax)
+        s4.rhs_fourier(k4, phi4, amp4, b4)
+        s4.close()
+        mixed = {"workload": wl4.name, "ndof": wl4.ndof}
+        for bits in (64, 32):
+            mixed[f"fcg_precond_fp{bits}"] = fcg_timing(wl4, bits, b4, args.steps, args.warmup)
+        mixed["speedup_fp32_over_fp64"] = (mixed["fcg_precond_fp64"]["ms_per_solve"]
+                                           / mixed["fcg_precond_fp32"]["ms_per_solve"])
+        detail["mixed_precision"] = mixed
+        log(f"mixed precision at {wl4.name}: FP32 preconditioner {mixed['speedup_fp32_over_fp64']:.2f}x "
+            f"the FP64 one")
+        del b4
 
     if args.serving_requests > 0:
         log("serving stream ...")
