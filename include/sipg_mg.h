@@ -59,10 +59,10 @@ typedef enum {
 typedef enum { SIPG_OVL_MIN = 0, SIPG_OVL_REL = 1, SIPG_OVL_MAX = 2 } sipg_overlap_mode;
 
 typedef struct {
-  int32_t ne[3];          /* elements per direction (x, y, z); >= 3, and >= 4 in a
+  int32_t ne[3];          /* elements per direction (x, y, z); 3..48, and >= 4 in a
                              direction whose subdomain takes whole neighbours      */
   double len[3];          /* domain lengths lx, ly, lz > 0                         */
-  int32_t P;              /* polynomial order, 1..16                               */
+  int32_t P;              /* polynomial order, 1..16 or 32                         */
   double penalty;         /* c_mu: mu_d = c_mu P_l (P_l + 1) / h_d on level l;
                              must exceed 1/2 (the stability threshold); 1.0 is
                              the paper's setting read as twice the threshold      */

@@ -392,11 +392,10 @@ std::string validate(const sipg_params &p) {
     return "need nsmooth_pre, nsmooth_post >= 0 with at least one smoothing step";
   if (p.smooth_growth < 1 || p.smooth_growth > 8) return "smooth_growth must be in 1..8";
   if (p.precond_bits != 64 && p.precond_bits != 32) return "precond_bits must be 64 or 32";
-  // the coarse solve holds two (y, x) and two (z, x) planes of the level-0
-  // tensor (2 ne_d nodes per direction) in 150 KiB of LDS
-  if (2.0 * (2 * p.ne[0]) * (2 * p.ne[1]) * sizeof(double) > 150 * 1024 ||
-      2.0 * (2 * p.ne[0]) * (2 * p.ne[2]) * sizeof(double) > 150 * 1024)
-    return "mesh too large for the coarse solve (ne[0] * ne[1] and ne[0] * ne[2] at most 2400)";
+  // the coarse solve holds 2D planes of the level-0 tensor (2 ne_d nodes
+  // per direction) in LDS and at most 12 rows of a plane per thread
+  for (int d = 0; d < 3; ++d)
+    if (p.ne[d] > 48) return "ne[d] must be at most 48 (the level-0 planes of the coarse solve)";
   const int64_t E = (int64_t)p.ne[0] * p.ne[1] * p.ne[2];
   if (E * (int64_t)(p.P + 1) * (p.P + 1) * (p.P + 1) > (int64_t)1 << 31)
     return "problem too large (more than 2^31 unknowns)";
