@@ -398,7 +398,9 @@ void op_fill_zero(sipg_ctx *c, T *x, int64_t n) {
 // zero_start it is treated as zero.  r_top, if given, is f - A uL already
 // computed for the first pre-smoothing step.
 template <typename T>
-void vcycle_impl(sipg_ctx *c, T *uL, const T *fL, bool zero_start, const T *r_top) {
+void vcycle_impl(sipg_ctx *c, T *uL, const T *fL, bool zero_start, const T *r_top, T *u_out = nullptr) {
+  // u_out (optional): the cycle reads the top-level iterate from uL and
+  // writes the new one to u_out, leaving uL untouched
   ensure_work<T>(c);
   Work<T> &w = work_of<T>(c);
   const int L = c->L;
@@ -409,21 +411,24 @@ void vcycle_impl(sipg_ctx *c, T *uL, const T *fL, bool zero_start, const T *r_to
     for (int k = l; k < L; ++k) s *= growth;
     return s;
   };
+  T *top = u_out ? u_out : uL;
   if (L == 0) {
     check(sipg::launch_coarse<T>(c->coarse, fL, c->u0, true, c->stream), "coarse");
-    check(sipg::launch_convert<T, double>(c->u0, uL, level_ndof(H, 0), c->stream), "coarse copy");
+    check(sipg::launch_convert<T, double>(c->u0, top, level_ndof(H, 0), c->stream), "coarse copy");
     return;
   }
   for (int l = L; l >= 1; --l) {
-    T *ul = (l == L) ? uL : w.u[l];
+    T *ul = (l == L) ? top : w.u[l];
     const T *fl = (l == L) ? fL : w.f[l];
     const bool zero = (l < L) || zero_start;
     const int ns = nsteps(H.prm.nsmooth_pre, l);
+    if (l == L && u_out && !zero && (ns == 0 || !r_top))
+      check(sipg::launch_convert<T, T>(uL, u_out, level_ndof(H, L), c->stream), "copy");
     for (int s = 0; s < ns; ++s) {
       if (zero && s == 0) {
         op_schwarz<T>(c, l, fl, nullptr, ul);
       } else if (s == 0 && l == L && r_top) {
-        op_schwarz<T>(c, l, r_top, ul, ul);
+        op_schwarz<T>(c, l, r_top, u_out ? uL : ul, ul);
       } else {
         op_residual<T>(c, l, ul, fl, w.r);
         op_schwarz<T>(c, l, w.r, ul, ul);
@@ -434,7 +439,7 @@ void vcycle_impl(sipg_ctx *c, T *uL, const T *fL, bool zero_start, const T *r_to
   }
   check(sipg::launch_coarse<T>(c->coarse, w.f[0], c->u0, false, c->stream), "coarse");
   for (int l = 1; l <= L; ++l) {
-    T *ul = (l == L) ? uL : w.u[l];
+    T *ul = (l == L) ? top : w.u[l];
     const T *fl = (l == L) ? fL : w.f[l];
     if (l == 1) op_prolong<T, double>(c, 1, c->u0, true, ul);
     else op_prolong<T, T>(c, l, w.u[l - 1], false, ul);
@@ -538,7 +543,9 @@ int mg_solve_impl(sipg_ctx *c, double *u, const double *f, double rtol, int maxc
                   double *relres) {
   const int64_t N = level_ndof(c->H, c->L);
   ensure_work<double>(c);
-  double *bak = c->w64.uL;  // free during FP64 V-cycles
+  // two iterate buffers: the caller's u and a work vector free during FP64
+  // V-cycles; a speculative cycle writes the new iterate into the other one
+  double *cur = u, *alt = c->w64.uL;
   c->hist.clear();
   double r0 = -1.0;
   hipEvent_t ev = nullptr;
@@ -549,16 +556,13 @@ int mg_solve_impl(sipg_ctx *c, double *u, const double *f, double rtol, int maxc
   } guard{ev};
   bool spec = false;
   for (int cyc = 0;; ++cyc) {
-    residual_norm2(c, u, f, c->cg_r, sipg::FS_RR);
+    residual_norm2(c, cur, f, c->cg_r, sipg::FS_RR);
     check(hipMemcpyAsync(c->host_scal, c->scal, sipg::FS_COUNT * sizeof(double), hipMemcpyDeviceToHost,
                          c->stream),
           "scalar readback");
     check(hipEventRecord(ev, c->stream), "event");
     spec = spec && cyc < maxcyc;
-    if (spec) {
-      check(sipg::launch_convert<double, double>(u, bak, N, c->stream), "backup");
-      vcycle_impl<double>(c, u, f, false, c->cg_r);
-    }
+    if (spec) vcycle_impl<double>(c, cur, f, false, c->cg_r, alt);
     check(hipEventSynchronize(ev), "residual norm");
     const double rn = std::sqrt(c->host_scal[sipg::FS_RR]);
     c->hist.push_back(rn);
@@ -566,13 +570,15 @@ int mg_solve_impl(sipg_ctx *c, double *u, const double *f, double rtol, int maxc
     if (ncyc) *ncyc = cyc;
     if (relres) *relres = r0 > 0 ? rn / r0 : 0.0;
     if (!std::isfinite(rn) || rn <= rtol * r0 || cyc >= maxcyc) {
-      if (spec) check(sipg::launch_convert<double, double>(bak, u, N, c->stream), "restore");
+      // the checked iterate is cur; a speculative cycle's result is dropped
+      if (cur != u) check(sipg::launch_convert<double, double>(cur, u, N, c->stream), "result copy");
       check(hipStreamSynchronize(c->stream), "mg_solve");
       if (!std::isfinite(rn)) return fail(SIPG_ENOTFINITE, "residual norm is not finite");
       if (rn <= rtol * r0) return SIPG_OK;
       return fail(SIPG_ENOCONV, "mg_solve: tolerance not reached");
     }
-    if (!spec) vcycle_impl<double>(c, u, f, false, c->cg_r);
+    if (spec) std::swap(cur, alt);
+    else vcycle_impl<double>(c, cur, f, false, c->cg_r);
     // speculate on the next check if the observed rate says it cannot pass
     const size_t h = c->hist.size();
     spec = h >= 2 && c->hist[h - 2] > 0 && rn * (rn / c->hist[h - 2]) > 10.0 * rtol * r0;
