@@ -111,8 +111,12 @@ constexpr int kDotBlocks = 1024;
 // partial[b] = sum over block b of x[i]*y[i] (fixed partition, deterministic)
 template <typename TX, typename TY>
 hipError_t launch_dot_partials(const TX *x, const TY *y, int64_t n, double *partial, hipStream_t st);
-// out[0] = scale * sum_{b<np} partial[b], reduced in a fixed order by one block
-hipError_t launch_finalize(const double *partial, int np, double scale, double *out, hipStream_t st);
+// out[0] = scale * sum_{b<np} partial[b], reduced in a fixed order by one
+// block; with pub_dst, pub_src[0..pub_n) (a scalar block holding out) is then
+// copied to pub_dst (a device-mapped host mirror), so no separate copy is
+// needed before the host reads it
+hipError_t launch_finalize(const double *partial, int np, double scale, double *out, hipStream_t st,
+                           const double *pub_src = nullptr, double *pub_dst = nullptr, int pub_n = 0);
 // partial[b] = sum over block b of x[i], kDotBlocks blocks
 template <typename T>
 hipError_t launch_sum_partials(const T *x, int64_t n, double *partial, hipStream_t st);

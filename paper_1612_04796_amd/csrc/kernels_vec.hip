@@ -58,12 +58,17 @@ sum_partials_kernel(const T *__restrict__ x, int64_t n, double *__restrict__ par
 }
 
 __global__ void __launch_bounds__(1024)
-finalize_kernel(const double *__restrict__ partial, int np, double scale, double *__restrict__ out) {
+finalize_kernel(const double *__restrict__ partial, int np, double scale, double *out, const double *pub_src,
+                double *pub_dst, int pub_n) {
   __shared__ double red[16];
   double s = 0.0;
   for (int i = threadIdx.x; i < np; i += blockDim.x) s += partial[i];
   s = block_reduce_sum(s, red);
-  if (threadIdx.x == 0) out[0] = scale * s;
+  if (threadIdx.x == 0) {
+    out[0] = scale * s;
+    // publish: copy the scalar block (which holds out) to the host mirror
+    for (int i = 0; i < pub_n; ++i) pub_dst[i] = pub_src[i];
+  }
 }
 
 template <typename T>
@@ -228,8 +233,9 @@ hipError_t launch_sum_partials(const T *x, int64_t n, double *partial, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double *partial, int np, double scale, double *out, hipStream_t st) {
-  finalize_kernel<<<1, 1024, 0, st>>>(partial, np, scale, out);
+hipError_t launch_finalize(const double *partial, int np, double scale, double *out, hipStream_t st,
+                           const double *pub_src, double *pub_dst, int pub_n) {
+  finalize_kernel<<<1, 1024, 0, st>>>(partial, np, scale, out, pub_src, pub_dst, pub_dst ? pub_n : 0);
   return hipGetLastError();
 }
 

@@ -91,6 +91,7 @@ struct sipg_ctx {
   double *scal = nullptr;               // FS_COUNT scalars + spare
   double *partial = nullptr;            // 2 * kDotBlocks
   double *host_scal = nullptr;          // pinned host mirror
+  double *host_scal_dev = nullptr;      // its device-mapped address
   int *rhs_k = nullptr;
   double *rhs_phi = nullptr, *rhs_amp = nullptr;
   const double *xi_top = nullptr, *mass_top[3] = {nullptr, nullptr, nullptr};
@@ -350,10 +351,13 @@ void op_residual(sipg_ctx *c, int l, const T *u, const T *f, T *r, T *partial = 
 }
 
 // ||f - A u||^2 into scal[slot], r = f - A u (FP64, top level)
-void residual_norm2(sipg_ctx *c, const double *u, const double *f, double *r, int slot) {
+// ||f - A u||^2 into scal[slot]; with publish the scalar block is also
+// written to the host mirror
+void residual_norm2(sipg_ctx *c, const double *u, const double *f, double *r, int slot, bool publish = false) {
   op_residual<double>(c, c->L, u, f, r, c->partial);
   check(sipg::launch_finalize(c->partial, sipg::apply_num_blocks(c->mesh.E, c->H.lev[c->L].n), 1.0,
-                              c->scal + slot, c->stream),
+                              c->scal + slot, c->stream, c->scal, publish ? c->host_scal_dev : nullptr,
+                              sipg::FS_COUNT),
         "residual norm");
 }
 
@@ -515,13 +519,6 @@ void fcg_precond(sipg_ctx *c) {
   check(hipGraphLaunch(c->precond_graph, c->stream), "graph launch");
 }
 
-// Device scalars -> host (synchronizes the stream).
-void read_scalars(sipg_ctx *c) {
-  check(hipMemcpyAsync(c->host_scal, c->scal, sipg::FS_COUNT * sizeof(double), hipMemcpyDeviceToHost,
-                       c->stream),
-        "scalar readback");
-  check(hipStreamSynchronize(c->stream), "scalar readback");
-}
 
 // ||x||^2 into scal[slot]
 void norm2(sipg_ctx *c, const double *x, int64_t n, int slot) {
@@ -556,10 +553,7 @@ int mg_solve_impl(sipg_ctx *c, double *u, const double *f, double rtol, int maxc
   } guard{ev};
   bool spec = false;
   for (int cyc = 0;; ++cyc) {
-    residual_norm2(c, cur, f, c->cg_r, sipg::FS_RR);
-    check(hipMemcpyAsync(c->host_scal, c->scal, sipg::FS_COUNT * sizeof(double), hipMemcpyDeviceToHost,
-                         c->stream),
-          "scalar readback");
+    residual_norm2(c, cur, f, c->cg_r, sipg::FS_RR, true);
     check(hipEventRecord(ev, c->stream), "event");
     spec = spec && cyc < maxcyc;
     if (spec) vcycle_impl<double>(c, cur, f, false, c->cg_r, alt);
@@ -655,16 +649,7 @@ int guarded(F &&fn) {
 namespace sipg {
 namespace detail {
 
-static void copy_scalars_async(sipg_ctx *c) {
-  check(hipMemcpyAsync(c->host_scal, c->scal, sipg::FS_COUNT * sizeof(double), hipMemcpyDeviceToHost,
-                       c->stream),
-        "scalar readback");
-}
-
-void fcg_start(sipg_ctx *c, double *x, const double *b) {
-  residual_norm2(c, x, b, c->cg_r, sipg::FS_RR);
-  copy_scalars_async(c);
-}
+void fcg_start(sipg_ctx *c, double *x, const double *b) { residual_norm2(c, x, b, c->cg_r, sipg::FS_RR, true); }
 
 void fcg_first_precond(sipg_ctx *c) {
   const int64_t N = level_ndof(c->H, c->L);
@@ -693,17 +678,17 @@ void fcg_apply_update(sipg_ctx *c) {
         "dot");
   float *r32 = c->H.prm.precond_bits == 32 ? c->w32.fL : nullptr;
   check(sipg::launch_fcg_r(c->cg_r, c->cg_q, N, c->scal, c->partial, r32, c->stream), "fcg update");
-  check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + sipg::FS_RR, c->stream), "dot");
+  check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + sipg::FS_RR, c->stream, c->scal,
+                              c->host_scal_dev, sipg::FS_COUNT),
+        "dot");
   c->x_pending = true;
-  copy_scalars_async(c);
 }
 
 void fcg_confirm(sipg_ctx *c, double *x, const double *b) {
   const int64_t N = level_ndof(c->H, c->L);
   if (c->x_pending) check(sipg::launch_fcg_x(x, c->cg_p, N, c->scal, c->stream), "fcg update");
   c->x_pending = false;
-  residual_norm2(c, x, b, c->cg_q, sipg::FS_RR);
-  copy_scalars_async(c);
+  residual_norm2(c, x, b, c->cg_q, sipg::FS_RR, true);
 }
 
 void fcg_restart_from_true(sipg_ctx *c) {
@@ -806,8 +791,10 @@ int sipg_setup(const sipg_params *p, void *hip_stream, sipg_ctx **out) {
     c->rhs_k = c->alloc<int>(64 * 3);
     c->rhs_phi = c->alloc<double>(64 * 3);
     c->rhs_amp = c->alloc<double>(64);
-    if (hipHostMalloc((void **)&c->host_scal, sipg::FS_COUNT * sizeof(double)) != hipSuccess)
+    if (hipHostMalloc((void **)&c->host_scal, sipg::FS_COUNT * sizeof(double),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
       throw std::bad_alloc();
+    check(hipHostGetDevicePointer((void **)&c->host_scal_dev, c->host_scal, 0), "host mirror");
     check(sipg::launch_fill<double>(c->scal, sipg::FS_COUNT, 0.0, c->stream), "init");
     if (p->precond_bits == 64) ensure_work<double>(c.get());
     else ensure_work<float>(c.get());

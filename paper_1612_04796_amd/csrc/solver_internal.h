@@ -1,8 +1,8 @@
 // Internal interface between the solver context (sipg_api.cpp) and the serving
 // loop (serving.cpp).  Every fcg_* call only enqueues work on the context's
-// stream; the scalars it produces are copied asynchronously to the context's
-// pinned host mirror (indices FcgScalar) and are valid once the stream has
-// passed that point.
+// stream; the scalars it produces are written by its last reduction kernel
+// to the context's pinned, device-mapped host mirror (indices FcgScalar) and
+// are valid once the stream has passed that point.
 #pragma once
 
 #include <hip/hip_runtime.h>
