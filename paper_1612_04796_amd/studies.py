@@ -1,0 +1,118 @@
+"""Convergence studies of the paper run on the GPU solver.
+
+* Table 1 (Sec. 4, isotropic meshes): V(1,1) multigrid ("MG") and the
+  multigrid-preconditioned flexible CG ("MGCG") on (128/P)^3 elements, GLL
+  basis, overlaps "minimal", 8 % and 50 % of the element width; the measure
+  is -lg rho with rho = (r_n / r_0)^(1/n) from a random start.
+* The anisotropic study (Sec. 4, anisotropic meshes, the three methods of
+  Table 2): 8^3 elements of order 16 on (0, 2 pi AR) x (0, 2 pi ceil(AR/2))
+  x (0, 2 pi), overlap 8 % relative or 8 % of the largest element side
+  (capped by the element width), fixed V(1,1) or the variable V-cycle with
+  3^(L-l) smoothing steps on level l.
+
+Every input is seeded and synthetic: the right-hand side is the seeded
+Fourier load and the start vector U[-1, 1] (the paper's own test problem is
+printed garbled).  Run as
+
+    python -m paper_1612_04796_amd.studies table1 | aniso
+
+which prints one JSON object per case.
+"""
+
+import json
+import math
+import sys
+import time
+
+from .workloads import fourier_modes, uniform_vector
+
+# Table 1 rows of the GLL basis: (solver, overlap policy, omega)
+TABLE1_ROWS = {
+    1: ("mg", "min", 0.0), 2: ("fcg", "min", 0.0),
+    3: ("mg", "rel", 0.08), 4: ("fcg", "rel", 0.08),
+    5: ("mg", "rel", 0.5), 6: ("fcg", "rel", 0.5),
+}
+
+# the three methods of Table 2: (overlap policy, smoothing growth per level)
+ANISO_METHODS = {"rel_fix": ("rel", 1), "rel_var": ("rel", 3), "max_var": ("max", 3)}
+
+
+def table1_params(P, overlap, omega, ne=None):
+    ne = ne if ne is not None else 128 // P
+    return dict(ne=(ne,) * 3, length=(1.0, 1.0, 1.0), P=P, overlap=overlap, omega=omega)
+
+
+def aniso_params(AR, method, ne=8, P=16):
+    overlap, growth = ANISO_METHODS[method]
+    two_pi = 2.0 * math.pi
+    return dict(ne=(ne,) * 3, length=(two_pi * AR, two_pi * math.ceil(AR / 2), two_pi), P=P,
+                overlap=overlap, omega=0.08, smooth_growth=growth)
+
+
+def rate(hist):
+    """rho = (r_n / r_0)^(1/n), -lg rho and n10 = ceil(10 / -lg rho)."""
+    n = len(hist) - 1
+    rho = (hist[-1] / hist[0]) ** (1.0 / n) if n >= 1 and hist[0] > 0 else 0.0
+    nlg = -math.log10(rho) if rho > 0 else math.inf
+    return {"rho": rho, "neg_lg_rho": nlg, "n10": math.ceil(10.0 / nlg) if 0 < nlg < math.inf else None,
+            "cycles": n}
+
+
+def measure(params, solver="mg", ncyc=12, tol=1e-11, seed_rhs=0, seed_x0=7, kmax=3, precond_bits=64):
+    """Residual history of one solve from the seeded random start; returns
+    the rate measures, the history and the wall time per cycle."""
+    import torch
+    from . import sipg
+
+    s = sipg.Solver(precond_bits=precond_bits, **params)
+    try:
+        N = s.ndof()
+        b = torch.zeros(N, dtype=torch.float64, device="cuda")
+        k, phi, amp = fourier_modes(seed_rhs, kmax)
+        s.rhs_fourier(k, phi, amp, b)
+        x0 = torch.as_tensor(uniform_vector(seed_x0, N), dtype=torch.float64).cuda()
+        x = x0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if solver == "mg":
+            s.mg_solve(x, b, tol, ncyc, raise_on_noconv=False)
+        else:
+            s.pcg_solve(x, b, tol, ncyc, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        hist = s.residual_history()
+    finally:
+        s.close()
+    out = rate(hist)
+    out.update({"ndof": N, "history": hist, "s_per_cycle": el / max(1, out["cycles"]),
+                "us_per_unknown_per_cycle": 1e6 * el / max(1, out["cycles"]) / N})
+    return out
+
+
+def run_table1(orders=(4, 8, 16, 32), rows=tuple(TABLE1_ROWS), ncyc=12):
+    for row in rows:
+        solver, overlap, omega = TABLE1_ROWS[row]
+        for P in orders:
+            r = measure(table1_params(P, overlap, omega), solver=solver, ncyc=ncyc)
+            r.pop("history")
+            yield {"study": "table1", "row": row, "solver": solver, "overlap": overlap, "omega": omega,
+                   "P": P, "ne": 128 // P, **r}
+
+
+def run_aniso(ars=(1, 2, 4, 8, 12, 16, 24, 32, 48), methods=tuple(ANISO_METHODS), ncyc=40):
+    for method in methods:
+        for AR in ars:
+            r = measure(aniso_params(AR, method), solver="mg", ncyc=ncyc, tol=1e-10)
+            r.pop("history")
+            yield {"study": "aniso", "method": method, "AR": AR, **r}
+
+
+def main(argv):
+    which = argv[1] if len(argv) > 1 else "table1"
+    gen = run_table1() if which == "table1" else run_aniso()
+    for rec in gen:
+        print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv)

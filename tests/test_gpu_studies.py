@@ -1,0 +1,101 @@
+"""The paper's convergence studies on the GPU solver.
+
+Parity: on small meshes the GPU residual histories of the Table 1 methods
+and of the three anisotropy methods equal the oracle's from the same seeded
+start (same algorithm, rounding only).  Measurement: at the paper's own
+meshes the GPU reproduces Table 1 (GLL rows) and the qualitative findings
+of the anisotropic study (Sec. 4); the measured values are listed in the
+design notes."""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_04796_amd import studies
+from paper_1612_04796_amd.workloads import fourier_modes, uniform_vector
+
+from _gpu import announce
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_gll.txt")
+
+
+def _oracle_history(params, solver, ncyc, tol=1e-11):
+    h = oracle.Hierarchy(params["ne"], params["length"], params["P"], overlap=params["overlap"],
+                         omega=params["omega"], growth=params.get("smooth_growth", 1))
+    k, phi, amp = fourier_modes(0, 3)
+    b = oracle.fourier_rhs(k, phi, amp, h)
+    x0 = uniform_vector(7, b.size)
+    if solver == "mg":
+        _, _, _, hist = oracle.mg_solve(b, h, tol=tol, maxcyc=ncyc, x0=x0)
+    else:
+        _, _, _, hist = oracle.fcg_solve(b, h, tol=tol, maxit=ncyc, x0=x0)
+    return np.array(hist)
+
+
+def _compare(params, solver, ncyc, tol=1e-11):
+    got = np.array(studies.measure(params, solver=solver, ncyc=ncyc, tol=tol)["history"])
+    ref = _oracle_history(params, solver, ncyc, tol)
+    n = min(len(got), len(ref))
+    assert n >= 3 and abs(len(got) - len(ref)) <= 1, (len(got), len(ref))
+    # each entry relative to the initial residual (later entries are tiny)
+    err = np.abs(got[:n] - ref[:n]) / ref[0]
+    assert err.max() <= 1e-9, (err, got, ref)
+
+
+@pytest.mark.parametrize("row", sorted(studies.TABLE1_ROWS))
+def test_table1_methods_match_oracle_small(row):
+    solver, overlap, omega = studies.TABLE1_ROWS[row]
+    announce(f"table1 row {row} small")
+    _compare(studies.table1_params(4, overlap, omega, ne=4), solver, ncyc=6)
+
+
+@pytest.mark.parametrize("method", sorted(studies.ANISO_METHODS))
+@pytest.mark.parametrize("AR", [4, 8])
+def test_aniso_methods_match_oracle_small(method, AR):
+    announce(f"aniso {method} AR={AR} small")
+    params = studies.aniso_params(AR, method, ne=4, P=4)
+    _compare(params, "mg", ncyc=6)
+
+
+def _table1_paper():
+    rows = {}
+    with open(GOLDEN) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            t = line.split()
+            rows[int(t[0])] = dict(zip((4, 8, 16, 32), (float(v) for v in t[8:12])))
+    return rows
+
+
+def test_table1_at_paper_meshes():
+    """-lg rho of the GLL rows at (128/P)^3 elements against the paper's
+    Table 1: within 0.2 for the minimal and 8 % overlaps (rows 1-4; 20 of
+    the 24 cells are within 0.1), within 0.3 for the 50 % overlap (rows 5-6),
+    where 3-5 cycles reach 1e-11 and the rate estimate is coarser."""
+    announce("table1 at paper meshes")
+    paper = _table1_paper()
+    for rec in studies.run_table1():
+        want = paper[rec["row"]][rec["P"]]
+        tol = 0.2 if rec["row"] <= 4 else 0.3
+        assert abs(rec["neg_lg_rho"] - want) <= tol, (rec["row"], rec["P"], rec["neg_lg_rho"], want)
+
+
+def test_aniso_study_trends():
+    """The anisotropic study (8^3 elements, P = 16, AR up to 48): the
+    overlap relative to each element's own width degrades quickly with the
+    aspect ratio, the variable V-cycle does not cure it, and an overlap set
+    by the largest element side keeps a few cycles per decade over the
+    whole range (the paper: from 4 to 13 cycles at AR = 48)."""
+    announce("aniso study")
+    res = {(r["method"], r["AR"]): r for r in studies.run_aniso(ars=(1, 8, 16, 48), ncyc=40)}
+    for m in studies.ANISO_METHODS:
+        assert res[(m, 1)]["n10"] <= 6
+    assert res[("rel_fix", 8)]["neg_lg_rho"] < 0.5 * res[("rel_fix", 1)]["neg_lg_rho"]
+    assert res[("max_var", 16)]["neg_lg_rho"] > res[("rel_var", 16)]["neg_lg_rho"] + 1.0
+    n10 = [res[("max_var", ar)]["n10"] for ar in (1, 8, 16, 48)]
+    assert all(v is not None for v in n10) and n10[-1] <= 30 and n10[1:] == sorted(n10[1:]) and n10[0] <= 6
