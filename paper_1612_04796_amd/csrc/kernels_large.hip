@@ -139,44 +139,70 @@ elem_axis(int E, int sx, int sy, int sz, int axis, int nout, const T *__restrict
 // length m, `count` of them with pitch `pitch`) or the columns (ROWS = false:
 // column j has entries P[k * pitch + j], k < m) of a plane in LDS, processed
 // in batches so that every output of a batch is computed before the batch is
-// written back: out[o] = sum_a At[a*m + o] in[a], so consecutive lanes (o)
-// read consecutive table entries (S for a forward, (W S)^T for a backward
-// contraction; in LDS when it fits).
-template <typename T, bool ROWS>
-__device__ void plane_contract(T *P, int pitch, int count, int m, const T *__restrict__ At) {
+// written back: out[o] = sum_a At[a*ld + o] in[a] (S for a forward, (W S)^T
+// for a backward contraction).  Each thread computes four consecutive outputs
+// of a line, so one read of an input entry feeds four multiply-adds; with the
+// table in LDS its rows are padded to ld = m rounded up to 4 (zeros), and the
+// four table entries of a step are one aligned vector read.
+template <typename T, bool ROWS, bool PADDED>
+__device__ void plane_contract(T *P, int pitch, int count, int m, const T *__restrict__ At, int ld) {
   const int nth = blockDim.x, tid = threadIdx.x;
-  const int per_batch = max(1, nth / m);  // lines per batch
+  const int mq = (m + 3) / 4;                // output quads per line
+  const int per_batch = max(1, nth / mq);    // lines per batch
   for (int l0 = 0; l0 < count; l0 += per_batch) {
     const int nl = min(per_batch, count - l0);
-    T acc = 0;
-    const bool act = tid < nl * m;
-    const int line = l0 + tid / m, o = tid % m;
+    T acc[4] = {0, 0, 0, 0};
+    const bool act = tid < nl * mq;
+    const int line = l0 + tid / mq, o0 = 4 * (tid % mq);
     if (act) {
-#pragma unroll 8
+#pragma unroll 4
       for (int a = 0; a < m; ++a) {
         const T x = ROWS ? P[line * pitch + a] : P[a * pitch + line];
-        acc += At[a * m + o] * x;
+        const T *ar = At + a * ld + o0;
+        if constexpr (PADDED) ar = static_cast<const T *>(__builtin_assume_aligned(ar, 4 * sizeof(T)));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (PADDED || o0 + r < m) acc[r] += ar[r] * x;
+        }
       }
     }
     __syncthreads();
     if (act) {
-      if (ROWS) P[line * pitch + o] = acc;
-      else P[o * pitch + line] = acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = o0 + r;
+        if (o < m) {
+          if (ROWS) P[line * pitch + o] = acc[r];
+          else P[o * pitch + line] = acc[r];
+        }
+      }
     }
     __syncthreads();
   }
 }
 
-// The tables a wide kernel contracts with: copied into LDS after the plane
-// (TL) or read from global memory.
+inline __host__ __device__ int pad4(int m) { return (m + 3) / 4 * 4; }
+
+// The m x m table a wide kernel contracts with: copied into LDS after the
+// plane with its rows padded to pad4(m) (TL), or read from global memory.
 template <typename T, bool TL>
-__device__ __forceinline__ const T *stage_table(T *lds, const T *__restrict__ g, int count) {
+__device__ __forceinline__ const T *stage_table(T *lds, const T *__restrict__ g, int m) {
   if constexpr (TL) {
-    for (int i = threadIdx.x; i < count; i += blockDim.x) lds[i] = g[i];
+    const int ld = pad4(m);
+    for (int i = threadIdx.x; i < m * ld; i += blockDim.x) {
+      const int a = i / ld, o = i - a * ld;
+      lds[i] = o < m ? g[a * m + o] : (T)0;
+    }
     return lds;
   } else {
     return g;
   }
+}
+
+template <typename T, bool TL, bool ROWS>
+__device__ __forceinline__ void contract(T *P, int pitch, int count, int m, const T *At) {
+  if constexpr (TL) plane_contract<T, ROWS, true>(P, pitch, count, m, At, pad4(m));
+  else plane_contract<T, ROWS, false>(P, pitch, count, m, At, m);
 }
 
 // for (i = tid; i < tot; i += nth) put(i, get(i)), with the loads of kGB
@@ -216,8 +242,8 @@ wide_slab1(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restr
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *P = reinterpret_cast<T *>(smem_raw);
   const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
-  const T *Ax = stage_table<T, TL>(P + mx * my, tb.S[0], mx * mx);
-  const T *Ay = stage_table<T, TL>(P + mx * my + mx * mx, tb.S[1], my * my);
+  const T *Ax = stage_table<T, TL>(P + pad4(mx * my), tb.S[0], mx);
+  const T *Ay = stage_table<T, TL>(P + pad4(mx * my) + mx * pad4(mx), tb.S[1], my);
   const int blk = blockIdx.x;
   const int s = blk / mz, c = blk - s * mz;
   const int ex = s % g.ne[0], rest = s / g.ne[0];
@@ -230,8 +256,8 @@ wide_slab1(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restr
       },
       [&](int idx, T v) { P[idx] = v; });
   __syncthreads();
-  plane_contract<T, true>(P, mx, my, mx, Ax);
-  plane_contract<T, false>(P, mx, mx, my, Ay);
+  contract<T, TL, true>(P, mx, my, mx, Ax);
+  contract<T, TL, false>(P, mx, mx, my, Ay);
   T *Ws = W + ((size_t)s * mz + c) * mx * my;
   batched_copy<T>(
       mx * my, threadIdx.x, blockDim.x, [&](int idx) { return P[idx]; }, [&](int idx, T v) { Ws[idx] = v; });
@@ -244,8 +270,8 @@ wide_slab2(int E, SchwarzTabs<T> tb, const T *__restrict__ ilam, T *__restrict__
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *P = reinterpret_cast<T *>(smem_raw);
   const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
-  const T *Af = stage_table<T, TL>(P + mx * mz, tb.S[2], mz * mz);
-  const T *Ab = stage_table<T, TL>(P + mx * mz + mz * mz, tb.WST[2], mz * mz);
+  const T *Af = stage_table<T, TL>(P + pad4(mx * mz), tb.S[2], mz);
+  const T *Ab = stage_table<T, TL>(P + pad4(mx * mz) + mz * pad4(mz), tb.WST[2], mz);
   const int blk = blockIdx.x;
   const int s = blk / my, b = blk - s * my;
   T *Ws = W + (size_t)s * mx * my * mz;
@@ -254,13 +280,13 @@ wide_slab2(int E, SchwarzTabs<T> tb, const T *__restrict__ ilam, T *__restrict__
       [&](int idx) { return Ws[((size_t)(idx / mx) * my + b) * mx + idx % mx]; },
       [&](int idx, T v) { P[idx] = v; });
   __syncthreads();
-  plane_contract<T, false>(P, mx, mx, mz, Af);
+  contract<T, TL, false>(P, mx, mx, mz, Af);
   batched_copy<T>(
       mx * mz, threadIdx.x, blockDim.x,
       [&](int idx) { return ilam[((size_t)(idx / mx) * my + b) * mx + idx % mx]; },
       [&](int idx, T v) { P[idx] *= v; });
   __syncthreads();
-  plane_contract<T, false>(P, mx, mx, mz, Ab);
+  contract<T, TL, false>(P, mx, mx, mz, Ab);
   batched_copy<T>(
       mx * mz, threadIdx.x, blockDim.x, [&](int idx) { return P[idx]; },
       [&](int idx, T v) { Ws[((size_t)(idx / mx) * my + b) * mx + idx % mx] = v; });
@@ -272,16 +298,16 @@ __global__ void __launch_bounds__(256) wide_slab3(int E, SchwarzTabs<T> tb, T *_
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *P = reinterpret_cast<T *>(smem_raw);
   const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
-  const T *Ay = stage_table<T, TL>(P + mx * my, tb.WST[1], my * my);
-  const T *Ax = stage_table<T, TL>(P + mx * my + my * my, tb.WST[0], mx * mx);
+  const T *Ay = stage_table<T, TL>(P + pad4(mx * my), tb.WST[1], my);
+  const T *Ax = stage_table<T, TL>(P + pad4(mx * my) + my * pad4(my), tb.WST[0], mx);
   const int blk = blockIdx.x;
   const int s = blk / mz, c = blk - s * mz;
   T *Ws = W + ((size_t)s * mz + c) * mx * my;
   batched_copy<T>(
       mx * my, threadIdx.x, blockDim.x, [&](int idx) { return Ws[idx]; }, [&](int idx, T v) { P[idx] = v; });
   __syncthreads();
-  plane_contract<T, false>(P, mx, mx, my, Ay);
-  plane_contract<T, true>(P, mx, my, mx, Ax);
+  contract<T, TL, false>(P, mx, mx, my, Ay);
+  contract<T, TL, true>(P, mx, my, mx, Ax);
   batched_copy<T>(
       mx * my, threadIdx.x, blockDim.x, [&](int idx) { return P[idx]; }, [&](int idx, T v) { Ws[idx] = v; });
 }
@@ -365,9 +391,10 @@ hipError_t launch_schwarz_wide(const SchwarzLaunch<T> &a, hipStream_t st) {
   const size_t e = sizeof(T);
   const size_t p13 = (size_t)m[0] * m[1] * e, p2 = (size_t)m[0] * m[2] * e;
   if (std::max(p13, p2) > 150 * 1024) return hipErrorInvalidValue;
-  // with the tables: x and y (phases 1 and 3), z forward and backward (phase 2)
-  const size_t t13 = p13 + ((size_t)m[0] * m[0] + (size_t)m[1] * m[1]) * e;
-  const size_t t2 = p2 + 2 * (size_t)m[2] * m[2] * e;
+  // with the padded tables: x and y (phases 1 and 3), z forward and
+  // backward (phase 2); the plane offset of the tables stays 16-byte aligned
+  const size_t t13 = ((size_t)pad4(m[0] * m[1]) + (size_t)m[0] * pad4(m[0]) + (size_t)m[1] * pad4(m[1])) * e;
+  const size_t t2 = ((size_t)pad4(m[0] * m[2]) + 2 * (size_t)m[2] * pad4(m[2])) * e;
   if (std::max(t13, t2) <= 150 * 1024) return launch_wide_tl<T, true>(a, t13, t2, st);
   return launch_wide_tl<T, false>(a, p13, p2, st);
 }
