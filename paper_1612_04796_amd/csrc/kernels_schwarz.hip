@@ -641,12 +641,14 @@ hipError_t launch_fixed(const SchwarzLaunch<T> &a, hipStream_t st) {
 }
 
 // (n, m_x, m_y, m_z) shapes with a compiled fast path: the isotropic
-// minimal and 8% overlaps of orders 2..16 and the levels of the 16:1:1
-// aspect-ratio mesh with the "max" overlap.
+// minimal and 8% overlaps of orders 2..16, the levels of the 16:1:1
+// aspect-ratio mesh with the "max" overlap, and the "max" overlap levels of
+// orders 2..8 at aspect ratios 2..8 (x the long direction).
 #define SIPG_FDM_SHAPES(X)                                                              \
   X(3, 5, 5, 5) X(5, 7, 7, 7) X(8, 10, 10, 10) X(8, 12, 12, 12) X(9, 11, 11, 11)        \
   X(9, 13, 13, 13) X(17, 19, 19, 19) X(17, 23, 23, 23) X(3, 5, 9, 9) X(5, 7, 15, 15)     \
-  X(9, 13, 27, 27)
+  X(9, 13, 27, 27) X(3, 5, 7, 7) X(5, 7, 9, 9) X(5, 7, 11, 11) X(9, 13, 15, 15)          \
+  X(9, 13, 17, 17) X(9, 13, 19, 19)
 
 template <typename T>
 hipError_t launch_fixed_if_any(const SchwarzLaunch<T> &a, hipStream_t st, bool &done) {

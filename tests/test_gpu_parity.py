@@ -61,6 +61,8 @@ SCHWARZ = [
     ((4, 4, 4), (16.0, 1.0, 1.0), 4, "max"),     # full-neighbour overlap in y and z
     ((3, 4, 4), (16.0, 1.0, 1.0), 16, "max"),    # large subdomains: the plane kernels
     ((3, 3, 3), (1.0, 1.0, 1.0), 16, "rel"),
+    ((4, 3, 3), (3.0, 1.0, 1.0), 8, "max"),      # compile-time shapes (5,7,9,9), (9,13,15,15)
+    ((4, 4, 4), (8.0, 1.0, 1.0), 8, "max"),      # (3,5,7,7), (5,7,11,11), (9,13,19,19)
 ]
 
 
