@@ -41,28 +41,46 @@ __device__ __forceinline__ int64_t elem_major_p1(const Dims &d, int gx, int gy, 
 // axes, with a 2D workgroup (blockDim.x >= pitch, so threadIdx.x is the q
 // index).  ALONG_Q contracts the rows (over q, n = pitch), else the columns
 // (over r, n = number of rows).  All inputs are read before any output is
-// written (two barriers).
+// written (two barriers).  Each thread accumulates up to four outputs (rows
+// r, r + blockDim.y, ...) at once, so the entry read per lane (table or tile)
+// feeds four multiply-adds and only the broadcast reads repeat.
 //   FWD: out[o] = sum_a A[a*n + o] in[a];  else out[o] = sum_a A[o*n + a] in[a]
 template <bool ALONG_Q, bool FWD>
 __device__ void tile_contract(double *P, double *W, int pitch, int rows, const double *A) {
-  const int q = threadIdx.x;
+  const int q = threadIdx.x, by = blockDim.y;
   const int n = ALONG_Q ? pitch : rows;
   if (q < pitch) {
-    for (int r = threadIdx.y; r < rows; r += blockDim.y) {
-      // ALONG_Q: output (r, o = q) from row r; else output (o = r, q) from column q
-      const int o = ALONG_Q ? q : r;
-      double acc = 0.0;
-#pragma unroll 8
+    for (int r0 = threadIdx.y; r0 < rows; r0 += 4 * by) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
       for (int a = 0; a < n; ++a) {
-        const double x = ALONG_Q ? P[r * pitch + a] : P[a * pitch + q];
-        acc += (FWD ? A[a * n + o] : A[o * n + a]) * x;
+        if (ALONG_Q) {
+          // output (r, q) from row r: the table entry depends on the lane
+          const double t = FWD ? A[a * n + q] : A[q * n + a];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int r = r0 + k * by;
+            if (r < rows) acc[k] += t * P[r * pitch + a];
+          }
+        } else {
+          // output (o = r, q) from column q: the tile entry depends on the lane
+          const double x = P[a * pitch + q];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int o = r0 + k * by;
+            if (o < rows) acc[k] += (FWD ? A[a * n + o] : A[o * n + a]) * x;
+          }
+        }
       }
-      W[r * pitch + q] = acc;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = r0 + k * by;
+        if (r < rows) W[r * pitch + q] = acc[k];
+      }
     }
   }
   __syncthreads();
   if (q < pitch)
-    for (int r = threadIdx.y; r < rows; r += blockDim.y) P[r * pitch + q] = W[r * pitch + q];
+    for (int r = threadIdx.y; r < rows; r += by) P[r * pitch + q] = W[r * pitch + q];
   __syncthreads();
 }
 
