@@ -39,6 +39,11 @@ struct ApplyTabs {
   const T *DL[3];
   const T *DR[3];
   T mu[3];
+  // even-odd form of Ld (centro-symmetric: Ld[i][j] = Ld[n-1-i][n-1-j]),
+  // h = n/2: Ae[i][j] = (Ld[i][j] + Ld[i][n-1-j])/2, Ao[i][j] = (Ld[i][j] -
+  // Ld[i][n-1-j])/2 (i, j < h), then for odd n Ld[i][h] (i < h) and the
+  // centre row Ld[h][j] (j <= h)
+  const T *LdEO[3];
 };
 
 // Fast-diagonalization data of one level (Sec. 3.1): per direction the

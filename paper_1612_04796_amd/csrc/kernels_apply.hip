@@ -9,8 +9,9 @@
 // (the neighbour value at the shared face and its one-sided derivative
 // there), so all neighbour loads of the workgroup are in flight at once.  The
 // element's own data is staged in LDS and each direction's n x n block of L_d
-// is applied with the line in registers (uniform table entries through the
-// scalar cache).  XCD-aware block numbering keeps neighbour re-reads in L2.
+// (centro-symmetric) is applied in even-odd form with the line in registers
+// (uniform table entries through the scalar cache).  XCD-aware block
+// numbering keeps neighbour re-reads in L2.
 //
 // With DL = D[0][:]/h, DR = D[p][:]/h the coupling of line v of element e to
 // its right neighbour line vr and left neighbour line vl is
@@ -72,16 +73,43 @@ __device__ __forceinline__ FaceData<T> face_data(const T *__restrict__ lr, const
   return fd;
 }
 
-// (L_d v)[i] including the face coupling, for the line v in registers.
+// All N outputs of L_d applied to the line v, with the face coupling; the
+// element block is applied in its even-odd form (about half the
+// multiply-adds of the plain n x n product; Ld is centro-symmetric).
 template <typename T, int N>
-__device__ __forceinline__ T line_op(const T (&v)[N], int i, const T *__restrict__ Ld, const T *__restrict__ DL,
-                                     const T *__restrict__ DR, T mu, const FaceData<T> &fd) {
-  T acc = DR[i] * fd.vR - DL[i] * fd.vL;
+__device__ __forceinline__ void line_op_all(const T (&v)[N], T (&out)[N], const T *__restrict__ eo,
+                                            const T *__restrict__ DL, const T *__restrict__ DR, T mu,
+                                            const FaceData<T> &fd) {
+  constexpr int H = N / 2;
+  const T *Ae = eo, *Ao = eo + H * H, *Ac = eo + 2 * H * H, *Acr = Ac + H;
+  T sm[H], df[H];
 #pragma unroll
-  for (int q = 0; q < N; ++q) acc += Ld[i * N + q] * v[q];
-  if (i == N - 1) acc -= fd.gR + mu * fd.vR;
-  if (i == 0) acc += fd.gL - mu * fd.vL;
-  return acc;
+  for (int j = 0; j < H; ++j) {
+    sm[j] = v[j] + v[N - 1 - j];
+    df[j] = v[j] - v[N - 1 - j];
+  }
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    T ev = 0, od = 0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      ev += Ae[i * H + j] * sm[j];
+      od += Ao[i * H + j] * df[j];
+    }
+    if constexpr (N & 1) ev += Ac[i] * v[H];
+    out[i] = ev + od;
+    out[N - 1 - i] = ev - od;
+  }
+  if constexpr (N & 1) {
+    T c = Acr[H] * v[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) c += Acr[j] * sm[j];
+    out[H] = c;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) out[i] += DR[i] * fd.vR - DL[i] * fd.vL;
+  out[N - 1] -= fd.gR + mu * fd.vR;
+  out[0] += fd.gL - mu * fd.vL;
 }
 
 // EPB (elements per workgroup) is chosen at launch, at most ApplyShape<N>::EPB.
@@ -147,8 +175,10 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = sl[i];
     const T sc = tb.M[2][p] * tb.M[1][q];
+    T o[N];
+    line_op_all<T, N>(v, o, tb.LdEO[0], tb.DL[0], tb.DR[0], tb.mu[0], fx);
 #pragma unroll
-    for (int i = 0; i < N; ++i) yl[i] = sc * line_op<T, N>(v, i, tb.Ld[0], tb.DL[0], tb.DR[0], tb.mu[0], fx);
+    for (int i = 0; i < N; ++i) yl[i] = sc * o[i];
   }
   __syncthreads();
   if (active) {  // y: line (k=p, i=q), stride N
@@ -158,8 +188,10 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
 #pragma unroll
     for (int j = 0; j < N; ++j) v[j] = sl[j * N];
     const T sc = tb.M[2][p] * tb.M[0][q];
+    T o[N];
+    line_op_all<T, N>(v, o, tb.LdEO[1], tb.DL[1], tb.DR[1], tb.mu[1], fy);
 #pragma unroll
-    for (int j = 0; j < N; ++j) yl[j * N] += sc * line_op<T, N>(v, j, tb.Ld[1], tb.DL[1], tb.DR[1], tb.mu[1], fy);
+    for (int j = 0; j < N; ++j) yl[j * N] += sc * o[j];
   }
   __syncthreads();
   T dot = 0;
@@ -171,9 +203,11 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
     for (int k = 0; k < N; ++k) v[k] = sl[k * N2];
     const T sc = tb.M[1][p] * tb.M[0][q];
     const size_t gbase = (size_t)(e0 + le) * N3 + pq;
+    T o[N];
+    line_op_all<T, N>(v, o, tb.LdEO[2], tb.DL[2], tb.DR[2], tb.mu[2], fz);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      const T y = yl[k * N2] + sc * line_op<T, N>(v, k, tb.Ld[2], tb.DL[2], tb.DR[2], tb.mu[2], fz);
+      const T y = yl[k * N2] + sc * o[k];
       if (MODE == MODE_APPLY) {
         out[gbase + k * N2] = y;
         if (DOT) dot += v[k] * y;

@@ -184,6 +184,23 @@ void ensure_work(sipg_ctx *c) {
   w.ready = true;
 }
 
+// Even-odd form of the element block Ld of one direction (see ApplyTabs):
+// [Ae (h x h), Ao (h x h), for odd n: Ld[i][h] (h), Ld[h][j] (h + 1)].
+std::vector<double> pack_ld_even_odd(const sipg::Dir1D &D) {
+  const int n = D.n, h = n / 2;
+  auto L = [&](int i, int j) { return D.Ld[(size_t)i * n + j]; };
+  std::vector<double> t;
+  for (int i = 0; i < h; ++i)
+    for (int j = 0; j < h; ++j) t.push_back(0.5 * (L(i, j) + L(i, n - 1 - j)));
+  for (int i = 0; i < h; ++i)
+    for (int j = 0; j < h; ++j) t.push_back(0.5 * (L(i, j) - L(i, n - 1 - j)));
+  if (n & 1) {
+    for (int i = 0; i < h; ++i) t.push_back(L(i, h));
+    for (int j = 0; j <= h; ++j) t.push_back(L(h, j));
+  }
+  return t;
+}
+
 // Even-odd half tables of one direction, in the layout the compile-time-shape
 // Schwarz kernel reads (H = m/2, NE = m - H even modes, NO = H odd modes):
 //   forward  FE[a][j] = S[a][j] (a < H, j < NE),  FC[j] = S[H][j] (m odd),
@@ -213,7 +230,7 @@ void upload_tables(sipg_ctx *c) {
   const sipg::HierarchyHost &H = c->H;
   Arena A;
   struct Off {
-    size_t Ld[3], M[3], DL[3], DR[3], S[3], WS[3], WST[3], lam[3], EO[3], J, ilam, ilam_eo;
+    size_t Ld[3], LdEO[3], M[3], DL[3], DR[3], S[3], WS[3], WST[3], lam[3], EO[3], J, ilam, ilam_eo;
   };
   std::vector<Off> o64(c->L + 1), o32(c->L + 1);
   auto put_level = [&](auto tag, std::vector<Off> &off) {
@@ -223,6 +240,7 @@ void upload_tables(sipg_ctx *c) {
       for (int d = 0; d < 3; ++d) {
         const sipg::Dir1D &D = lv.dir[d];
         off[l].Ld[d] = A.put<T>(D.Ld);
+        off[l].LdEO[d] = A.put<T>(pack_ld_even_odd(D));
         off[l].M[d] = A.put<T>(D.mass);
         off[l].DL[d] = A.put<T>(D.DLs);
         off[l].DR[d] = A.put<T>(D.DRs);
@@ -290,6 +308,7 @@ void upload_tables(sipg_ctx *c) {
       for (int d = 0; d < 3; ++d) {
         t.apply.Ld[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].Ld[d]);
         t.apply.M[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].M[d]);
+        t.apply.LdEO[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].LdEO[d]);
         t.apply.DL[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].DL[d]);
         t.apply.DR[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].DR[d]);
         t.apply.mu[d] = (T)lv.dir[d].mu;
