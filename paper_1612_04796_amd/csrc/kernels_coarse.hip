@@ -41,47 +41,48 @@ __device__ __forceinline__ int64_t elem_major_p1(const Dims &d, int gx, int gy, 
 // axes, with a 2D workgroup (blockDim.x >= pitch, so threadIdx.x is the q
 // index).  ALONG_Q contracts the rows (over q, n = pitch), else the columns
 // (over r, n = number of rows).  All inputs are read before any output is
-// written (two barriers).  Each thread accumulates up to four outputs (rows
-// r, r + blockDim.y, ...) at once, so the entry read per lane (table or tile)
-// feeds four multiply-adds and only the broadcast reads repeat.
+// written (two barriers).
 //   FWD: out[o] = sum_a A[a*n + o] in[a];  else out[o] = sum_a A[o*n + a] in[a]
 template <bool ALONG_Q, bool FWD>
 __device__ void tile_contract(double *P, double *W, int pitch, int rows, const double *A) {
-  const int q = threadIdx.x, by = blockDim.y;
+  const int q = threadIdx.x;
   const int n = ALONG_Q ? pitch : rows;
   if (q < pitch) {
-    for (int r0 = threadIdx.y; r0 < rows; r0 += 4 * by) {
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = threadIdx.y; r < rows; r += blockDim.y) {
+      // ALONG_Q: output (r, o = q) from row r; else output (o = r, q) from column q
+      const int o = ALONG_Q ? q : r;
+      double acc = 0.0;
+#pragma unroll 8
       for (int a = 0; a < n; ++a) {
-        if (ALONG_Q) {
-          // output (r, q) from row r: the table entry depends on the lane
-          const double t = FWD ? A[a * n + q] : A[q * n + a];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int r = r0 + k * by;
-            if (r < rows) acc[k] += t * P[r * pitch + a];
-          }
-        } else {
-          // output (o = r, q) from column q: the tile entry depends on the lane
-          const double x = P[a * pitch + q];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int o = r0 + k * by;
-            if (o < rows) acc[k] += (FWD ? A[a * n + o] : A[o * n + a]) * x;
-          }
-        }
+        const double x = ALONG_Q ? P[r * pitch + a] : P[a * pitch + q];
+        acc += (FWD ? A[a * n + o] : A[o * n + a]) * x;
       }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int r = r0 + k * by;
-        if (r < rows) W[r * pitch + q] = acc[k];
-      }
+      W[r * pitch + q] = acc;
     }
   }
   __syncthreads();
   if (q < pitch)
-    for (int r = threadIdx.y; r < rows; r += by) P[r * pitch + q] = W[r * pitch + q];
+    for (int r = threadIdx.y; r < rows; r += blockDim.y) P[r * pitch + q] = W[r * pitch + q];
   __syncthreads();
+}
+
+// for (i = i0; i < tot; i += step) put(i, get(i)), the loads of four
+// consecutive iterations issued before any of their values is stored
+template <typename Get, typename Put>
+__device__ __forceinline__ void copy4(int i0, int tot, int step, Get get, Put put) {
+  for (int b = i0; b < tot; b += 4 * step) {
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = b + k * step;
+      v[k] = i < tot ? get(i) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = b + k * step;
+      if (i < tot) put(i, v[k]);
+    }
+  }
 }
 
 __device__ __forceinline__ int flat_tid() { return threadIdx.y * blockDim.x + threadIdx.x; }
@@ -113,19 +114,19 @@ coarse_plane_xy_fwd(Dims d, CoarseLaunch c, const TI *__restrict__ f0, double *_
   const int tid = flat_tid(), nth = flat_nth();
   if (TL) {
     double *sx = W + Nx * Ny, *sy = sx + Nx * Nx;
-    for (int i = tid; i < Nx * Nx; i += nth) sx[i] = c.S[0][i];
-    for (int i = tid; i < Ny * Ny; i += nth) sy[i] = c.S[1][i];
+    copy4(tid, Nx * Nx, nth, [&](int i) { return c.S[0][i]; }, [&](int i, double v) { sx[i] = v; });
+    copy4(tid, Ny * Ny, nth, [&](int i) { return c.S[1][i]; }, [&](int i, double v) { sy[i] = v; });
     Sx = sx;
     Sy = sy;
   }
   const int z = blockIdx.x;
   double s = 0.0;
   if (threadIdx.x < Nx)
-    for (int y = threadIdx.y; y < Ny; y += blockDim.y) {
-      const double v = (double)f0[elem_major_p1(d, threadIdx.x, y, z)];
-      P[y * Nx + threadIdx.x] = v;
-      s += v;
-    }
+    copy4(threadIdx.y, Ny, blockDim.y, [&](int y) { return (double)f0[elem_major_p1(d, threadIdx.x, y, z)]; },
+          [&](int y, double v) {
+            P[y * Nx + threadIdx.x] = v;
+            s += v;
+          });
   s = block_sum_2d(s, red);
   if (tid == 0) c.partial[z] = s;
   __syncthreads();
@@ -149,26 +150,45 @@ __global__ void __launch_bounds__(1024) coarse_plane_z(Dims d, CoarseLaunch c, d
   const int tid = flat_tid(), nth = flat_nth();
   if (TL) {
     double *sz = W + Nx * Nz;
-    for (int i = tid; i < Nz * Nz; i += nth) sz[i] = c.S[2][i];
+    copy4(tid, Nz * Nz, nth, [&](int i) { return c.S[2][i]; }, [&](int i, double v) { sz[i] = v; });
     Sz = sz;
   }
   const int y = blockIdx.x;
   if (threadIdx.x < Nx)
-    for (int z = threadIdx.y; z < Nz; z += blockDim.y) P[z * Nx + threadIdx.x] = t[((size_t)z * Ny + y) * Nx + threadIdx.x];
+    copy4(threadIdx.y, Nz, blockDim.y, [&](int z) { return t[((size_t)z * Ny + y) * Nx + threadIdx.x]; },
+          [&](int z, double v) { P[z * Nx + threadIdx.x] = v; });
   double s = 0.0;
   for (int i = tid; i < Nz; i += nth) s += c.partial[i];
+  // the 1D eigenvalues and column sums the scaling needs, loaded before the
+  // reductions and contractions (their latency hides behind them)
+  const int x = threadIdx.x;
+  const bool lane = x < Nx;
+  const double cxy = lane ? c.colsum[0][x] * c.colsum[1][y] : 0.0;
+  const double lxy = lane ? c.lam[0][x] + c.lam[1][y] : 1.0;
+  double cz[4], lz[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int o = threadIdx.y + k * blockDim.y;
+    cz[k] = o < Nz ? c.colsum[2][o] : 0.0;
+    lz[k] = o < Nz ? c.lam[2][o] : 0.0;
+  }
   s = block_sum_2d(s, red);
   if (tid == 0) mean_sh = s / ((double)Nx * Ny * Nz);
   __syncthreads();
   tile_contract<false, true>(P, W, Nx, Nz, Sz);
   const double mean = mean_sh;
-  if (threadIdx.x < Nx) {
-    const int x = threadIdx.x;
-    for (int o = threadIdx.y; o < Nz; o += blockDim.y) {
-      const double v = P[o * Nx + x] - mean * c.colsum[2][o] * c.colsum[1][y] * c.colsum[0][x];
-      const bool zero = (x == c.zero[0] && y == c.zero[1] && o == c.zero[2]);
-      P[o * Nx + x] = zero ? 0.0 : v / (c.lam[0][x] + c.lam[1][y] + c.lam[2][o]);
+  auto scale = [&](int o, double czo, double lzo) {
+    const double v = P[o * Nx + x] - mean * czo * cxy;
+    const bool zero = (x == c.zero[0] && y == c.zero[1] && o == c.zero[2]);
+    P[o * Nx + x] = zero ? 0.0 : v / (lxy + lzo);
+  };
+  if (lane) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int o = threadIdx.y + k * blockDim.y;
+      if (o < Nz) scale(o, cz[k], lz[k]);
     }
+    for (int o = threadIdx.y + 4 * blockDim.y; o < Nz; o += blockDim.y) scale(o, c.colsum[2][o], c.lam[2][o]);
   }
   __syncthreads();
   tile_contract<false, false>(P, W, Nx, Nz, Sz);
@@ -192,14 +212,15 @@ coarse_plane_xy_bwd(Dims d, CoarseLaunch c, const double *__restrict__ t, double
     // Sx is stored transposed so that the x backward reads it along
     // consecutive addresses (no LDS bank conflicts)
     double *sxt = W + Nx * Ny, *sy = sxt + Nx * Nx;
-    for (int i = tid; i < Nx * Nx; i += nth) sxt[(i % Nx) * Nx + i / Nx] = c.S[0][i];
-    for (int i = tid; i < Ny * Ny; i += nth) sy[i] = c.S[1][i];
+    copy4(tid, Nx * Nx, nth, [&](int i) { return c.S[0][i]; },
+          [&](int i, double v) { sxt[(i % Nx) * Nx + i / Nx] = v; });
+    copy4(tid, Ny * Ny, nth, [&](int i) { return c.S[1][i]; }, [&](int i, double v) { sy[i] = v; });
     Sx = sxt;
     Sy = sy;
   }
   const int z = blockIdx.x;
   const double *tz = t + (size_t)z * Nx * Ny;
-  for (int i = tid; i < Nx * Ny; i += nth) P[i] = tz[i];
+  copy4(tid, Nx * Ny, nth, [&](int i) { return tz[i]; }, [&](int i, double v) { P[i] = v; });
   __syncthreads();
   tile_contract<false, false>(P, W, Nx, Ny, Sy);
   if (TL) tile_contract<true, true>(P, W, Nx, Ny, Sx);  // (Sx^T)^T = Sx
