@@ -129,7 +129,9 @@ template <typename T>
 hipError_t launch_fill(T *x, int64_t n, T v, hipStream_t st);
 
 // Flexible CG scalars live in device memory: see kernels_vec.hip.
-enum FcgScalar { FS_RZ = 0, FS_PQ = 1, FS_RR = 2, FS_ZQ = 3, FS_RZNEW = 4, FS_ALPHA = 5, FS_BETA = 6, FS_COUNT = 8 };
+enum FcgScalar { FS_RZ = 0, FS_PQ = 1, FS_RR = 2, FS_ZQ = 3, FS_RZNEW = 4, FS_ALPHA = 5, FS_BETA = 6,
+                 FS_MEAN = 7,  // mean of a generated right-hand side
+                 FS_COUNT = 8 };
 // One flexible-CG iteration is split so that no vector is read twice where
 // it can be avoided:
 //   r -= alpha q, partial = r.r, r32 = (float) r when given   (alpha = s[RZ] / s[PQ])

@@ -88,7 +88,7 @@ struct sipg_ctx {
   Work<float> w32;
   // flexible CG vectors (FP64, top level) and device scalars
   double *cg_r = nullptr, *cg_p = nullptr, *cg_q = nullptr, *cg_z = nullptr;
-  double *scal = nullptr;               // FS_COUNT scalars + spare
+  double *scal = nullptr;               // the FS_COUNT slots of FcgScalar
   double *partial = nullptr;            // 2 * kDotBlocks
   double *host_scal = nullptr;          // pinned host mirror
   double *host_scal_dev = nullptr;      // its device-mapped address
@@ -879,10 +879,10 @@ int sipg_rhs_fourier(sipg_ctx *c, int nmodes, const int32_t *k, const double *ph
     check(sipg::launch_rhs(a, b, c->stream), "rhs");
     const int64_t N = level_ndof(H, c->L);
     check(sipg::launch_sum_partials<double>(b, N, c->partial, c->stream), "rhs mean");
-    check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0 / (double)N, c->scal + sipg::FS_COUNT - 1,
+    check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0 / (double)N, c->scal + sipg::FS_MEAN,
                                 c->stream),
           "rhs mean");
-    check(sipg::launch_sub_scalar<double>(b, N, c->scal + sipg::FS_COUNT - 1, c->stream), "rhs mean");
+    check(sipg::launch_sub_scalar<double>(b, N, c->scal + sipg::FS_MEAN, c->stream), "rhs mean");
     // the host-side copies of k/phi/amp must stay valid until the copies ran
     check(hipStreamSynchronize(c->stream), "rhs");
     return (int)SIPG_OK;

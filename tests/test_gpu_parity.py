@@ -106,8 +106,13 @@ def test_transfers(ne, length, P):
     s.close()
 
 
-@pytest.mark.parametrize("ne,length", [((3, 3, 3), (1.0, 1.0, 1.0)), ((4, 3, 5), (2.0, 1.0, 0.5)),
-                                       ((16, 16, 16), (1.0, 1.0, 1.0))])
+# up to the 48 elements per direction the coarse planes allow, with odd and
+# unequal counts
+COARSE = [((3, 3, 3), (1.0, 1.0, 1.0)), ((4, 3, 5), (2.0, 1.0, 0.5)), ((16, 16, 16), (1.0, 1.0, 1.0)),
+          ((7, 32, 9), (1.0, 3.0, 1.0)), ((3, 40, 3), (1.0, 1.0, 1.0)), ((5, 4, 48), (1.0, 1.0, 2.0))]
+
+
+@pytest.mark.parametrize("ne,length", COARSE)
 def test_coarse_solve(ne, length):
     announce("coarse", ne, length)
     h, s = pair(ne, length, 2)
