@@ -118,9 +118,10 @@ def cpu_baseline(wl, cycles, k, phi, amp):
     }
 
 
-def fcg_timing(wl, bits, b, steps, warmup):
+def fcg_timing(wl, bits, b, steps, warmup, keep=None):
     """Flexible CG from x0 = 0 to 1e-10 on workload wl with the given
-    preconditioner precision: mean wall time over `steps` solves."""
+    preconditioner precision (16: FP32 with FP16 matrix-core local solves):
+    mean wall time over `steps` solves; keep[bits] receives the solution."""
     import torch
     from paper_1612_04796_amd import sipg
     s = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
@@ -137,6 +138,8 @@ def fcg_timing(wl, bits, b, steps, warmup):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     s.close()
+    if keep is not None:
+        keep[bits] = x
     log(f"FCG {wl.name}, FP{bits} preconditioner: {1e3 * el / steps:.3f} ms/solve, {it} iterations")
     return {"unknowns_per_s": wl.ndof * steps / el, "ms_per_solve": 1e3 * el / steps,
             "iterations": it, "final_relres": rr}
@@ -330,14 +333,21 @@ def main():
         s4.rhs_fourier(k4, phi4, amp4, b4)
         s4.close()
         mixed = {"workload": wl4.name, "ndof": wl4.ndof}
-        for bits in (64, 32):
-            mixed[f"fcg_precond_fp{bits}"] = fcg_timing(wl4, bits, b4, args.steps, args.warmup)
-        mixed["speedup_fp32_over_fp64"] = (mixed["fcg_precond_fp64"]["ms_per_solve"]
-                                           / mixed["fcg_precond_fp32"]["ms_per_solve"])
+        sols = {}
+        for bits in (64, 32, 16):
+            mixed[f"fcg_precond_fp{bits}"] = fcg_timing(wl4, bits, b4, args.steps, args.warmup, sols)
+        for bits in (32, 16):
+            m = mixed[f"fcg_precond_fp{bits}"]
+            m["speedup_over_fp64"] = mixed["fcg_precond_fp64"]["ms_per_solve"] / m["ms_per_solve"]
+            # distance to the solution of the FP64-preconditioned solve
+            m["rel_l2_vs_fp64_solution"] = float(torch.linalg.vector_norm(sols[bits] - sols[64])
+                                                 / torch.linalg.vector_norm(sols[64]))
+        mixed["speedup_fp32_over_fp64"] = mixed["fcg_precond_fp32"]["speedup_over_fp64"]
+        mixed["speedup_fp16_over_fp64"] = mixed["fcg_precond_fp16"]["speedup_over_fp64"]
         detail["mixed_precision"] = mixed
-        log(f"mixed precision at {wl4.name}: FP32 preconditioner {mixed['speedup_fp32_over_fp64']:.2f}x "
-            f"the FP64 one")
-        del b4
+        log(f"mixed precision at {wl4.name}: FP32 preconditioner {mixed['speedup_fp32_over_fp64']:.2f}x, "
+            f"FP16 local solves {mixed['speedup_fp16_over_fp64']:.2f}x the FP64 one")
+        del b4, sols
 
     if args.serving_requests > 0:
         log("serving stream ...")

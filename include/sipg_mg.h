@@ -73,8 +73,12 @@ typedef struct {
   int32_t smooth_growth;  /* steps on level l are multiplied by growth^(L-l);
                              1 = fixed V-cycle, 3 = the variable V-cycle of Table 2 */
   int32_t precond_bits;   /* precision of the multigrid preconditioner inside
-                             sipg_pcg_solve and of sipg_precond: 64 or 32
-                             (FP32 storage and arithmetic, coarse solve in FP64) */
+                             sipg_pcg_solve and of sipg_precond: 64, 32 (FP32
+                             storage and arithmetic, coarse solve in FP64) or 16
+                             (as 32, but the local fast-diagonalization solves of
+                             levels with cubic subdomains of 10-13 nodes (P = 7, 8)
+                             run in FP16 on the matrix cores with FP32
+                             accumulation and per-subdomain power-of-two scaling) */
 } sipg_params;
 
 /* Fills *p with the defaults: ne = 4^3, unit cube, P = 4, penalty 1.0,

@@ -391,7 +391,8 @@ std::string validate(const sipg_params &p) {
   if (p.nsmooth_pre < 0 || p.nsmooth_post < 0 || p.nsmooth_pre + p.nsmooth_post < 1)
     return "need nsmooth_pre, nsmooth_post >= 0 with at least one smoothing step";
   if (p.smooth_growth < 1 || p.smooth_growth > 8) return "smooth_growth must be in 1..8";
-  if (p.precond_bits != 64 && p.precond_bits != 32) return "precond_bits must be 64 or 32";
+  if (p.precond_bits != 64 && p.precond_bits != 32 && p.precond_bits != 16)
+    return "precond_bits must be 64, 32 or 16";
   // the coarse solve holds 2D planes of the level-0 tensor (2 ne_d nodes
   // per direction) in LDS and at most 12 rows of a plane per thread
   for (int d = 0; d < 3; ++d)

@@ -63,6 +63,20 @@ hipError_t launch_prolong_large(const ProlongLaunch<T, TC> &a, T *tmp, hipStream
 // every subdomain s (m_x*m_y*m_z values per subdomain, layout [s][c][b][a]),
 // then u_out = u_in + sum_s R_s^T C[s] in a fixed order (u_in may be null,
 // u_out may equal u_in).
+// Tables of the FP16 matrix-core local solves (kernels_mfma.hip) of one
+// level with cubic subdomains of m <= 16 nodes per direction; q = l / 16.
+struct MfmaTabs {
+  const _Float16 *fwd[3];  // lane l, item v: S[4q + v][l % 16] / f_d (zero beyond m)
+  const _Float16 *bwd[3];  // lane l, item v: w[l % 16] S[l % 16][4q + v] / g_d
+  const float *ilam;       // [tile][lane][4]: (1/lambda) / max(1/lambda), zero-padded
+  float kout;              // f_x f_y f_z g_x g_y g_z max(1/lambda)
+};
+// f_d: largest absolute column sum of S_d; g_d: largest absolute row sum of W S_d
+bool mfma_fdm_supported(int n, const int m[3]);
+int mfma_fdm_tiles(int m);  // 16-line tiles of the m^2 lines of one direction
+hipError_t launch_schwarz_mfma(const Mesh &mesh, int n, const int m[3], const MfmaTabs &tb, const float *r,
+                               float *C, hipStream_t st);
+
 template <typename T>
 struct SchwarzLaunch {
   Mesh mesh;
@@ -73,6 +87,7 @@ struct SchwarzLaunch {
   const T *ilam;    // 1 / (lam_x[a] + lam_y[b] + lam_z[c]), layout [c][b][a]
   const T *u_in;
   T *u_out;
+  const MfmaTabs *mfma = nullptr;  // FP32 levels: local solves in FP16 on the matrix cores
 };
 template <typename T>
 hipError_t launch_schwarz(const SchwarzLaunch<T> &a, hipStream_t st);

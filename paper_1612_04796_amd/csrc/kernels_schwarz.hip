@@ -691,6 +691,9 @@ bool schwarz_fits_lds(const int m[3], size_t eb) {
 
 template <typename T>
 hipError_t launch_schwarz_local(const SchwarzLaunch<T> &a, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (a.mfma) return launch_schwarz_mfma(a.mesh, a.n, a.tabs.m, *a.mfma, a.r, a.C, st);
+  }
   if (a.tabs.ilam_eo) {
     bool done = false;
     hipError_t e = launch_fixed_if_any<T>(a, st, done);

@@ -43,6 +43,8 @@ struct LevelTabs {
   sipg::SchwarzTabs<T> schwarz;
   const T *J = nullptr;  // n x n_prev (levels >= 1)
   const T *ilam = nullptr;  // 1 / (lam_x + lam_y + lam_z) per subdomain entry (levels >= 1)
+  sipg::MfmaTabs mfma{};    // FP16 matrix-core local solves (FP32 levels that have them)
+  bool has_mfma = false;
   int n = 0, nc = 0;
   int64_t ndof = 0;
 };
@@ -226,11 +228,67 @@ std::vector<double> pack_even_odd(const sipg::Dir1D &D) {
   return t;
 }
 
+// Tables of the FP16 matrix-core local solves of one level (cubic
+// subdomains): per direction the forward operand S / f_d and the backward
+// operand W S / g_d in the lane order of a 16 x 16 MFMA operand, and 1/lambda
+// over its maximum in the order of the forward z result; see MfmaTabs.
+struct MfmaHost {
+  std::vector<double> fwd[3], bwd[3], ilam;
+  double kout = 1.0;
+};
+
+MfmaHost build_mfma_tables(const sipg::LevelHost &lv) {
+  MfmaHost h;
+  const int m = lv.dir[0].m, tiles = sipg::mfma_fdm_tiles(m);
+  for (int d = 0; d < 3; ++d) {
+    const sipg::Dir1D &D = lv.dir[d];
+    double f = 0.0, g = 0.0;
+    for (int j = 0; j < m; ++j) {
+      double cs = 0.0, rs = 0.0;
+      for (int a = 0; a < m; ++a) {
+        cs += std::fabs(D.S[(size_t)a * m + j]);
+        rs += std::fabs(D.wsub[j] * D.S[(size_t)j * m + a]);
+      }
+      f = std::max(f, cs);
+      g = std::max(g, rs);
+    }
+    h.fwd[d].assign(256, 0.0);
+    h.bwd[d].assign(256, 0.0);
+    for (int l = 0; l < 64; ++l)
+      for (int v = 0; v < 4; ++v) {
+        const int k = 4 * (l / 16) + v, c = l % 16;
+        if (k < m && c < m) {
+          h.fwd[d][l * 4 + v] = D.S[(size_t)k * m + c] / f;
+          h.bwd[d][l * 4 + v] = D.wsub[c] * D.S[(size_t)c * m + k] / g;
+        }
+      }
+    h.kout *= f * g;
+  }
+  const sipg::Dir1D &X = lv.dir[0], &Y = lv.dir[1], &Z = lv.dir[2];
+  double imax = 0.0;
+  for (int k = 0; k < m; ++k)
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) imax = std::max(imax, 1.0 / (X.lam[i] + Y.lam[j] + Z.lam[k]));
+  h.ilam.assign((size_t)tiles * 256, 0.0);
+  for (int t = 0; t < tiles; ++t)
+    for (int l = 0; l < 64; ++l)
+      for (int v = 0; v < 4; ++v) {
+        const int line = t * 16 + l % 16, jy = line / m, jx = line % m, jz = 4 * (l / 16) + v;
+        if (line < m * m && jz < m)
+          h.ilam[((size_t)t * 64 + l) * 4 + v] = 1.0 / (X.lam[jx] + Y.lam[jy] + Z.lam[jz]) / imax;
+      }
+  h.kout *= imax;
+  return h;
+}
+
 void upload_tables(sipg_ctx *c) {
   const sipg::HierarchyHost &H = c->H;
   Arena A;
   struct Off {
     size_t Ld[3], LdEO[3], M[3], DL[3], DR[3], S[3], WS[3], WST[3], lam[3], EO[3], J, ilam, ilam_eo;
+    size_t mf[3], mb[3], mil;
+    double kout;
+    bool mfma;
   };
   std::vector<Off> o64(c->L + 1), o32(c->L + 1);
   auto put_level = [&](auto tag, std::vector<Off> &off) {
@@ -272,6 +330,18 @@ void upload_tables(sipg_ctx *c) {
             for (int ax = 0; ax < X.m; ++ax)
               il[((size_t)cz * Y.m + by) * X.m + ax] = 1.0 / (X.lam_eo[ax] + Y.lam_eo[by] + Z.lam_eo[cz]);
         off[l].ilam_eo = A.put<T>(il);
+        const int m3[3] = {X.m, Y.m, Z.m};
+        off[l].mfma = std::is_same<T, float>::value && sipg::mfma_fdm_supported(lv.n, m3) &&
+                      (int64_t)c->mesh.E * lv.n * lv.n * lv.n < ((int64_t)1 << 30);
+        if (off[l].mfma) {
+          const MfmaHost mh = build_mfma_tables(lv);
+          for (int d = 0; d < 3; ++d) {
+            off[l].mf[d] = A.put<_Float16>(mh.fwd[d]);
+            off[l].mb[d] = A.put<_Float16>(mh.bwd[d]);
+          }
+          off[l].mil = A.put<float>(mh.ilam);
+          off[l].kout = mh.kout;
+        }
       }
     }
   };
@@ -326,6 +396,15 @@ void upload_tables(sipg_ctx *c) {
         t.J = reinterpret_cast<const T *>(c->tab_dev + off[l].J);
         t.ilam = reinterpret_cast<const T *>(c->tab_dev + off[l].ilam);
         t.schwarz.ilam_eo = reinterpret_cast<const T *>(c->tab_dev + off[l].ilam_eo);
+        t.has_mfma = off[l].mfma;
+        if (t.has_mfma) {
+          for (int d = 0; d < 3; ++d) {
+            t.mfma.fwd[d] = reinterpret_cast<const _Float16 *>(c->tab_dev + off[l].mf[d]);
+            t.mfma.bwd[d] = reinterpret_cast<const _Float16 *>(c->tab_dev + off[l].mb[d]);
+          }
+          t.mfma.ilam = reinterpret_cast<const float *>(c->tab_dev + off[l].mil);
+          t.mfma.kout = (float)off[l].kout;
+        }
       }
     }
   };
@@ -387,10 +466,16 @@ void op_residual_restrict(sipg_ctx *c, int l, const T *u, const T *f, T *fc) {
   run_apply<T>(c, a, "residual_restrict");
 }
 
+// the FP16 matrix-core local solves: FP32 levels of a precond_bits = 16 context
+template <typename T>
+const sipg::MfmaTabs *mfma_of(const sipg_ctx *c, const LevelTabs<T> &t) {
+  return std::is_same<T, float>::value && c->H.prm.precond_bits == 16 && t.has_mfma ? &t.mfma : nullptr;
+}
+
 template <typename T>
 void op_schwarz(sipg_ctx *c, int l, const T *r, const T *u_in, T *u_out) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
-  sipg::SchwarzLaunch<T> a{c->mesh, t.n, t.schwarz, r, work_of<T>(c).C, t.ilam, u_in, u_out};
+  sipg::SchwarzLaunch<T> a{c->mesh, t.n, t.schwarz, r, work_of<T>(c).C, t.ilam, u_in, u_out, mfma_of(c, t)};
   check(sipg::launch_schwarz<T>(a, c->stream), "schwarz");
 }
 
@@ -514,7 +599,7 @@ void fcg_precond(sipg_ctx *c) {
   if (!c->precond_graph) {
     // every work buffer exists before the capture (no allocation inside it)
     ensure_work<double>(c);
-    if (c->H.prm.precond_bits == 32) ensure_work<float>(c);
+    if (c->H.prm.precond_bits != 64) ensure_work<float>(c);
     check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "graph capture");
     hipGraph_t g = nullptr;
     try {
@@ -672,7 +757,7 @@ void fcg_start(sipg_ctx *c, double *x, const double *b) { residual_norm2(c, x, b
 
 void fcg_first_precond(sipg_ctx *c) {
   const int64_t N = level_ndof(c->H, c->L);
-  const bool single = c->H.prm.precond_bits == 32;
+  const bool single = c->H.prm.precond_bits != 64;
   if (single) {
     ensure_work<float>(c);
     check(sipg::launch_convert<float, double>(c->cg_r, c->w32.fL, N, c->stream), "precond cast");
@@ -695,7 +780,7 @@ void fcg_apply_update(sipg_ctx *c) {
   check(sipg::launch_finalize(c->partial, sipg::apply_num_blocks(c->mesh.E, c->t64[c->L].n), 1.0,
                               c->scal + sipg::FS_PQ, c->stream),
         "dot");
-  float *r32 = c->H.prm.precond_bits == 32 ? c->w32.fL : nullptr;
+  float *r32 = c->H.prm.precond_bits != 64 ? c->w32.fL : nullptr;
   check(sipg::launch_fcg_r(c->cg_r, c->cg_q, N, c->scal, c->partial, r32, c->stream), "fcg update");
   check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + sipg::FS_RR, c->stream, c->scal,
                               c->host_scal_dev, sipg::FS_COUNT),
@@ -713,7 +798,7 @@ void fcg_confirm(sipg_ctx *c, double *x, const double *b) {
 void fcg_restart_from_true(sipg_ctx *c) {
   const int64_t N = level_ndof(c->H, c->L);
   check(sipg::launch_convert<double, double>(c->cg_q, c->cg_r, N, c->stream), "copy");
-  if (c->H.prm.precond_bits == 32)
+  if (c->H.prm.precond_bits != 64)
     check(sipg::launch_convert<float, double>(c->cg_r, c->w32.fL, N, c->stream), "precond cast");
   op_apply<double>(c, c->L, c->cg_p, c->cg_q, nullptr);
 }
@@ -721,7 +806,7 @@ void fcg_restart_from_true(sipg_ctx *c) {
 void fcg_precond_update(sipg_ctx *c, double *x) {
   const int64_t N = level_ndof(c->H, c->L);
   fcg_precond(c);
-  if (c->H.prm.precond_bits == 32) {
+  if (c->H.prm.precond_bits != 64) {
     check(sipg::launch_fcg_dot2<float>(c->w32.uL, c->cg_q, c->cg_r, N, c->partial, c->stream), "dot2");
     check(sipg::launch_fcg_finalize2(c->partial, c->scal, c->stream), "dot2");
     check(sipg::launch_fcg_xp<float>(x, c->cg_p, c->w32.uL, N, c->scal, c->x_pending, c->stream), "fcg update");
@@ -770,8 +855,8 @@ int sipg_footprint(const sipg_params *p, size_t *bytes) {
     sipg::build_hierarchy(*p, H);
     const int L = (int)H.lev.size() - 1;
     const int64_t N = level_ndof(H, L);
-    size_t b = work_bytes(H, p->precond_bits == 32 ? sizeof(float) : sizeof(double));
-    if (p->precond_bits == 32) b += (size_t)level_ndof(H, 0) * sizeof(double);
+    size_t b = work_bytes(H, p->precond_bits != 64 ? sizeof(float) : sizeof(double));
+    if (p->precond_bits != 64) b += (size_t)level_ndof(H, 0) * sizeof(double);
     b += 4 * (size_t)N * sizeof(double);                 // flexible CG vectors
     b += (size_t)level_ndof(H, 0) * sizeof(double) * 3;  // coarse work
     b += 1 << 20;                                        // tables and scalars (bound)
@@ -1024,7 +1109,7 @@ int sipg_time_kernel(sipg_ctx *c, int kernel, int level, int bits, int reps, dou
       check(sipg::launch_fill<T>(f, N, (T)0.5, c->stream), "fill");
       check(sipg::launch_fill<T>(r, N, (T)0.75, c->stream), "fill");
       const LevelTabs<T> &t = tabs_of<T>(c, l);
-      sipg::SchwarzLaunch<T> sa{c->mesh, t.n, t.schwarz, r, w.C, t.ilam, u, u};
+      sipg::SchwarzLaunch<T> sa{c->mesh, t.n, t.schwarz, r, w.C, t.ilam, u, u, mfma_of(c, t)};
       check(sipg::launch_schwarz_local<T>(sa, c->stream), "schwarz");  // valid corrections in C
       hipEvent_t e0, e1;
       check(hipEventCreate(&e0), "event");

@@ -1,0 +1,68 @@
+"""FP16 local solves on the matrix cores (precond_bits = 16): the
+fast-diagonalization contractions of the Schwarz smoother on levels with
+cubic subdomains of 10-13 nodes (P = 7, 8) run in FP16 with FP32
+accumulation and per-subdomain power-of-two scaling, the rest of the
+preconditioner in FP32 and the outer flexible CG in FP64.
+
+The preconditioner (one V-cycle from zero) is compared with the FP64
+oracle's at a tolerance set by FP16 rounding (unit roundoff 4.9e-4 per
+stored intermediate, six of them per local solve): 1e-2.  That the
+matrix-core path ran is checked by its error being well above the FP32
+preconditioner's (which stays below 1e-5).  Solves reach 1e-10 and the
+exact discrete solution (flexible CG recovers the accuracy)."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_04796_amd.workloads import fourier_modes
+
+from _gpu import announce, dev, host, pair, rel, zeros
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (ne, length, P, overlap): m = 12, 13, 10, 11 nodes per subdomain side
+    ((4, 3, 5), (2.0, 1.0, 0.5), 7, "rel"),
+    ((3, 4, 3), (1.0, 1.0, 1.0), 8, "rel"),
+    ((4, 4, 3), (1.0, 1.0, 1.0), 7, "min"),
+    ((3, 3, 4), (1.0, 3.0, 1.0), 8, "min"),
+]
+
+
+@pytest.mark.parametrize("ne,length,P,overlap", CASES)
+def test_fp16_preconditioner(ne, length, P, overlap):
+    announce("fp16 precond", ne, length, P, overlap)
+    k, phi, amp = fourier_modes(2, 3)
+    errs = {}
+    for bits in (16, 32):
+        h, s = pair(ne, length, P, overlap=overlap, precond_bits=bits)
+        f = oracle.fourier_rhs(k, phi, amp, h)
+        z = zeros(h.ndof())
+        s.precond(dev(f), z)
+        errs[bits] = rel(host(z), oracle.vcycle(np.zeros_like(f), f, h))
+        s.close()
+    print(f"  precond rel. L2 error: FP16 local solves {errs[16]:.2e}, FP32 {errs[32]:.2e}")
+    assert errs[32] <= 1e-5
+    assert 1e-5 < errs[16] <= 1e-2
+
+
+@pytest.mark.parametrize("ne,length,P,overlap", CASES[:2])
+def test_fp16_preconditioned_solve(ne, length, P, overlap):
+    announce("fp16 solve", ne, length, P, overlap)
+    h, s = pair(ne, length, P, overlap=overlap, precond_bits=64)
+    k, phi, amp = fourier_modes(0, 3)
+    b = oracle.fourier_rhs(k, phi, amp, h)
+    x = zeros(h.ndof())
+    it64, _ = s.pcg_solve(x, dev(b), rtol=1e-10, maxit=60)
+    s.close()
+    h, s = pair(ne, length, P, overlap=overlap, precond_bits=16)
+    x = zeros(h.ndof())
+    it, rr = s.pcg_solve(x, dev(b), rtol=1e-10, maxit=60)
+    s.close()
+    print(f"  iterations: FP16 local solves {it}, FP64 {it64}")
+    assert rr <= 1e-10
+    assert it <= it64 + 2
+    xs = oracle.exact_solution(b, h)
+    xh = host(x)
+    assert rel(xh - xh.mean(), xs) <= 1e-8
