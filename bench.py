@@ -118,7 +118,7 @@ def cpu_baseline(wl, cycles, k, phi, amp):
     }
 
 
-def fcg_timing(wl, bits, b, steps, warmup, keep=None):
+def fcg_timing(wl, bits, b, steps, warmup, keep=None, autotune=True):
     """Flexible CG from x0 = 0 to 1e-10 on workload wl with the given
     preconditioner precision (16: FP32 with FP16 matrix-core local solves):
     mean wall time over `steps` solves; keep[bits] receives the solution."""
@@ -126,6 +126,8 @@ def fcg_timing(wl, bits, b, steps, warmup, keep=None):
     from paper_1612_04796_amd import sipg
     s = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
                     smooth_growth=wl.growth, precond_bits=bits)
+    if autotune:
+        s.autotune()
     x = torch.zeros_like(b)
     for _ in range(max(1, warmup)):
         x.zero_()
@@ -237,6 +239,11 @@ def main():
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel timing")
     ap.add_argument("--serving-requests", type=int, default=24,
                     help="requests of the serving stream run after the main measurement (0 = skip)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in launch shapes (no sipg_autotune before the timed runs)")
+    ap.add_argument("--fcg-only", type=int, default=0, metavar="BITS",
+                    help="profiling run: only the flexible-CG timing of --workload with this "
+                         "preconditioner precision (64, 32 or 16); prints its JSON and exits")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this solver's build runs on a single MI355X "
@@ -253,9 +260,24 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     wl = WORKLOADS[args.workload]
+    if args.fcg_only:
+        s = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
+                        smooth_growth=wl.growth)
+        b = torch.zeros(s.ndof(), dtype=torch.float64, device="cuda")
+        k, phi, amp = fourier_modes(0, wl.kmax)
+        s.rhs_fourier(k, phi, amp, b)
+        s.close()
+        print(json.dumps({"workload": wl.name, "precond_bits": args.fcg_only,
+                          **fcg_timing(wl, args.fcg_only, b, args.steps, args.warmup,
+                                       autotune=not args.no_autotune)}))
+        return
     log(f"workload {wl.name}: ne={wl.ne} P={wl.P} overlap={wl.overlap} N={wl.ndof}")
     s = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
                     smooth_growth=wl.growth)
+    if not args.no_autotune:
+        s.autotune()
+    tuning = {f"level{l}": list(s.tuning(l, 64)) for l in range(1, s.L + 1)}
+    log(f"launch shapes (elements / subdomains per workgroup, 0 = default): {tuning}")
     N = s.ndof()
     k, phi, amp = fourier_modes(0, wl.kmax)
     b = torch.zeros(N, dtype=torch.float64, device="cuda")
@@ -320,9 +342,10 @@ def main():
 
     # ---- flexible CG on the same workload, FP64 and FP32 preconditioner
     detail = {"kernels_ms_per_launch": kern, "launches_per_solve": per_solve,
-              "iterations": cyc, "final_relres": rr}
+              "iterations": cyc, "final_relres": rr, "launch_shapes": tuning}
     for bits in (64, 32):
-        detail[f"fcg_precond_fp{bits}"] = fcg_timing(wl, bits, b, args.steps, args.warmup)
+        detail[f"fcg_precond_fp{bits}"] = fcg_timing(wl, bits, b, args.steps, args.warmup,
+                                                    autotune=not args.no_autotune)
     # ---- mixed precision at the 32^3, P = 7 workload (16.8M unknowns)
     if not args.no_mixed:
         wl4 = WORKLOADS["cube32_p7_rel"]
@@ -335,7 +358,8 @@ def main():
         mixed = {"workload": wl4.name, "ndof": wl4.ndof}
         sols = {}
         for bits in (64, 32, 16):
-            mixed[f"fcg_precond_fp{bits}"] = fcg_timing(wl4, bits, b4, args.steps, args.warmup, sols)
+            mixed[f"fcg_precond_fp{bits}"] = fcg_timing(wl4, bits, b4, args.steps, args.warmup, sols,
+                                                        autotune=not args.no_autotune)
         for bits in (32, 16):
             m = mixed[f"fcg_precond_fp{bits}"]
             m["speedup_over_fp64"] = mixed["fcg_precond_fp64"]["ms_per_solve"] / m["ms_per_solve"]

@@ -194,6 +194,26 @@ typedef enum {
  * Synchronizes. */
 int sipg_time_kernel(sipg_ctx *c, int kernel, int level, int bits, int reps, double *ms);
 
+/* Autotuner.  For every level >= 1 of the context (FP64, and FP32 when
+ * precond_bits is 32 or 16) times each candidate launch shape of the
+ * operator kernel (elements per workgroup: powers of two up to the most that
+ * fit 256 threads) and of the compile-time-shape local-solve kernel
+ * (subdomains per workgroup, 1 up to the most its LDS tile allows) with
+ * `reps` launches between HIP events on the context stream, and keeps the
+ * fastest for all later launches of the context.  Choices are cached for the
+ * process by (precision, order, subdomain shape, element count), so later
+ * contexts of the same shape take them without timing.  Every element and
+ * subdomain is computed as before; only the partition of the fused p.Ap and
+ * residual-norm partial sums follows the new workgroup count.  Overwrites
+ * the context's internal work vectors; drops a captured preconditioner graph
+ * (captured again on its next use).  Synchronizes.  reps in 1..1000. */
+int sipg_autotune(sipg_ctx *c, int reps);
+/* Launch shapes in use on level `level` (>= 1, or -1 for the top) in
+ * precision `bits` (64 or 32): elements per workgroup of the operator kernel
+ * and subdomains per workgroup of the local-solve kernel; 0 = the built-in
+ * default (not tuned, or the level has no such kernel). */
+int sipg_tuning(const sipg_ctx *c, int level, int bits, int *apply_epb, int *schwarz_spb);
+
 /* Context options. */
 typedef enum {
   SIPG_OPT_GRAPH = 0  /* value 1: capture the flexible-CG preconditioner V-cycle into a

@@ -25,12 +25,17 @@ struct ApplyLaunch {
   T *partial;       // PLAIN only: one partial dot product per block, or null
   const T *J;       // RESTRICT: n x nc interpolation matrix
   int nc;           // RESTRICT: coarse nodes per direction
+  int epb = 0;      // elements per workgroup (0: the default choice)
 };
 template <typename T>
 hipError_t launch_apply(const ApplyLaunch<T> &a, hipStream_t st);
 
-// Number of partial sums launch_apply / launch_apply_large write with partials.
-int apply_num_blocks(int E, int n);
+// Number of partial sums launch_apply / launch_apply_large write with partials
+// (epb as in ApplyLaunch).
+int apply_num_blocks(int E, int n, int epb = 0);
+// Largest elements-per-workgroup of the compile-time operator kernel of order
+// n - 1 (0 when the order uses the large-element path).
+int apply_max_epb(int n);
 
 // Orders whose elements do not fit in LDS (n = 33): axis-by-axis operator
 // passes from global memory.  tmp holds E*(n^3 + n^2*nc) values (restriction
@@ -88,7 +93,12 @@ struct SchwarzLaunch {
   const T *u_in;
   T *u_out;
   const MfmaTabs *mfma = nullptr;  // FP32 levels: local solves in FP16 on the matrix cores
+  int spb = 0;                     // subdomains per workgroup of the compile-time-shape kernel
+                                   // (0: its default)
 };
+// Largest subdomains-per-workgroup of the compile-time-shape local-solve
+// kernel for (n, m) (0 when there is none).
+int schwarz_fixed_max_spb(int n, const int m[3]);
 template <typename T>
 hipError_t launch_schwarz(const SchwarzLaunch<T> &a, hipStream_t st);
 // the two phases separately: local solves into C, then the assembly into u

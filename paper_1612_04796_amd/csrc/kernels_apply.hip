@@ -362,10 +362,14 @@ int apply_epb(int E, int n) {
   return std::max(1, std::min(full, 64 / (n * n)));
 }
 
+int launch_epb(int E, int n, int epb) {
+  return epb > 0 ? std::min(epb, std::max(1, 256 / (n * n))) : apply_epb(E, n);
+}
+
 template <typename T, int N, int MODE, bool DOT>
 hipError_t launch_mode(const ApplyLaunch<T> &a, hipStream_t st) {
   using Sh = ApplyShape<N>;
-  const int epb = apply_epb(a.mesh.E, N);
+  const int epb = launch_epb(a.mesh.E, N, a.epb);
   const int nblk = (a.mesh.E + epb - 1) / epb;
   const int nth = std::min(Sh::NTH, (epb * N * N + 63) / 64 * 64);
   const size_t shm = 2 * (size_t)epb * N * N * N * sizeof(T);
@@ -411,11 +415,13 @@ hipError_t launch_prolong_n(const ProlongLaunch<T, TC> &a, hipStream_t st) {
 
 }  // namespace
 
-int apply_num_blocks(int E, int n) {
+int apply_num_blocks(int E, int n, int epb) {
   if (apply_is_large(n)) return apply_large_num_blocks(E, n);
-  const int epb = apply_epb(E, n);
-  return (E + epb - 1) / epb;
+  const int b = launch_epb(E, n, epb);
+  return (E + b - 1) / b;
 }
+
+int apply_max_epb(int n) { return apply_is_large(n) ? 0 : std::max(1, 256 / (n * n)); }
 
 #define SIPG_ORDER_CASES(X) \
   X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17)

@@ -633,7 +633,7 @@ template <typename T, int N, int MX, int MY, int MZ>
 hipError_t launch_fixed(const SchwarzLaunch<T> &a, hipStream_t st) {
   using Sh = FdmShape<MX, MY, MZ>;
   static_assert(Sh::SPB * Sh::TILE * sizeof(T) <= 160 * 1024, "subdomain tile exceeds LDS");
-  const int spb = Sh::SPB;
+  const int spb = a.spb > 0 ? std::min(a.spb, Sh::SPB) : Sh::SPB;
   const int nblk = (a.mesh.E + spb - 1) / spb;
   const int nth = std::min(Sh::NTH, ((spb * Sh::LINES + Sh::LPT - 1) / Sh::LPT + 63) / 64 * 64);
   schwarz_fdm_fixed<T, N, MX, MY, MZ><<<nblk, nth, 0, st>>>(a.mesh, a.tabs, a.r, a.C, spb);
@@ -663,6 +663,18 @@ hipError_t launch_fixed_if_any(const SchwarzLaunch<T> &a, hipStream_t st, bool &
 }
 
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+}  // namespace
+
+int schwarz_fixed_max_spb(int n, const int m[3]) {
+#define SIPG_MAXSPB(NN, AX, AY, AZ) \
+  if (n == NN && m[0] == AX && m[1] == AY && m[2] == AZ) return FdmShape<AX, AY, AZ>::SPB;
+  SIPG_FDM_SHAPES(SIPG_MAXSPB)
+#undef SIPG_MAXSPB
+  return 0;
+}
+
+namespace {
 
 size_t lds_bytes(const int m[3], size_t eb) { return (size_t)m[2] * m[1] * (m[0] | 1) * eb; }
 

@@ -6,9 +6,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -45,6 +48,8 @@ struct LevelTabs {
   const T *ilam = nullptr;  // 1 / (lam_x + lam_y + lam_z) per subdomain entry (levels >= 1)
   sipg::MfmaTabs mfma{};    // FP16 matrix-core local solves (FP32 levels that have them)
   bool has_mfma = false;
+  int apply_epb = 0;        // launch parameters chosen by sipg_autotune (0: defaults)
+  int schwarz_spb = 0;
   int n = 0, nc = 0;
   int64_t ndof = 0;
 };
@@ -436,7 +441,7 @@ void run_apply(sipg_ctx *c, const sipg::ApplyLaunch<T> &a, const char *what) {
 template <typename T>
 void op_apply(sipg_ctx *c, int l, const T *u, T *y, T *partial) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
-  sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, nullptr, y, sipg::APPLY_PLAIN, partial, nullptr, 0};
+  sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, nullptr, y, sipg::APPLY_PLAIN, partial, nullptr, 0, t.apply_epb};
   run_apply<T>(c, a, "apply_A");
 }
 
@@ -444,7 +449,7 @@ void op_apply(sipg_ctx *c, int l, const T *u, T *y, T *partial) {
 template <typename T>
 void op_residual(sipg_ctx *c, int l, const T *u, const T *f, T *r, T *partial = nullptr) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
-  sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, f, r, sipg::APPLY_RESID, partial, nullptr, 0};
+  sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, f, r, sipg::APPLY_RESID, partial, nullptr, 0, t.apply_epb};
   run_apply<T>(c, a, "residual");
 }
 
@@ -453,8 +458,8 @@ void op_residual(sipg_ctx *c, int l, const T *u, const T *f, T *r, T *partial = 
 // written to the host mirror
 void residual_norm2(sipg_ctx *c, const double *u, const double *f, double *r, int slot, bool publish = false) {
   op_residual<double>(c, c->L, u, f, r, c->partial);
-  check(sipg::launch_finalize(c->partial, sipg::apply_num_blocks(c->mesh.E, c->H.lev[c->L].n), 1.0,
-                              c->scal + slot, c->stream, c->scal, publish ? c->host_scal_dev : nullptr,
+  check(sipg::launch_finalize(c->partial, sipg::apply_num_blocks(c->mesh.E, c->H.lev[c->L].n, c->t64[c->L].apply_epb),
+                              1.0, c->scal + slot, c->stream, c->scal, publish ? c->host_scal_dev : nullptr,
                               sipg::FS_COUNT),
         "residual norm");
 }
@@ -462,7 +467,7 @@ void residual_norm2(sipg_ctx *c, const double *u, const double *f, double *r, in
 template <typename T>
 void op_residual_restrict(sipg_ctx *c, int l, const T *u, const T *f, T *fc) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
-  sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, f, fc, sipg::APPLY_RESTRICT, nullptr, t.J, t.nc};
+  sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, f, fc, sipg::APPLY_RESTRICT, nullptr, t.J, t.nc, t.apply_epb};
   run_apply<T>(c, a, "residual_restrict");
 }
 
@@ -475,7 +480,8 @@ const sipg::MfmaTabs *mfma_of(const sipg_ctx *c, const LevelTabs<T> &t) {
 template <typename T>
 void op_schwarz(sipg_ctx *c, int l, const T *r, const T *u_in, T *u_out) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
-  sipg::SchwarzLaunch<T> a{c->mesh, t.n, t.schwarz, r, work_of<T>(c).C, t.ilam, u_in, u_out, mfma_of(c, t)};
+  sipg::SchwarzLaunch<T> a{c->mesh, t.n, t.schwarz, r, work_of<T>(c).C, t.ilam, u_in, u_out, mfma_of(c, t),
+                          t.schwarz_spb};
   check(sipg::launch_schwarz<T>(a, c->stream), "schwarz");
 }
 
@@ -777,7 +783,8 @@ void fcg_first_precond(sipg_ctx *c) {
 void fcg_apply_update(sipg_ctx *c) {
   const int64_t N = level_ndof(c->H, c->L);
   op_apply<double>(c, c->L, c->cg_p, c->cg_q, c->partial);
-  check(sipg::launch_finalize(c->partial, sipg::apply_num_blocks(c->mesh.E, c->t64[c->L].n), 1.0,
+  check(sipg::launch_finalize(c->partial,
+                              sipg::apply_num_blocks(c->mesh.E, c->t64[c->L].n, c->t64[c->L].apply_epb), 1.0,
                               c->scal + sipg::FS_PQ, c->stream),
         "dot");
   float *r32 = c->H.prm.precond_bits != 64 ? c->w32.fL : nullptr;
@@ -828,6 +835,89 @@ void set_error(const std::string &m) { g_err = m; }
 
 }  // namespace detail
 }  // namespace sipg
+
+// ---- autotuner ------------------------------------------------------------
+namespace {
+
+// process-wide choices by (precision bits, level order n, m_x, m_y, m_z,
+// elements, matrix-core local solves): {elements per workgroup of the
+// operator kernel, subdomains per workgroup of the local-solve kernel}
+std::mutex g_tune_mu;
+std::map<std::array<int, 7>, std::array<int, 2>> g_tuned;
+
+// mean duration (ms) of one of `reps` launches after one untimed launch
+template <typename F>
+double time_launches(sipg_ctx *c, int reps, F &&launch) {
+  launch();
+  hipEvent_t e0, e1;
+  check(hipEventCreate(&e0), "event");
+  check(hipEventCreate(&e1), "event");
+  check(hipEventRecord(e0, c->stream), "event");
+  for (int i = 0; i < reps; ++i) launch();
+  check(hipEventRecord(e1, c->stream), "event");
+  check(hipEventSynchronize(e1), "event");
+  float el = 0.f;
+  check(hipEventElapsedTime(&el, e0, e1), "event");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return (double)el / reps;
+}
+
+template <typename T>
+void tune_level(sipg_ctx *c, int l, int reps) {
+  LevelTabs<T> &t = tabs_of<T>(c, l);
+  const sipg::MfmaTabs *mf = mfma_of(c, t);
+  const std::array<int, 7> key{(int)(8 * sizeof(T)), t.n, t.schwarz.m[0], t.schwarz.m[1], t.schwarz.m[2],
+                               c->mesh.E, mf != nullptr};
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      t.apply_epb = it->second[0];
+      t.schwarz_spb = it->second[1];
+      return;
+    }
+  }
+  ensure_work<T>(c);
+  Work<T> &w = work_of<T>(c);
+  const int64_t N = level_ndof(c->H, l);
+  T *u = w.uL, *f = w.fL, *r = w.r;
+  check(sipg::launch_fill<T>(u, N, (T)0.25, c->stream), "fill");
+  check(sipg::launch_fill<T>(f, N, (T)0.5, c->stream), "fill");
+  check(sipg::launch_fill<T>(r, N, (T)0.75, c->stream), "fill");
+  // operator: powers of two up to the full packing, and the full packing
+  const int full = sipg::apply_max_epb(t.n);
+  if (full > 1) {
+    std::vector<int> cand;
+    for (int e = 1; e < full; e *= 2) cand.push_back(e);
+    cand.push_back(full);
+    double best = 1e30;
+    int pick = 0;
+    for (int e : cand) {
+      t.apply_epb = e;
+      const double ms = time_launches(c, reps, [&] { op_residual<T>(c, l, u, f, r); });
+      if (ms < best) best = ms, pick = e;
+    }
+    t.apply_epb = pick;
+  }
+  // compile-time-shape local solves: 1 .. the most subdomains that fit
+  const int maxspb = mf ? 0 : sipg::schwarz_fixed_max_spb(t.n, t.schwarz.m);
+  if (maxspb > 1) {
+    double best = 1e30;
+    int pick = 0;
+    for (int sp = 1; sp <= maxspb; ++sp) {
+      t.schwarz_spb = sp;
+      sipg::SchwarzLaunch<T> sa{c->mesh, t.n, t.schwarz, r, w.C, t.ilam, u, u, mf, sp};
+      const double ms = time_launches(c, reps, [&] { check(sipg::launch_schwarz_local<T>(sa, c->stream), "schwarz"); });
+      if (ms < best) best = ms, pick = sp;
+    }
+    t.schwarz_spb = pick;
+  }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tuned[key] = {t.apply_epb, t.schwarz_spb};
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -891,7 +981,7 @@ int sipg_setup(const sipg_params *p, void *hip_stream, sipg_ctx **out) {
     // partial sums: the reductions use 2 * kDotBlocks, the fused p.Ap of the
     // top-level apply one per apply workgroup
     c->partial = c->alloc<double>(
-        std::max<size_t>(2 * sipg::kDotBlocks, sipg::apply_num_blocks(c->mesh.E, c->H.lev[c->L].n)));
+        std::max<size_t>(2 * sipg::kDotBlocks, sipg::apply_num_blocks(c->mesh.E, c->H.lev[c->L].n, 1)));
     c->rhs_k = c->alloc<int>(64 * 3);
     c->rhs_phi = c->alloc<double>(64 * 3);
     c->rhs_amp = c->alloc<double>(64);
@@ -1109,7 +1199,7 @@ int sipg_time_kernel(sipg_ctx *c, int kernel, int level, int bits, int reps, dou
       check(sipg::launch_fill<T>(f, N, (T)0.5, c->stream), "fill");
       check(sipg::launch_fill<T>(r, N, (T)0.75, c->stream), "fill");
       const LevelTabs<T> &t = tabs_of<T>(c, l);
-      sipg::SchwarzLaunch<T> sa{c->mesh, t.n, t.schwarz, r, w.C, t.ilam, u, u, mfma_of(c, t)};
+      sipg::SchwarzLaunch<T> sa{c->mesh, t.n, t.schwarz, r, w.C, t.ilam, u, u, mfma_of(c, t), t.schwarz_spb};
       check(sipg::launch_schwarz_local<T>(sa, c->stream), "schwarz");  // valid corrections in C
       hipEvent_t e0, e1;
       check(hipEventCreate(&e0), "event");
@@ -1141,6 +1231,39 @@ int sipg_time_kernel(sipg_ctx *c, int kernel, int level, int bits, int reps, dou
     else run(float());
     return (int)SIPG_OK;
   });
+}
+
+int sipg_autotune(sipg_ctx *c, int reps) {
+  if (!c) return fail(SIPG_EINVAL, "null context");
+  if (reps < 1 || reps > 1000) return fail(SIPG_EINVAL, "reps must be in 1..1000");
+  return guarded([&]() {
+    // a captured preconditioner holds the old launch shapes
+    if (c->precond_graph) {
+      check(hipStreamSynchronize(c->stream), "sync");
+      check(hipGraphExecDestroy(c->precond_graph), "graph");
+      c->precond_graph = nullptr;
+    }
+    for (int l = 1; l <= c->L; ++l) tune_level<double>(c, l, reps);
+    if (c->H.prm.precond_bits != 64)
+      for (int l = 1; l <= c->L; ++l) tune_level<float>(c, l, reps);
+    check(hipStreamSynchronize(c->stream), "autotune");
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_tuning(const sipg_ctx *c, int level, int bits, int *apply_epb, int *schwarz_spb) {
+  if (!c || !apply_epb || !schwarz_spb) return fail(SIPG_EINVAL, "null argument");
+  if (bits != 64 && bits != 32) return fail(SIPG_EINVAL, "bits must be 64 or 32");
+  const int l = level == -1 ? c->L : level;
+  if (l < 1 || l > c->L) return fail(SIPG_EINVAL, "level must be in 1..L or -1");
+  if (bits == 64) {
+    *apply_epb = c->t64[l].apply_epb;
+    *schwarz_spb = c->t64[l].schwarz_spb;
+  } else {
+    *apply_epb = c->t32[l].apply_epb;
+    *schwarz_spb = c->t32[l].schwarz_spb;
+  }
+  return SIPG_OK;
 }
 
 int sipg_set_option(sipg_ctx *c, int option, int value) {

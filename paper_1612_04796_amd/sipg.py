@@ -26,7 +26,8 @@ EXPORTS = (
     "sipg_level_info", "sipg_rhs_fourier", "sipg_apply_A", "sipg_residual", "sipg_schwarz",
     "sipg_smooth", "sipg_restrict", "sipg_prolong_add", "sipg_coarse_solve", "sipg_vcycle",
     "sipg_precond", "sipg_mg_solve", "sipg_pcg_solve", "sipg_residual_history",
-    "sipg_last_error", "sipg_host_table", "sipg_time_kernel", "sipg_set_option",
+    "sipg_last_error", "sipg_host_table", "sipg_time_kernel", "sipg_autotune", "sipg_tuning",
+    "sipg_set_option",
     "sipg_server_create", "sipg_server_submit", "sipg_server_progress", "sipg_server_status",
     "sipg_server_fetch", "sipg_server_destroy",
 )
@@ -95,6 +96,8 @@ def lib():
             "sipg_last_error": (ctypes.c_char_p, []),
             "sipg_host_table": (c_int, [P(Params), c_int, c_int, c_int, P(c_double), c_int, P(c_int)]),
             "sipg_time_kernel": (c_int, [vp, c_int, c_int, c_int, c_int, P(c_double)]),
+            "sipg_autotune": (c_int, [vp, c_int]),
+            "sipg_tuning": (c_int, [vp, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
             "sipg_set_option": (c_int, [vp, c_int, c_int]),
             "sipg_server_create": (c_int, [ctypes.c_size_t, c_int, P(vp)]),
             "sipg_server_submit": (c_int, [vp, P(Params), c_int, P(ctypes.c_int32), P(c_double), P(c_double),
@@ -293,6 +296,17 @@ class Solver:
         ms = ctypes.c_double()
         _check(lib().sipg_time_kernel(self._h, KERNELS[kernel], level, bits, reps, ctypes.byref(ms)))
         return ms.value
+
+    def autotune(self, reps=10):
+        """Time the candidate launch shapes of every level and keep the
+        fastest (see sipg_autotune)."""
+        _check(lib().sipg_autotune(self._h, int(reps)))
+
+    def tuning(self, level=-1, bits=64):
+        """(elements per workgroup, subdomains per workgroup) in use; 0 = default."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib().sipg_tuning(self._h, level, bits, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def set_option(self, option, value):
         """SIPG_OPT_GRAPH (0): replay the flexible-CG preconditioner from a

@@ -1,0 +1,55 @@
+"""The autotuner (sipg_autotune): it picks a launch shape per level among
+the valid candidates, leaves every computed value unchanged (the V-cycle
+and the preconditioner are bitwise the same before and after tuning, as
+each element and subdomain is computed the same way), keeps the solves
+converging, and later contexts of the same shape reuse its choices."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_04796_amd import sipg
+from paper_1612_04796_amd.workloads import fourier_modes, uniform_vector
+
+from _gpu import announce, dev, host, pair, zeros
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("ne,P,overlap,bits", [((6, 5, 4), 8, "rel", 64), ((5, 6, 4), 4, "min", 32),
+                                               ((4, 4, 5), 7, "rel", 16)])
+def test_autotune_keeps_results(ne, P, overlap, bits):
+    announce("autotune", ne, P, overlap, bits)
+    h, s = pair(ne, (1.0, 1.0, 1.0), P, overlap=overlap, precond_bits=bits)
+    k, phi, amp = fourier_modes(1, 3)
+    f = dev(oracle.fourier_rhs(k, phi, amp, h))
+    u0 = dev(uniform_vector(4, h.ndof()))
+
+    def outputs():
+        u = u0.clone()
+        s.vcycle(u, f)
+        z = zeros(h.ndof())
+        s.precond(f, z)
+        return host(u), host(z)
+
+    before = outputs()
+    s.autotune(reps=3)
+    after = outputs()
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    tb = 64 if bits == 64 else 32
+    for lv in range(1, h.L + 1):
+        n = h.levels[lv].n
+        epb, spb = s.tuning(lv, tb)
+        full = max(1, 256 // (n * n))
+        assert (epb == 0 and full == 1) or 1 <= epb <= full
+        assert spb >= 0
+    x = zeros(h.ndof())
+    it, rr = s.mg_solve(x, f, 1e-10, 60)
+    assert rr <= 1e-10
+    # a second context of the same shape takes the cached choices
+    s2 = sipg.Solver(ne=ne, length=(1.0, 1.0, 1.0), P=P, overlap=overlap, precond_bits=bits)
+    s2.autotune(reps=3)
+    for lv in range(1, h.L + 1):
+        assert s2.tuning(lv, tb) == s.tuning(lv, tb)
+    s2.close()
+    s.close()
