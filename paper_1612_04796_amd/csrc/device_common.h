@@ -18,6 +18,18 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
   return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
 }
 
+// Outputs larger than this many bytes are written with non-temporal stores:
+// they cannot stay in the 256 MB last-level cache together with the other
+// arrays a kernel and its successor touch (measured faster at 32^3, P = 7;
+// at 16^3 the next kernel reads smaller outputs back from that cache).
+constexpr long long kStreamOutBytes = 96ll << 20;
+
+template <typename T>
+__device__ __forceinline__ void store_out(T *p, T v, bool nt) {
+  if (nt) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 struct Mesh {
   int ne[3];   // elements per direction
   int E;       // ne[0]*ne[1]*ne[2]

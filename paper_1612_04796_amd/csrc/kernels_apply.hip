@@ -212,13 +212,11 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
     for (int k = 0; k < N; ++k) {
       const T y = yl[k * N2] + sc * o[k];
       if (MODE == MODE_APPLY) {
-        if (nt) __builtin_nontemporal_store(y, out + gbase + k * N2);
-        else out[gbase + k * N2] = y;
+        store_out(out + gbase + k * N2, y, nt);
         if (DOT) dot += v[k] * y;
       } else if (MODE == MODE_RESID) {
         const T r = fl[k] - y;
-        if (nt) __builtin_nontemporal_store(r, out + gbase + k * N2);
-        else out[gbase + k * N2] = r;
+        store_out(out + gbase + k * N2, r, nt);
         if (DOT) dot += r * r;
       } else {
         yl[k * N2] = fl[k] - y;
@@ -367,8 +365,6 @@ int apply_epb(int E, int n) {
   return std::max(1, std::min(full, 64 / (n * n)));
 }
 
-constexpr int64_t kStreamOutBytes = 96ll << 20;
-
 int launch_epb(int E, int n, int epb) {
   return epb > 0 ? std::min(epb, std::max(1, 256 / (n * n))) : apply_epb(E, n);
 }
@@ -382,9 +378,6 @@ hipError_t launch_mode(const ApplyLaunch<T> &a, hipStream_t st) {
   const size_t shm = 2 * (size_t)epb * N * N * N * sizeof(T);
   hipError_t e = allow_lds(apply_kernel<T, N, MODE, DOT>, shm);
   if (e != hipSuccess) return e;
-  // outputs too large to stay in the last-level cache with the kernel's
-  // other arrays bypass it (measured: faster at 16.8M FP64 values, slower
-  // at 3M, where the next kernel reads the output back from that cache)
   const bool nt = (int64_t)a.mesh.E * N * N * N * (int64_t)sizeof(T) > kStreamOutBytes;
   apply_kernel<T, N, MODE, DOT><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, a.partial, a.J, epb, nt);
   return hipGetLastError();
