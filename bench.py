@@ -72,6 +72,45 @@ def schwarz_flops(m):
     return 4 * vol * (mx + my + mz) + vol
 
 
+def solve_roofline(s, E, cycles, ms_measured):
+    """Roofline time of a whole FP64 MG solve (x0 = 0, `cycles` V(1,1) cycles
+    plus one residual norm per cycle and a final one): every launch priced at
+    max(algorithmic bytes / HBM peak, algorithmic flops / FP64 peak), summed,
+    and divided by the measured solve time.  Per level l >= 1 (n nodes per
+    direction, N_l unknowns, subdomain volume V): residual 24 B and 6n + 36
+    flop per unknown; residual + restriction 16 B per unknown plus 8 B per
+    coarse unknown; prolongation the same bytes; local solves 8 B per
+    unknown read plus 8 V B per subdomain written and 4 V (m_x + m_y + m_z)
+    + V flop per subdomain; assembly (1 + V/n^3) or (2 + V/n^3) x 8 B per
+    unknown (without or with the read of u).  Below the top level every
+    pre-smoothing step starts from zero.  Level 0: three plane passes of
+    16 B per unknown."""
+    bw, pk = HBM_PEAK_GBS * 1e9, FP64_VALU_PEAK_TFLOPS * 1e12
+    t = lambda by, fl: max(by / bw, fl / pk)
+    total = 0.0
+    L = s.L
+    for l in range(L, 0, -1):
+        n, m, N = level_geometry(s, l)
+        Nc = s.level_info(l - 1)["ndof"]
+        V = m[0] * m[1] * m[2]
+        nc = s.level_info(l - 1)["order"] + 1
+        res = t(24 * N, (6 * n + 36) * N)
+        rst = t(16 * N + 8 * Nc, (6 * n + 36) * N + 2 * E * (n ** 3 * nc + n ** 2 * nc ** 2 + n * nc ** 3))
+        pro = t(16 * N + 8 * Nc, 2 * E * (nc ** 3 * n + nc ** 2 * n ** 2 + nc * n ** 3))
+        fdm = t(8 * N + 8 * V * E, schwarz_flops(m) * E)
+        asm0 = t((1 + V / n ** 3) * 8 * N, V * E)
+        asm1 = t((2 + V / n ** 3) * 8 * N, V * E)
+        if l == L:  # check residual + both smoothing steps on a nonzero iterate (the first pre-step excepted)
+            per = res + fdm + asm1 + rst + pro + res + fdm + asm1
+            total += cycles * per + res - (asm1 - asm0)
+        else:
+            total += cycles * (fdm + asm0 + rst + pro + res + fdm + asm1)
+    N0 = s.level_info(0)["ndof"]
+    total += cycles * 3 * t(16 * N0, 0)
+    return {"t_roofline_ms": 1e3 * total, "t_measured_ms": ms_measured, "frac": 1e3 * total / ms_measured,
+            "model": "sum over all launches of max(bytes / 8 TB/s, flop / 78.6 TFLOP/s)"}
+
+
 def level_geometry(s, l):
     info = s.level_info(l)
     n = info["order"] + 1
@@ -80,8 +119,8 @@ def level_geometry(s, l):
 
 
 def cpu_baseline(wl, cycles, k, phi, amp):
-    """The FP64 oracle on the host: time two V-cycles plus their residual
-    norms of the same solve, scale to the solve's cycle count."""
+    """The FP64 oracle on the host: time a sample of V-cycles plus their
+    residual norms of the same solve, scale to the solve's cycle count."""
     import numpy as np
     import oracle
     from oracle.multigrid import _vcycle_global
@@ -292,14 +331,25 @@ def main():
     for i in range(args.warmup):
         it, rr = step()
         log(f"warmup {i}: {it} iterations, rel. residual {rr:.2e}")
+    # every top-level launch of the local-solve kernel inside the last timed
+    # solve is bracketed by HIP events on the library's stream (each event
+    # record costs a few microseconds, so the other solves run without them);
+    # the events are created here, before the timed region
+    s.trace_kernel("schwarz_solve")
+    s.trace_kernel(None)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = []
     for i in range(args.steps):
+        if i == args.steps - 1:
+            s.trace_kernel("schwarz_solve")
         it, rr = step()
         iters.append(it)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    traced_ms, traced_n = s.traced_kernel_ms()
+    s.trace_kernel(None)
+    log(f"local-solve kernel in the timed solves: {traced_n} launches, {1e3 * traced_ms:.2f} us mean")
     ms = 1e3 * elapsed / args.steps
     value = N * args.steps / elapsed
     log(f"timed {args.steps} solves: {ms:.3f} ms/solve, {value:.4g} unknowns/s, iterations {iters}, "
@@ -326,12 +376,14 @@ def main():
         + f"; dominant {dominant}")
     if dominant == "schwarz_solve":
         work = schwarz_flops(m) * E
-        achieved = work / (kern[dominant] * 1e-3) / 1e12
+        achieved = work / (traced_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VALU_PEAK_TFLOPS,
                 "traffic": pmc_traffic() if (n, m) == (9, (13, 13, 13)) else None,
                 "kernel": f"schwarz_fdm_fixed<double, {n}, {m[0]}, {m[1]}, {m[2]}>",
-                "work_per_launch": work, "ms_per_launch": kern[dominant]}
+                "work_per_launch": work, "ms_per_launch": traced_ms, "launches_timed": traced_n,
+                "timing": "HIP events around each launch of the kernel inside the last timed solve",
+                "ms_per_launch_isolated": kern[dominant]}
     else:
         bytes_per = {"residual": 24, "schwarz_assemble": 24, "restrict": 16 + 8 / 8, "prolong": 16 + 8 / 8}
         work = bytes_per.get(dominant, 24) * N
@@ -343,6 +395,10 @@ def main():
     # ---- flexible CG on the same workload, FP64 and FP32 preconditioner
     detail = {"kernels_ms_per_launch": kern, "launches_per_solve": per_solve,
               "iterations": cyc, "final_relres": rr, "launch_shapes": tuning}
+    if wl.solver == "mg":
+        detail["solve_roofline"] = solve_roofline(s, E, cyc, ms)
+        log(f"whole-solve roofline: {detail['solve_roofline']['t_roofline_ms']:.3f} ms of {ms:.3f} ms "
+            f"({detail['solve_roofline']['frac']:.2f})")
     for bits in (64, 32):
         detail[f"fcg_precond_fp{bits}"] = fcg_timing(wl, bits, b, args.steps, args.warmup,
                                                     autotune=not args.no_autotune)

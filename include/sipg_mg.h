@@ -216,11 +216,22 @@ int sipg_tuning(const sipg_ctx *c, int level, int bits, int *apply_epb, int *sch
 
 /* Context options. */
 typedef enum {
-  SIPG_OPT_GRAPH = 0  /* value 1: capture the flexible-CG preconditioner V-cycle into a
-                         HIP graph on its first use and replay it afterwards (needs a
-                         non-NULL stream at sipg_setup; kernel nodes only) */
+  SIPG_OPT_GRAPH = 0,       /* value 1: capture the flexible-CG preconditioner V-cycle into a
+                               HIP graph on its first use and replay it afterwards (needs a
+                               non-NULL stream at sipg_setup; kernel nodes only) */
+  SIPG_OPT_TRACE_KERNEL = 1 /* value k in SIPG_KERNEL_RESIDUAL..SIPG_KERNEL_PROLONG: from now
+                               on every launch of that kernel on the top level in FP64
+                               (inside sipg_mg_solve, sipg_vcycle, ...) is bracketed by a
+                               pair of HIP events on the context's stream (at most 1024
+                               launches are kept; later ones are not timed); -1 stops.
+                               Setting it drops the launches recorded so far.  Allocates
+                               the events when first set (not inside the solves). */
 } sipg_option;
 int sipg_set_option(sipg_ctx *c, int option, int value);
+/* Launch durations recorded under SIPG_OPT_TRACE_KERNEL: waits for the last
+ * recorded event, returns their count and mean duration in milliseconds
+ * (*mean_ms = 0 when none), and drops them (tracing stays on). */
+int sipg_traced_kernel_ms(sipg_ctx *c, double *mean_ms, int *count);
 
 /* ---- serving: continuous batching of heterogeneous solves ---------------
  * A server accepts solves of any mesh, order and aspect ratio (each a

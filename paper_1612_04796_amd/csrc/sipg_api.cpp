@@ -108,6 +108,12 @@ struct sipg_ctx {
   hipGraphExec_t precond_graph = nullptr;
   bool graph_failed = false;
   bool x_pending = false;  // flexible CG: x += alpha p not yet applied
+  // SIPG_OPT_TRACE_KERNEL: event pairs around the launches of one top-level
+  // FP64 kernel (none while a graph is being captured)
+  int trace_kernel = -1;
+  bool capturing = false;
+  std::vector<hipEvent_t> trace_ev;  // 2 * kTraceMax, created on first use
+  int trace_n = 0;
 
   template <typename T>
   T *alloc(size_t count) {
@@ -122,6 +128,7 @@ struct sipg_ctx {
   }
   ~sipg_ctx() {
     if (precond_graph) (void)hipGraphExecDestroy(precond_graph);
+    for (hipEvent_t e : trace_ev) (void)hipEventDestroy(e);
     for (void *p : allocs) (void)hipFree(p);
     if (host_scal) (void)hipHostFree(host_scal);
   }
@@ -428,6 +435,24 @@ void upload_tables(sipg_ctx *c) {
 }
 
 // ---- level operations -----------------------------------------------------
+constexpr int kTraceMax = 1024;
+
+// Opens a traced launch of `kernel` on level l in precision T: returns the
+// slot of its event pair (its start event recorded), or -1 when not traced.
+template <typename T>
+int trace_begin(sipg_ctx *c, int kernel, int l) {
+  if (c->trace_kernel != kernel || l != c->L || !std::is_same<T, double>::value || c->capturing ||
+      c->trace_n >= kTraceMax)
+    return -1;
+  const int k = c->trace_n++;
+  check(hipEventRecord(c->trace_ev[2 * k], c->stream), "trace event");
+  return k;
+}
+
+void trace_end(sipg_ctx *c, int k) {
+  if (k >= 0) check(hipEventRecord(c->trace_ev[2 * k + 1], c->stream), "trace event");
+}
+
 template <typename T>
 void run_apply(sipg_ctx *c, const sipg::ApplyLaunch<T> &a, const char *what) {
   if (sipg::apply_is_large(a.n)) {
@@ -450,7 +475,9 @@ template <typename T>
 void op_residual(sipg_ctx *c, int l, const T *u, const T *f, T *r, T *partial = nullptr) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
   sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, f, r, sipg::APPLY_RESID, partial, nullptr, 0, t.apply_epb};
+  const int k = trace_begin<T>(c, SIPG_KERNEL_RESIDUAL, l);
   run_apply<T>(c, a, "residual");
+  trace_end(c, k);
 }
 
 // ||f - A u||^2 into scal[slot], r = f - A u (FP64, top level)
@@ -468,7 +495,9 @@ template <typename T>
 void op_residual_restrict(sipg_ctx *c, int l, const T *u, const T *f, T *fc) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
   sipg::ApplyLaunch<T> a{c->mesh, t.n, t.apply, u, f, fc, sipg::APPLY_RESTRICT, nullptr, t.J, t.nc, t.apply_epb};
+  const int k = trace_begin<T>(c, SIPG_KERNEL_RESTRICT, l);
   run_apply<T>(c, a, "residual_restrict");
+  trace_end(c, k);
 }
 
 // the FP16 matrix-core local solves: FP32 levels of a precond_bits = 16 context
@@ -482,7 +511,12 @@ void op_schwarz(sipg_ctx *c, int l, const T *r, const T *u_in, T *u_out) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
   sipg::SchwarzLaunch<T> a{c->mesh, t.n, t.schwarz, r, work_of<T>(c).C, t.ilam, u_in, u_out, mfma_of(c, t),
                           t.schwarz_spb};
-  check(sipg::launch_schwarz<T>(a, c->stream), "schwarz");
+  int k = trace_begin<T>(c, SIPG_KERNEL_SCHWARZ_SOLVE, l);
+  check(sipg::launch_schwarz_local<T>(a, c->stream), "schwarz");
+  trace_end(c, k);
+  k = trace_begin<T>(c, SIPG_KERNEL_SCHWARZ_ASSEMBLE, l);
+  check(sipg::launch_schwarz_assemble<T>(a, c->stream), "schwarz");
+  trace_end(c, k);
 }
 
 // u_l += I_l u_{l-1}; with_mean: u_{l-1} is the level-0 solution whose
@@ -494,12 +528,14 @@ void op_prolong(sipg_ctx *c, int l, const TC *uc, bool with_mean, T *uf) {
   sipg::ProlongLaunch<T, TC> a{c->mesh.E, t.n, t.nc, t.J, uc,
                                with_mean ? c->coarse.partial_u : nullptr,
                                sipg::coarse_num_partials(c->coarse), 1.0 / (double)N0, uf};
+  const int k = trace_begin<T>(c, SIPG_KERNEL_PROLONG, l);
   if (sipg::apply_is_large(t.n)) {
     ensure_work<T>(c);
     check(sipg::launch_prolong_large<T, TC>(a, work_of<T>(c).big, c->stream), "prolong");
   } else {
     check(sipg::launch_prolong<T, TC>(a, c->stream), "prolong");
   }
+  trace_end(c, k);
 }
 
 template <typename T>
@@ -608,14 +644,17 @@ void fcg_precond(sipg_ctx *c) {
     if (c->H.prm.precond_bits != 64) ensure_work<float>(c);
     check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "graph capture");
     hipGraph_t g = nullptr;
+    c->capturing = true;
     try {
       fcg_precond_body(c);
     } catch (...) {
+      c->capturing = false;
       (void)hipStreamEndCapture(c->stream, &g);
       if (g) (void)hipGraphDestroy(g);
       c->graph_failed = true;
       throw;
     }
+    c->capturing = false;
     check(hipStreamEndCapture(c->stream, &g), "graph capture");
     hipError_t e = hipGraphInstantiate(&c->precond_graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -1268,9 +1307,41 @@ int sipg_tuning(const sipg_ctx *c, int level, int bits, int *apply_epb, int *sch
 
 int sipg_set_option(sipg_ctx *c, int option, int value) {
   if (!c) return fail(SIPG_EINVAL, "null context");
-  if (option != SIPG_OPT_GRAPH) return fail(SIPG_EINVAL, "unknown option");
-  c->use_graph = value != 0;
-  return SIPG_OK;
+  if (option == SIPG_OPT_GRAPH) {
+    c->use_graph = value != 0;
+    return SIPG_OK;
+  }
+  if (option != SIPG_OPT_TRACE_KERNEL) return fail(SIPG_EINVAL, "unknown option");
+  if (value != -1 && (value < SIPG_KERNEL_RESIDUAL || value > SIPG_KERNEL_PROLONG))
+    return fail(SIPG_EINVAL, "trace kernel must be -1 or a SIPG_KERNEL_* value");
+  return guarded([&]() {
+    if (value >= 0 && c->trace_ev.empty()) {
+      c->trace_ev.assign(2 * kTraceMax, nullptr);
+      // device-scope release: no system-wide cache flush at each record
+      for (hipEvent_t &e : c->trace_ev) check(hipEventCreateWithFlags(&e, hipEventReleaseToDevice), "trace event");
+    }
+    c->trace_kernel = value;
+    c->trace_n = 0;
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_traced_kernel_ms(sipg_ctx *c, double *mean_ms, int *count) {
+  if (!c || !mean_ms || !count) return fail(SIPG_EINVAL, "null argument");
+  return guarded([&]() {
+    double sum = 0.0;
+    const int n = c->trace_n;
+    if (n > 0) check(hipEventSynchronize(c->trace_ev[2 * n - 1]), "trace event");
+    for (int k = 0; k < n; ++k) {
+      float ms = 0.f;
+      check(hipEventElapsedTime(&ms, c->trace_ev[2 * k], c->trace_ev[2 * k + 1]), "trace event");
+      sum += ms;
+    }
+    *count = n;
+    *mean_ms = n > 0 ? sum / n : 0.0;
+    c->trace_n = 0;
+    return (int)SIPG_OK;
+  });
 }
 
 int sipg_residual_history(const sipg_ctx *c, double *out, int cap, int *n) {

@@ -27,7 +27,7 @@ EXPORTS = (
     "sipg_smooth", "sipg_restrict", "sipg_prolong_add", "sipg_coarse_solve", "sipg_vcycle",
     "sipg_precond", "sipg_mg_solve", "sipg_pcg_solve", "sipg_residual_history",
     "sipg_last_error", "sipg_host_table", "sipg_time_kernel", "sipg_autotune", "sipg_tuning",
-    "sipg_set_option",
+    "sipg_set_option", "sipg_traced_kernel_ms",
     "sipg_server_create", "sipg_server_submit", "sipg_server_progress", "sipg_server_status",
     "sipg_server_fetch", "sipg_server_destroy",
 )
@@ -99,6 +99,7 @@ def lib():
             "sipg_autotune": (c_int, [vp, c_int]),
             "sipg_tuning": (c_int, [vp, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
             "sipg_set_option": (c_int, [vp, c_int, c_int]),
+            "sipg_traced_kernel_ms": (c_int, [vp, P(c_double), P(c_int)]),
             "sipg_server_create": (c_int, [ctypes.c_size_t, c_int, P(vp)]),
             "sipg_server_submit": (c_int, [vp, P(Params), c_int, P(ctypes.c_int32), P(c_double), P(c_double),
                                            c_double, c_int, P(ctypes.c_int64)]),
@@ -312,6 +313,19 @@ class Solver:
         """SIPG_OPT_GRAPH (0): replay the flexible-CG preconditioner from a
         captured HIP graph (needs a non-default stream)."""
         _check(lib().sipg_set_option(self._h, int(option), int(value)))
+
+    def trace_kernel(self, kernel):
+        """Bracket every later top-level FP64 launch of `kernel` (a KERNELS
+        name, or None to stop) with HIP events on the library's stream
+        (SIPG_OPT_TRACE_KERNEL)."""
+        self.set_option(1, -1 if kernel is None else KERNELS[kernel])
+
+    def traced_kernel_ms(self):
+        """(mean launch duration in ms, number of launches) of the traced
+        kernel since tracing started or since the last call."""
+        ms, n = ctypes.c_double(), ctypes.c_int()
+        _check(lib().sipg_traced_kernel_ms(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def residual_history(self):
         n = ctypes.c_int()

@@ -53,3 +53,33 @@ def test_autotune_keeps_results(ne, P, overlap, bits):
         assert s2.tuning(lv, tb) == s.tuning(lv, tb)
     s2.close()
     s.close()
+
+
+def test_kernel_trace_counts_launches_and_keeps_results():
+    """SIPG_OPT_TRACE_KERNEL brackets each top-level FP64 launch of the chosen
+    kernel with events: one V(1,1) cycle from a nonzero iterate launches the
+    local solve, the assembly and the residual twice each on the top level and
+    the restriction and prolongation once; the traced cycle computes the same
+    values as an untraced one."""
+    announce("kernel trace")
+    h, s = pair((5, 4, 6), (1.0, 1.0, 1.0), 8, overlap="rel")
+    k, phi, amp = fourier_modes(2, 3)
+    f = dev(oracle.fourier_rhs(k, phi, amp, h))
+    u0 = dev(uniform_vector(6, h.ndof()))
+    ref = u0.clone()
+    s.vcycle(ref, f)
+    for name, launches in (("schwarz_solve", 2), ("schwarz_assemble", 2), ("residual", 2), ("restrict", 1),
+                           ("prolong", 1)):
+        s.trace_kernel(name)
+        u = u0.clone()
+        s.vcycle(u, f)
+        ms, n = s.traced_kernel_ms()
+        assert n == launches, (name, n)
+        assert 0.0 < ms < 1e3
+        assert np.array_equal(host(u), host(ref))
+        assert s.traced_kernel_ms() == (0.0, 0)
+    s.trace_kernel(None)
+    s.vcycle(u0.clone(), f)
+    assert s.traced_kernel_ms()[1] == 0
+    with pytest.raises(sipg.SipgError):
+        s.set_option(1, 7)
