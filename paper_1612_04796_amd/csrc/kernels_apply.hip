@@ -112,11 +112,40 @@ __device__ __forceinline__ void line_op_all(const T (&v)[N], T (&out)[N], const 
   out[0] += fd.gL - mu * fd.vL;
 }
 
+// First element of the group of EPB consecutive elements that workgroup
+// `blk` owns.  When the groups tile the x rows (ne_x divisible by EPB) they
+// are visited in column tiles of about 8 x 8 elements in x and y, each tile
+// marching along z: a tile's z neighbours were read a tile layer (a few
+// hundred KB) earlier and are still in the XCD's L2, where in plain linear
+// order they were a whole xy plane (megabytes) earlier and came back from
+// memory.  Used when an xy plane of the vector exceeds half an L2 (2 MB);
+// otherwise, or when the groups do not tile the rows, linear order.  Both
+// orders are bijections onto the groups.  (The same order for the local
+// solves and the assembly was slower: their neighbour reads are already
+// served by linear order.)
+__device__ __forceinline__ int group_first_element(const Mesh &g, int blk, int epb, bool tiled) {
+  if (!tiled || g.ne[0] % epb != 0) return blk * epb;
+  constexpr int TY = 8;
+  const int ngx = g.ne[0] / epb, tgx = epb >= 8 ? 1 : 8 / epb;
+  const int n1 = g.ne[1], n2 = g.ne[2];
+  const int row = ngx * TY * n2;  // groups in a full row of tiles
+  const int ty = blk / row;
+  int q = blk - ty * row;
+  const int h = min(TY, n1 - ty * TY);
+  const int tx = q / (tgx * h * n2);
+  q -= tx * tgx * h * n2;
+  const int w = min(tgx, ngx - tx * tgx);
+  const int ez = q / (w * h);
+  q -= ez * w * h;
+  const int y = q / w, x = q - y * w;
+  return elem_index(g, (tx * tgx + x) * epb, ty * TY + y, ez);
+}
+
 // EPB (elements per workgroup) is chosen at launch, at most ApplyShape<N>::EPB.
 template <typename T, int N, int MODE, bool DOT>
 __global__ void __launch_bounds__(ApplyShape<N>::NTH)
 apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restrict__ f, T *__restrict__ out,
-             T *__restrict__ partial, const T *__restrict__ J, int EPB, bool nt) {
+             T *__restrict__ partial, const T *__restrict__ J, int EPB, bool nt, bool tiled) {
   using Sh = ApplyShape<N>;
   constexpr int N2 = Sh::N2, N3 = Sh::N3;
   constexpr int NC = coarse_n(N);
@@ -125,7 +154,7 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
   T *sy = su + EPB * N3;
   __shared__ T red[16];
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int e0 = blk * EPB;
+  const int e0 = group_first_element(g, blk, EPB, tiled);
   const int nloc = min(EPB, g.E - e0);
   const int t = threadIdx.x;
   const bool active = t < nloc * N2;
@@ -379,7 +408,9 @@ hipError_t launch_mode(const ApplyLaunch<T> &a, hipStream_t st) {
   hipError_t e = allow_lds(apply_kernel<T, N, MODE, DOT>, shm);
   if (e != hipSuccess) return e;
   const bool nt = (int64_t)a.mesh.E * N * N * N * (int64_t)sizeof(T) > kStreamOutBytes;
-  apply_kernel<T, N, MODE, DOT><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, a.partial, a.J, epb, nt);
+  const bool tiled = (int64_t)a.mesh.ne[0] * a.mesh.ne[1] * N * N * N * (int64_t)sizeof(T) >= (2 << 20);
+  apply_kernel<T, N, MODE, DOT><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, a.partial, a.J, epb, nt,
+                                                        tiled);
   return hipGetLastError();
 }
 
