@@ -10,7 +10,8 @@
 //   (S^T x S^T x S^T)(f - m 1) = (S^T x S^T x S^T) f - m cs_z x cs_y x cs_x.
 //
 // Three kernels on 2D planes held in LDS, with the 1D eigenvector tables in
-// LDS too when they fit (lexicographic (z, y, x) order):
+// LDS too when they fit (lexicographic (z, y, x) order); when the planes are
+// few, each plane is shared by several workgroups (split kernels below):
 //   1. per z plane: x and y forward from the element-major f_0; plane sums
 //   2. per y plane: z forward, mean correction, Lambda^+, z backward
 //   3. per z plane: y and x backward into the element-major u_0; plane sums
@@ -236,6 +237,154 @@ coarse_plane_xy_bwd(Dims d, CoarseLaunch c, const double *__restrict__ t, double
   if (tid == 0) c.partial_u[z] = s;
 }
 
+// ---- split plane kernels: np workgroups share a plane ------------------------
+// With one workgroup per plane only 2 ne_d workgroups run (32 or 64 at the
+// 16^3 and 32^3 meshes) and most CUs idle.  Here each plane is shared by np
+// workgroups: the forward xy pass splits the plane's output columns (every
+// part reads the whole input plane, contracts x for its columns only, then y
+// on them), the z pass splits the columns of its (z, x) plane, the backward
+// xy pass splits the output rows (y backward for its rows, then x).  Tables
+// (and transposed copies where a contraction runs along a table row) are
+// staged in LDS; LDS row pitches are odd so that rows read by one wavefront
+// fall on different banks.  1024 threads per workgroup, outputs flat over
+// the threads.
+
+template <typename TI>
+__global__ void __launch_bounds__(1024)
+coarse_split_xy_fwd(Dims d, CoarseLaunch c, const TI *__restrict__ f0, double *__restrict__ t, int np) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  const int Nx = d.N[0], Ny = d.N[1], px = Nx + 1;
+  const int z = blockIdx.x, part = blockIdx.y;
+  const int cw = (Nx + np - 1) / np, x0 = part * cw, nx = min(cw, Nx - x0), pw = cw + 1;
+  double *P = reinterpret_cast<double *>(smem_raw);  // Ny x px: input plane
+  double *W = P + Ny * px;                            // Ny x pw: after x
+  double *sx = W + Ny * pw, *sy = sx + Nx * Nx;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  copy4(tid, Nx * Nx, nth, [&](int i) { return c.S[0][i]; }, [&](int i, double v) { sx[i] = v; });
+  copy4(tid, Ny * Ny, nth, [&](int i) { return c.S[1][i]; }, [&](int i, double v) { sy[i] = v; });
+  double s = 0.0;
+  copy4(tid, Nx * Ny, nth,
+        [&](int i) {
+          const int y = i / Nx;
+          return (double)f0[elem_major_p1(d, i - y * Nx, y, z)];
+        },
+        [&](int i, double v) {
+          const int y = i / Nx;
+          P[y * px + i - y * Nx] = v;
+          s += v;
+        });
+  s = block_sum_2d(s, red);
+  if (tid == 0 && part == 0) c.partial[z] = s;
+  __syncthreads();
+  for (int i = tid; i < Ny * nx; i += nth) {  // x forward on columns x0 .. x0 + nx
+    const int y = i / nx, j = i - y * nx;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int a = 0; a < Nx; ++a) acc += sx[a * Nx + x0 + j] * P[y * px + a];
+    W[y * pw + j] = acc;
+  }
+  __syncthreads();
+  for (int i = tid; i < Ny * nx; i += nth) {  // y forward
+    const int yo = i / nx, j = i - yo * nx;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int a = 0; a < Ny; ++a) acc += sy[a * Ny + yo] * W[a * pw + j];
+    t[((size_t)z * Ny + yo) * Nx + x0 + j] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(1024) coarse_split_z(Dims d, CoarseLaunch c, double *__restrict__ t, int np) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  __shared__ double mean_sh;
+  const int Nx = d.N[0], Ny = d.N[1], Nz = d.N[2];
+  const int y = blockIdx.x, part = blockIdx.y;
+  const int cw = (Nx + np - 1) / np, x0 = part * cw, nx = min(cw, Nx - x0), pw = cw + 1;
+  double *P = reinterpret_cast<double *>(smem_raw);  // Nz x pw
+  double *W = P + Nz * pw;                            // Nz x pw
+  double *sz = W + Nz * pw, *szt = sz + Nz * Nz;     // Sz and its transpose
+  const int tid = threadIdx.x, nth = blockDim.x;
+  copy4(tid, Nz * Nz, nth, [&](int i) { return c.S[2][i]; }, [&](int i, double v) {
+    sz[i] = v;
+    szt[(i % Nz) * Nz + i / Nz] = v;
+  });
+  copy4(tid, Nz * nx, nth, [&](int i) {
+    const int zz = i / nx;
+    return t[((size_t)zz * Ny + y) * Nx + x0 + i - zz * nx];
+  }, [&](int i, double v) {
+    const int zz = i / nx;
+    P[zz * pw + i - zz * nx] = v;
+  });
+  double s = 0.0;
+  for (int i = tid; i < Nz; i += nth) s += c.partial[i];
+  s = block_sum_2d(s, red);
+  if (tid == 0) mean_sh = s / ((double)Nx * Ny * Nz);
+  __syncthreads();
+  const double mean = mean_sh;
+  const double cy = c.colsum[1][y], ly = c.lam[1][y];
+  for (int i = tid; i < Nz * nx; i += nth) {  // z forward, mean correction, Lambda^+
+    const int o = i / nx, j = i - o * nx, x = x0 + j;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int a = 0; a < Nz; ++a) acc += sz[a * Nz + o] * P[a * pw + j];
+    const double cxy = c.colsum[0][x] * cy, lxy = c.lam[0][x] + ly;
+    const double v = acc - mean * c.colsum[2][o] * cxy;
+    const bool zero = (x == c.zero[0] && y == c.zero[1] && o == c.zero[2]);
+    W[o * pw + j] = zero ? 0.0 : v / (lxy + c.lam[2][o]);
+  }
+  __syncthreads();
+  for (int i = tid; i < Nz * nx; i += nth) {  // z backward
+    const int o = i / nx, j = i - o * nx;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int a = 0; a < Nz; ++a) acc += szt[a * Nz + o] * W[a * pw + j];
+    t[((size_t)o * Ny + y) * Nx + x0 + j] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(1024)
+coarse_split_xy_bwd(Dims d, CoarseLaunch c, const double *__restrict__ t, double *__restrict__ u0, int np) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  const int Nx = d.N[0], Ny = d.N[1], px = Nx + 1;
+  const int z = blockIdx.x, part = blockIdx.y;
+  const int rh = (Ny + np - 1) / np, y0 = part * rh, ny = min(rh, Ny - y0);
+  double *P = reinterpret_cast<double *>(smem_raw);  // Ny x px: input plane
+  double *W = P + Ny * px;                            // rh x px: after y
+  double *sxt = W + rh * px, *syt = sxt + Nx * Nx;   // transposed Sx and Sy
+  const int tid = threadIdx.x, nth = blockDim.x;
+  copy4(tid, Nx * Nx, nth, [&](int i) { return c.S[0][i]; },
+        [&](int i, double v) { sxt[(i % Nx) * Nx + i / Nx] = v; });
+  copy4(tid, Ny * Ny, nth, [&](int i) { return c.S[1][i]; },
+        [&](int i, double v) { syt[(i % Ny) * Ny + i / Ny] = v; });
+  const double *tz = t + (size_t)z * Nx * Ny;
+  copy4(tid, Nx * Ny, nth, [&](int i) { return tz[i]; }, [&](int i, double v) {
+    const int y = i / Nx;
+    P[y * px + i - y * Nx] = v;
+  });
+  __syncthreads();
+  for (int i = tid; i < ny * Nx; i += nth) {  // y backward on rows y0 .. y0 + ny
+    const int r = i / Nx, xq = i - r * Nx;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int a = 0; a < Ny; ++a) acc += syt[a * Ny + y0 + r] * P[a * px + xq];
+    W[r * px + xq] = acc;
+  }
+  __syncthreads();
+  double s = 0.0;
+  for (int i = tid; i < ny * Nx; i += nth) {  // x backward
+    const int r = i / Nx, x = i - r * Nx;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int a = 0; a < Nx; ++a) acc += sxt[a * Nx + x] * W[r * px + a];
+    u0[elem_major_p1(d, x, y0 + r, z)] = acc;
+    s += acc;
+  }
+  s = block_sum_2d(s, red);
+  if (tid == 0) c.partial_u[z * np + part] = s;
+}
+
 // LDS bytes of the plane kernels: two planes, plus the 1D tables when they fit
 constexpr size_t kCoarseLds = 150 * 1024;
 size_t plane_bytes(const Dims &d, int a, int b) { return 2 * (size_t)d.N[a] * d.N[b] * sizeof(double); }
@@ -245,7 +394,24 @@ size_t tab_bytes(const Dims &d, int a, int b) {
 
 }  // namespace
 
-int coarse_num_partials(const CoarseLaunch &c) { return c.N[2]; }
+// Workgroups per plane of the split kernels: doubled while the plane passes
+// have fewer than 256 workgroups and each part keeps at least 4 columns
+// (rows); 1 (one workgroup per plane) when their LDS would not fit.
+int coarse_parts(const CoarseLaunch &c) {
+  const int N0 = c.N[0], N1 = c.N[1], N2 = c.N[2];
+  int np = 1;
+  while (np < 8 && std::min(N1, N2) * np * 2 <= 256 && N0 / (2 * np) >= 4 && N1 / (2 * np) >= 4) np *= 2;
+  if (np == 1) return 1;
+  const size_t cw = (N0 + np - 1) / np, rh = (N1 + np - 1) / np;
+  const size_t tabs = (size_t)N0 * N0 + (size_t)N1 * N1;
+  const size_t fwd = (size_t)N1 * (N0 + 1) + N1 * (cw + 1) + tabs;
+  const size_t zk = 2 * (size_t)N2 * (cw + 1) + 2 * (size_t)N2 * N2;
+  const size_t bwd = (size_t)N1 * (N0 + 1) + rh * (N0 + 1) + tabs;
+  if (std::max(fwd, std::max(zk, bwd)) * sizeof(double) > kCoarseLds) return 1;
+  return np;
+}
+
+int coarse_num_partials(const CoarseLaunch &c) { return c.N[2] * coarse_parts(c); }
 
 template <typename K>
 static hipError_t allow_lds(K kernel, size_t shm) {
@@ -253,14 +419,9 @@ static hipError_t allow_lds(K kernel, size_t shm) {
   return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
 }
 
+// one workgroup per plane
 template <typename TI>
-hipError_t launch_coarse(const CoarseLaunch &c, const TI *f0, double *u0, bool subtract_mean, hipStream_t st) {
-  Dims d;
-  for (int i = 0; i < 3; ++i) {
-    d.N[i] = c.N[i];
-    d.ne[i] = c.ne[i];
-  }
-  const int64_t N0 = (int64_t)d.N[0] * d.N[1] * d.N[2];
+hipError_t launch_planes(const Dims &d, const CoarseLaunch &c, const TI *f0, double *u0, hipStream_t st) {
   size_t sxy = plane_bytes(d, 0, 1), sz = plane_bytes(d, 0, 2);
   if (sxy > kCoarseLds || sz > kCoarseLds) return hipErrorInvalidValue;
   const bool lds_xy = sxy + tab_bytes(d, 0, 1) <= kCoarseLds;
@@ -285,9 +446,39 @@ hipError_t launch_coarse(const CoarseLaunch &c, const TI *f0, double *u0, bool s
   else coarse_plane_z<false><<<d.N[1], blk, sz, st>>>(d, c, c.t0);
   if (lds_xy) coarse_plane_xy_bwd<true><<<d.N[2], blk, sxy, st>>>(d, c, c.t0, u0);
   else coarse_plane_xy_bwd<false><<<d.N[2], blk, sxy, st>>>(d, c, c.t0, u0);
+  return hipGetLastError();
+}
+
+template <typename TI>
+hipError_t launch_coarse(const CoarseLaunch &c, const TI *f0, double *u0, bool subtract_mean, hipStream_t st) {
+  Dims d;
+  for (int i = 0; i < 3; ++i) {
+    d.N[i] = c.N[i];
+    d.ne[i] = c.ne[i];
+  }
+  const int64_t N0 = (int64_t)d.N[0] * d.N[1] * d.N[2];
+  hipError_t e;
+  const int np = coarse_parts(c);
+  if (np > 1) {
+    const int Nx = d.N[0], Ny = d.N[1], Nz = d.N[2];
+    const size_t cw = (Nx + np - 1) / np, rh = (Ny + np - 1) / np;
+    const size_t tabs = (size_t)Nx * Nx + (size_t)Ny * Ny;
+    const size_t s1 = ((size_t)Ny * (Nx + 1) + Ny * (cw + 1) + tabs) * sizeof(double);
+    const size_t s2 = (2 * (size_t)Nz * (cw + 1) + 2 * (size_t)Nz * Nz) * sizeof(double);
+    const size_t s3 = ((size_t)Ny * (Nx + 1) + rh * (Nx + 1) + tabs) * sizeof(double);
+    if ((e = allow_lds(coarse_split_xy_fwd<TI>, s1)) != hipSuccess) return e;
+    if ((e = allow_lds(coarse_split_z, s2)) != hipSuccess) return e;
+    if ((e = allow_lds(coarse_split_xy_bwd, s3)) != hipSuccess) return e;
+    coarse_split_xy_fwd<TI><<<dim3(Nz, np), 1024, s1, st>>>(d, c, f0, c.t0, np);
+    coarse_split_z<<<dim3(Ny, np), 1024, s2, st>>>(d, c, c.t0, np);
+    coarse_split_xy_bwd<<<dim3(Nz, np), 1024, s3, st>>>(d, c, c.t0, u0, np);
+  } else {
+    if ((e = launch_planes<TI>(d, c, f0, u0, st)) != hipSuccess) return e;
+  }
   e = hipGetLastError();
   if (e != hipSuccess || !subtract_mean) return e;
-  if ((e = launch_finalize(c.partial_u, d.N[2], 1.0 / (double)N0, c.scalars + 1, st)) != hipSuccess) return e;
+  if ((e = launch_finalize(c.partial_u, coarse_num_partials(c), 1.0 / (double)N0, c.scalars + 1, st)) != hipSuccess)
+    return e;
   return launch_sub_scalar<double>(u0, N0, c.scalars + 1, st);
 }
 
