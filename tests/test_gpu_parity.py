@@ -109,7 +109,9 @@ def test_transfers(ne, length, P):
 # up to the 48 elements per direction the coarse planes allow, with odd and
 # unequal counts
 COARSE = [((3, 3, 3), (1.0, 1.0, 1.0)), ((4, 3, 5), (2.0, 1.0, 0.5)), ((16, 16, 16), (1.0, 1.0, 1.0)),
-          ((7, 32, 9), (1.0, 3.0, 1.0)), ((3, 40, 3), (1.0, 1.0, 1.0)), ((5, 4, 48), (1.0, 1.0, 2.0))]
+          ((7, 32, 9), (1.0, 3.0, 1.0)), ((3, 40, 3), (1.0, 1.0, 1.0)), ((5, 4, 48), (1.0, 1.0, 2.0)),
+          # planes shared by 4 workgroups with a ragged last part: columns (18 = 5+5+5+3), rows (18)
+          ((9, 20, 20), (1.0, 1.0, 1.0)), ((20, 9, 11), (2.0, 1.0, 1.0))]
 
 
 @pytest.mark.parametrize("ne,length", COARSE)
