@@ -192,7 +192,8 @@ def serving_run(nreq, seed, log_every=4):
     FP64 flexible CG to 1e-10) with Poisson arrivals at the rate that gives
     about 70 % utilisation.  The mean service time is measured first by
     serving the same requests one at a time; then the stream is replayed in
-    real time into a server with 8 slots.  Latency = finish - arrival."""
+    real time into a server with 8 slots (same-order requests that are ready
+    together share their operator launches).  Latency = finish - arrival."""
     import numpy as np
     import torch
     from paper_1612_04796_amd import sipg
@@ -242,6 +243,7 @@ def serving_run(nreq, seed, log_every=4):
             _a, _q, c = srv.progress(wait_ms=wait)
             finished = sum(1 for i in range(nxt) if srv.status(ids[i])["state"] in (sipg.REQ_DONE, sipg.REQ_FAILED))
         t_end = time.perf_counter() - t0
+        fused_launches, fused_requests = srv.stats()
         for i, rid in enumerate(ids):
             st = srv.status(rid)
             if st["state"] != sipg.REQ_DONE or st["relres"] > 1e-10:
@@ -264,6 +266,8 @@ def serving_run(nreq, seed, log_every=4):
         "total_unknowns": int(sum(ndof)),
         "iterations": iters,
         "precision": "FP32 preconditioner, FP64 flexible CG",
+        "batched_operator_launches": fused_launches,
+        "requests_in_batched_launches": fused_requests,
     }
 
 

@@ -273,6 +273,20 @@ int sipg_server_status(sipg_server *s, int64_t id, int *state, int *iters, doubl
  * the request's memory. */
 int sipg_server_fetch(sipg_server *s, int64_t id, double *u, void *hip_stream);
 
+/* Server options.  SIPG_SERVER_FUSE_APPLY (default 1): when several active
+ * requests of the same order, the same operator launch shape and a similar
+ * size (unknowns within a factor of 8) are ready for a flexible-CG iteration
+ * at the same time, their outer operator applications q = A p (with the p.q
+ * partial sums) run as one launch over all of them (at most 8), on a server
+ * stream that waits for each member's preconditioner; the rest of each
+ * member's step follows on that stream.  Every member computes exactly what
+ * it computes alone.  0: every request steps on its own stream only. */
+typedef enum { SIPG_SERVER_FUSE_APPLY = 0 } sipg_server_option;
+int sipg_server_set_option(sipg_server *s, int option, int value);
+
+/* Fused operator launches so far and the requests they served. */
+int sipg_server_stats(const sipg_server *s, int64_t *fused_launches, int64_t *fused_requests);
+
 /* Waits for the device and frees everything the server holds. */
 int sipg_server_destroy(sipg_server *s);
 

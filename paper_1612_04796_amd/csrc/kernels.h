@@ -30,6 +30,15 @@ struct ApplyLaunch {
 template <typename T>
 hipError_t launch_apply(const ApplyLaunch<T> &a, hipStream_t st);
 
+// Several PLAIN applications of one order (n <= 17) and one elements-per-
+// workgroup choice in one launch (at most kMaxApplySegments): each computes
+// exactly what its own launch_apply would, partial sums included.
+constexpr int kMaxApplySegments = 8;
+// elements per workgroup a launch with ApplyLaunch::epb = epb uses
+int apply_launch_epb(int E, int n, int epb);
+template <typename T>
+hipError_t launch_apply_segments(const ApplyLaunch<T> *a, int n, hipStream_t st);
+
 // Number of partial sums launch_apply / launch_apply_large write with partials
 // (epb as in ApplyLaunch).
 int apply_num_blocks(int E, int n, int epb = 0);

@@ -141,19 +141,60 @@ __device__ __forceinline__ int group_first_element(const Mesh &g, int blk, int e
   return elem_index(g, (tx * tgx + x) * epb, ty * TY + y, ez);
 }
 
+// Several operator applications of one order in one launch (the same-order
+// work of several resident solves): segment k owns workgroups
+// [blk0, blk0 + nblk) and runs them exactly as its own launch would (same
+// elements per workgroup, workgroup numbering and partial sums).
+template <typename T>
+struct ApplySeg {
+  Mesh g;
+  ApplyTabs<T> tb;
+  const T *u;
+  const T *f;
+  T *out;
+  T *partial;
+  const T *J;
+  int blk0, nblk;
+  bool nt, tiled;
+};
+template <typename T>
+struct ApplySegs {
+  ApplySeg<T> s[kMaxApplySegments];
+  int n;
+};
+
 // EPB (elements per workgroup) is chosen at launch, at most ApplyShape<N>::EPB.
-template <typename T, int N, int MODE, bool DOT>
+// SEG: the launch covers the segments in `segs` (every other operand except
+// EPB is taken from the workgroup's segment).
+template <typename T, int N, int MODE, bool DOT, bool SEG>
 __global__ void __launch_bounds__(ApplyShape<N>::NTH)
 apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restrict__ f, T *__restrict__ out,
-             T *__restrict__ partial, const T *__restrict__ J, int EPB, bool nt, bool tiled) {
+             T *__restrict__ partial, const T *__restrict__ J, int EPB, bool nt, bool tiled, ApplySegs<T> segs) {
   using Sh = ApplyShape<N>;
+  int bid = blockIdx.x, nblocks = gridDim.x;
+  if constexpr (SEG) {
+    int k = 0;
+    while (k + 1 < segs.n && bid >= segs.s[k + 1].blk0) ++k;
+    const ApplySeg<T> &a = segs.s[k];
+    g = a.g;
+    tb = a.tb;
+    u = a.u;
+    f = a.f;
+    out = a.out;
+    partial = a.partial;
+    J = a.J;
+    nt = a.nt;
+    tiled = a.tiled;
+    bid -= a.blk0;
+    nblocks = a.nblk;
+  }
   constexpr int N2 = Sh::N2, N3 = Sh::N3;
   constexpr int NC = coarse_n(N);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *su = reinterpret_cast<T *>(smem_raw);
   T *sy = su + EPB * N3;
   __shared__ T red[16];
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int blk = xcd_block(bid, nblocks);
   const int e0 = group_first_element(g, blk, EPB, tiled);
   const int nloc = min(EPB, g.E - e0);
   const int t = threadIdx.x;
@@ -398,6 +439,17 @@ int launch_epb(int E, int n, int epb) {
   return epb > 0 ? std::min(epb, std::max(1, 256 / (n * n))) : apply_epb(E, n);
 }
 
+// outputs beyond the last-level cache: non-temporal stores
+template <typename T, int N>
+bool out_streams(const Mesh &g) {
+  return (int64_t)g.E * N * N * N * (int64_t)sizeof(T) > kStreamOutBytes;
+}
+// xy planes beyond half an L2: column-tile visiting order
+template <typename T, int N>
+bool tiled_order(const Mesh &g) {
+  return (int64_t)g.ne[0] * g.ne[1] * N * N * N * (int64_t)sizeof(T) >= (2 << 20);
+}
+
 template <typename T, int N, int MODE, bool DOT>
 hipError_t launch_mode(const ApplyLaunch<T> &a, hipStream_t st) {
   using Sh = ApplyShape<N>;
@@ -405,12 +457,11 @@ hipError_t launch_mode(const ApplyLaunch<T> &a, hipStream_t st) {
   const int nblk = (a.mesh.E + epb - 1) / epb;
   const int nth = std::min(Sh::NTH, (epb * N * N + 63) / 64 * 64);
   const size_t shm = 2 * (size_t)epb * N * N * N * sizeof(T);
-  hipError_t e = allow_lds(apply_kernel<T, N, MODE, DOT>, shm);
+  hipError_t e = allow_lds(apply_kernel<T, N, MODE, DOT, false>, shm);
   if (e != hipSuccess) return e;
-  const bool nt = (int64_t)a.mesh.E * N * N * N * (int64_t)sizeof(T) > kStreamOutBytes;
-  const bool tiled = (int64_t)a.mesh.ne[0] * a.mesh.ne[1] * N * N * N * (int64_t)sizeof(T) >= (2 << 20);
-  apply_kernel<T, N, MODE, DOT><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, a.partial, a.J, epb, nt,
-                                                        tiled);
+  const bool nt = out_streams<T, N>(a.mesh), tiled = tiled_order<T, N>(a.mesh);
+  apply_kernel<T, N, MODE, DOT, false><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, a.partial, a.J, epb,
+                                                               nt, tiled, ApplySegs<T>{});
   return hipGetLastError();
 }
 
@@ -461,6 +512,53 @@ int apply_max_epb(int n) { return apply_is_large(n) ? 0 : std::max(1, 256 / (n *
 #define SIPG_ORDER_CASES(X) \
   X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17)
 
+template <typename T, int N>
+hipError_t launch_segments_n(const ApplyLaunch<T> *a, int n, hipStream_t st) {
+  using Sh = ApplyShape<N>;
+  const bool dot = a[0].partial != nullptr;
+  const int epb = launch_epb(a[0].mesh.E, N, a[0].epb);
+  ApplySegs<T> S{};
+  S.n = n;
+  int blk = 0;
+  for (int k = 0; k < n; ++k) {
+    if (a[k].n != N || a[k].mode != APPLY_PLAIN || (a[k].partial != nullptr) != dot ||
+        launch_epb(a[k].mesh.E, N, a[k].epb) != epb)
+      return hipErrorInvalidValue;
+    const int nblk = (a[k].mesh.E + epb - 1) / epb;
+    S.s[k] = ApplySeg<T>{a[k].mesh, a[k].tabs, a[k].u, a[k].f, a[k].out, a[k].partial, a[k].J,
+                         blk, nblk, out_streams<T, N>(a[k].mesh), tiled_order<T, N>(a[k].mesh)};
+    blk += nblk;
+  }
+  const int nth = std::min(Sh::NTH, (epb * N * N + 63) / 64 * 64);
+  const size_t shm = 2 * (size_t)epb * N * N * N * sizeof(T);
+  hipError_t e;
+  const ApplyLaunch<T> &a0 = a[0];
+  if (dot) {
+    if ((e = allow_lds(apply_kernel<T, N, MODE_APPLY, true, true>, shm)) != hipSuccess) return e;
+    apply_kernel<T, N, MODE_APPLY, true, true><<<blk, nth, shm, st>>>(a0.mesh, a0.tabs, a0.u, a0.f, a0.out, a0.partial,
+                                                                      a0.J, epb, false, false, S);
+  } else {
+    if ((e = allow_lds(apply_kernel<T, N, MODE_APPLY, false, true>, shm)) != hipSuccess) return e;
+    apply_kernel<T, N, MODE_APPLY, false, true><<<blk, nth, shm, st>>>(a0.mesh, a0.tabs, a0.u, a0.f, a0.out,
+                                                                       a0.partial, a0.J, epb, false, false, S);
+  }
+  return hipGetLastError();
+}
+
+int apply_launch_epb(int E, int n, int epb) { return launch_epb(E, n, epb); }
+
+template <typename T>
+hipError_t launch_apply_segments(const ApplyLaunch<T> *a, int n, hipStream_t st) {
+  if (n < 1 || n > kMaxApplySegments || apply_is_large(a[0].n)) return hipErrorInvalidValue;
+  switch (a[0].n) {
+#define CASE(NN) \
+  case NN: return launch_segments_n<T, NN>(a, n, st);
+    SIPG_ORDER_CASES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T>
 hipError_t launch_apply(const ApplyLaunch<T> &a, hipStream_t st) {
   switch (a.n) {
@@ -485,6 +583,7 @@ hipError_t launch_prolong(const ProlongLaunch<T, TC> &a, hipStream_t st) {
 
 template hipError_t launch_apply<double>(const ApplyLaunch<double> &, hipStream_t);
 template hipError_t launch_apply<float>(const ApplyLaunch<float> &, hipStream_t);
+template hipError_t launch_apply_segments<double>(const ApplyLaunch<double> *, int, hipStream_t);
 template hipError_t launch_prolong<double, double>(const ProlongLaunch<double, double> &, hipStream_t);
 template hipError_t launch_prolong<float, float>(const ProlongLaunch<float, float> &, hipStream_t);
 template hipError_t launch_prolong<float, double>(const ProlongLaunch<float, double> &, hipStream_t);

@@ -13,6 +13,14 @@
 // kernels overlap on the device, and new requests are admitted as slots and
 // memory free up.  Each request's kernel sequence is exactly the one of
 // sipg_pcg_solve, so its result does not depend on what else is running.
+//
+// Same-order batching: the requests that become ready for a flexible-CG
+// iteration in the same pass are grouped by order, operator launch shape and
+// size class (unknowns within a factor of 8).  A group of two or more runs
+// its preconditioners on the members' own streams, then one operator launch
+// q = A p over all members (launch_apply_segments, each member's workgroups
+// computing exactly what its own launch would) on a server stream that waits
+// for every member, followed by each member's remaining step on that stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,6 +31,7 @@
 #include <memory>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "kernels.h"
@@ -61,6 +70,9 @@ struct Request {
 struct sipg_server {
   size_t budget = 0, used = 0;
   int max_active = 1;
+  bool fuse = true;
+  hipStream_t fuse_stream = nullptr;  // fused operator launches and what follows them (created on first use)
+  int64_t fused_launches = 0, fused_requests = 0;
   Clock::time_point t0 = Clock::now();
   int64_t next_id = 1;
   std::deque<Request *> queue;
@@ -177,21 +189,24 @@ bool admit(sipg_server *s, Request *r) {
   return true;
 }
 
+enum Advance { ADV_LEFT = 0, ADV_STEPPED = 1, ADV_ITERATE = 2 };
+
 // The request's last step has completed: decide and enqueue the next one.
-// Returns false when the request left the active set.
-bool advance(sipg_server *s, Request *r) {
+// ADV_LEFT: the request left the active set; ADV_ITERATE: it needs a plain
+// flexible-CG iteration, which the caller enqueues (alone or batched).
+int advance(sipg_server *s, Request *r) {
   const double *hs = sipg::detail::host_scalars(r->ctx);
   try {
     if (r->phase == PH_START) {
       r->r0 = std::sqrt(hs[2]);
       if (!std::isfinite(r->r0)) {
         finish(s, r, SIPG_REQ_FAILED, "initial residual is not finite");
-        return false;
+        return ADV_LEFT;
       }
       if (r->r0 == 0.0) {
         r->relres = 0.0;
         finish(s, r, SIPG_REQ_DONE);
-        return false;
+        return ADV_LEFT;
       }
       sipg::detail::fcg_first_precond(r->ctx);
       sipg::detail::fcg_apply_update(r->ctx);
@@ -201,11 +216,11 @@ bool advance(sipg_server *s, Request *r) {
       const double pq = hs[1], rn = std::sqrt(hs[2]);
       if (!(pq > 0.0) || !std::isfinite(pq)) {
         finish(s, r, SIPG_REQ_FAILED, "flexible CG breakdown");
-        return false;
+        return ADV_LEFT;
       }
       if (!std::isfinite(rn)) {
         finish(s, r, SIPG_REQ_FAILED, "residual norm is not finite");
-        return false;
+        return ADV_LEFT;
       }
       r->relres = rn / r->r0;
       if (rn <= r->rtol * r->r0) {
@@ -213,22 +228,20 @@ bool advance(sipg_server *s, Request *r) {
         r->phase = PH_CONFIRM;
       } else if (r->iters >= r->maxit) {
         finish(s, r, SIPG_REQ_FAILED, "tolerance not reached");
-        return false;
+        return ADV_LEFT;
       } else {
-        sipg::detail::fcg_precond_update(r->ctx, r->x);
-        sipg::detail::fcg_apply_update(r->ctx);
-        r->iters += 1;
+        return ADV_ITERATE;
       }
     } else {  // PH_CONFIRM
       const double rt = std::sqrt(hs[2]);
       if (rt <= r->rtol * r->r0) {
         r->relres = rt / r->r0;
         finish(s, r, SIPG_REQ_DONE);
-        return false;
+        return ADV_LEFT;
       }
       if (r->iters >= r->maxit) {
         finish(s, r, SIPG_REQ_FAILED, "tolerance not reached");
-        return false;
+        return ADV_LEFT;
       }
       sipg::detail::fcg_restart_from_true(r->ctx);
       sipg::detail::fcg_precond_update(r->ctx, r->x);
@@ -238,13 +251,139 @@ bool advance(sipg_server *s, Request *r) {
     }
   } catch (const std::exception &e) {
     finish(s, r, SIPG_REQ_FAILED, e.what());
+    return ADV_LEFT;
+  }
+  if (hipEventRecord(r->ev, r->stream) != hipSuccess) {
+    finish(s, r, SIPG_REQ_FAILED, "event record failed");
+    return ADV_LEFT;
+  }
+  return ADV_STEPPED;
+}
+
+// One plain iteration of a request on its own stream.
+bool iterate_alone(sipg_server *s, Request *r) {
+  try {
+    sipg::detail::fcg_precond_update(r->ctx, r->x);
+    sipg::detail::fcg_apply_update(r->ctx);
+  } catch (const std::exception &e) {
+    finish(s, r, SIPG_REQ_FAILED, e.what());
     return false;
   }
+  r->iters += 1;
   if (hipEventRecord(r->ev, r->stream) != hipSuccess) {
     finish(s, r, SIPG_REQ_FAILED, "event record failed");
     return false;
   }
   return true;
+}
+
+// One iteration of every member of a group with one operator launch; on a
+// failure the members not yet enqueued fall back to iterate_alone.  Returns
+// the members that left the active set.
+std::vector<Request *> iterate_batched(sipg_server *s, const std::vector<Request *> &g,
+                                       const std::vector<sipg::ApplyLaunch<double>> &a) {
+  std::vector<Request *> left;
+  bool ok = true;
+  try {
+    for (Request *r : g) {
+      sipg::detail::fcg_precond_update(r->ctx, r->x);
+      ok = ok && hipEventRecord(r->ev, r->stream) == hipSuccess &&
+           hipStreamWaitEvent(s->fuse_stream, r->ev, 0) == hipSuccess;
+    }
+    ok = ok && sipg::launch_apply_segments<double>(a.data(), (int)a.size(), s->fuse_stream) == hipSuccess;
+    if (ok)
+      for (Request *r : g) sipg::detail::fcg_after_apply(r->ctx, s->fuse_stream);
+  } catch (const std::exception &e) {
+    sipg::detail::set_error(e.what());
+    ok = false;
+  }
+  for (Request *r : g) {
+    if (!ok) {
+      finish(s, r, SIPG_REQ_FAILED, "batched operator launch failed: " + sipg::detail::last_error());
+      left.push_back(r);
+      continue;
+    }
+    r->iters += 1;
+    if (hipEventRecord(r->ev, s->fuse_stream) != hipSuccess) {
+      finish(s, r, SIPG_REQ_FAILED, "event record failed");
+      left.push_back(r);
+    }
+  }
+  if (ok) {
+    s->fused_launches += 1;
+    s->fused_requests += (int64_t)g.size();
+  }
+  return left;
+}
+
+// Enqueues the plain iterations: batched by (order, elements per workgroup,
+// size class) where two or more requests share them, alone otherwise.
+// Returns the requests that left the active set.
+using BatchKey = std::tuple<int, int, int>;
+
+// The batching key of a request (order, elements per operator workgroup,
+// size class); false when its operator cannot be batched or batching is off.
+bool batch_key(sipg_server *s, Request *r, BatchKey *key, sipg::ApplyLaunch<double> *a) {
+  if (!s->fuse) return false;
+  if (!s->fuse_stream && hipStreamCreateWithFlags(&s->fuse_stream, hipStreamNonBlocking) != hipSuccess) {
+    s->fuse_stream = nullptr;
+    return false;
+  }
+  if (!sipg::detail::fcg_apply_launch(r->ctx, a)) return false;
+  int cls = 0;
+  while ((r->ndof >> (3 * (cls + 1))) > 0) ++cls;  // unknowns in [8^cls, 8^(cls+1))
+  *key = std::make_tuple(a->n, a->epb, cls);
+  return true;
+}
+
+// Keeps batchable requests that stepped in the same pass in phase: each one's
+// step-complete event is re-recorded on the server stream after all of their
+// steps, so they become ready together and their next iterations batch.
+void join_cohorts(sipg_server *s, const std::vector<Request *> &stepped) {
+  std::map<BatchKey, std::vector<Request *>> groups;
+  for (Request *r : stepped) {
+    BatchKey key;
+    sipg::ApplyLaunch<double> a{};
+    if (r->state == SIPG_REQ_ACTIVE && batch_key(s, r, &key, &a)) groups[key].push_back(r);
+  }
+  for (auto &kv : groups) {
+    const std::vector<Request *> &g = kv.second;
+    if (g.size() < 2) continue;
+    for (Request *r : g) (void)hipStreamWaitEvent(s->fuse_stream, r->ev, 0);
+    for (Request *r : g) (void)hipEventRecord(r->ev, s->fuse_stream);
+  }
+}
+
+std::vector<Request *> iterate(sipg_server *s, const std::vector<Request *> &ready) {
+  std::vector<Request *> left;
+  std::map<BatchKey, std::vector<std::pair<Request *, sipg::ApplyLaunch<double>>>> groups;
+  for (Request *r : ready) {
+    sipg::ApplyLaunch<double> a{};
+    BatchKey key;
+    if (batch_key(s, r, &key, &a)) {
+      groups[key].push_back({r, a});
+    } else if (!iterate_alone(s, r)) {
+      left.push_back(r);
+    }
+  }
+  for (auto &kv : groups) {
+    auto &v = kv.second;
+    for (size_t i0 = 0; i0 < v.size(); i0 += sipg::kMaxApplySegments) {
+      const size_t i1 = std::min(v.size(), i0 + sipg::kMaxApplySegments);
+      if (i1 - i0 == 1) {
+        if (!iterate_alone(s, v[i0].first)) left.push_back(v[i0].first);
+        continue;
+      }
+      std::vector<Request *> g;
+      std::vector<sipg::ApplyLaunch<double>> a;
+      for (size_t i = i0; i < i1; ++i) {
+        g.push_back(v[i].first);
+        a.push_back(v[i].second);
+      }
+      for (Request *r : iterate_batched(s, g, a)) left.push_back(r);
+    }
+  }
+  return left;
 }
 
 }  // namespace
@@ -290,13 +429,17 @@ int sipg_server_progress(sipg_server *s, int wait_ms, int *nactive, int *nqueued
   const double deadline = s->now() + std::max(0, wait_ms) * 1e-3;
   for (;;) {
     // admission, first come first served, while slots and memory allow
+    std::vector<Request *> stepped;
     while (!s->queue.empty() && (int)s->active.size() < s->max_active) {
       Request *r = s->queue.front();
       if (!admit(s, r)) break;
       s->queue.pop_front();
       if (r->state != SIPG_REQ_ACTIVE) ++done;
+      else stepped.push_back(r);
     }
-    // advance every request whose step has completed
+    // advance every request whose step has completed; plain iterations are
+    // collected and enqueued together (batched where they share an order)
+    std::vector<Request *> ready;
     for (size_t i = 0; i < s->active.size();) {
       Request *r = s->active[i];
       const hipError_t q = hipEventQuery(r->ev);
@@ -304,14 +447,26 @@ int sipg_server_progress(sipg_server *s, int wait_ms, int *nactive, int *nqueued
         ++i;
         continue;
       }
-      bool keep = (q == hipSuccess) ? advance(s, r) : (finish(s, r, SIPG_REQ_FAILED, hipGetErrorString(q)), false);
-      if (!keep) {
+      const int a = (q == hipSuccess) ? advance(s, r) : (finish(s, r, SIPG_REQ_FAILED, hipGetErrorString(q)), ADV_LEFT);
+      if (a == ADV_LEFT) {
         ++done;
         s->active.erase(s->active.begin() + i);
       } else {
+        if (a == ADV_ITERATE) ready.push_back(r);
+        else stepped.push_back(r);
         ++i;
       }
     }
+    if (!ready.empty()) {
+      const std::vector<Request *> left = iterate(s, ready);
+      for (Request *r : left) {
+        ++done;
+        s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+      }
+      for (Request *r : ready)
+        if (std::find(left.begin(), left.end(), r) == left.end()) stepped.push_back(r);
+    }
+    join_cohorts(s, stepped);
     if (done > 0 || s->now() >= deadline || (s->active.empty() && s->queue.empty())) break;
     std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
@@ -358,10 +513,25 @@ int sipg_server_fetch(sipg_server *s, int64_t id, double *u, void *hip_stream) {
   return SIPG_OK;
 }
 
+int sipg_server_set_option(sipg_server *s, int option, int value) {
+  if (!s) return fail(SIPG_EINVAL, "null server");
+  if (option != SIPG_SERVER_FUSE_APPLY) return fail(SIPG_EINVAL, "unknown server option");
+  s->fuse = value != 0;
+  return SIPG_OK;
+}
+
+int sipg_server_stats(const sipg_server *s, int64_t *fused_launches, int64_t *fused_requests) {
+  if (!s) return fail(SIPG_EINVAL, "null server");
+  if (fused_launches) *fused_launches = s->fused_launches;
+  if (fused_requests) *fused_requests = s->fused_requests;
+  return SIPG_OK;
+}
+
 int sipg_server_destroy(sipg_server *s) {
   if (!s) return SIPG_OK;
   (void)hipDeviceSynchronize();
   for (auto &kv : s->all) release_all(s, kv.second.get());
+  if (s->fuse_stream) (void)hipStreamDestroy(s->fuse_stream);
   delete s;
   return SIPG_OK;
 }

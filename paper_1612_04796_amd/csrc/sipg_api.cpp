@@ -819,19 +819,31 @@ void fcg_first_precond(sipg_ctx *c) {
   c->x_pending = false;
 }
 
-void fcg_apply_update(sipg_ctx *c) {
+void fcg_after_apply(sipg_ctx *c, hipStream_t st) {
   const int64_t N = level_ndof(c->H, c->L);
-  op_apply<double>(c, c->L, c->cg_p, c->cg_q, c->partial);
   check(sipg::launch_finalize(c->partial,
                               sipg::apply_num_blocks(c->mesh.E, c->t64[c->L].n, c->t64[c->L].apply_epb), 1.0,
-                              c->scal + sipg::FS_PQ, c->stream),
+                              c->scal + sipg::FS_PQ, st),
         "dot");
   float *r32 = c->H.prm.precond_bits != 64 ? c->w32.fL : nullptr;
-  check(sipg::launch_fcg_r(c->cg_r, c->cg_q, N, c->scal, c->partial, r32, c->stream), "fcg update");
-  check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + sipg::FS_RR, c->stream, c->scal,
+  check(sipg::launch_fcg_r(c->cg_r, c->cg_q, N, c->scal, c->partial, r32, st), "fcg update");
+  check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + sipg::FS_RR, st, c->scal,
                               c->host_scal_dev, sipg::FS_COUNT),
         "dot");
   c->x_pending = true;
+}
+
+bool fcg_apply_launch(sipg_ctx *c, sipg::ApplyLaunch<double> *a) {
+  const LevelTabs<double> &t = c->t64[c->L];
+  if (sipg::apply_is_large(t.n)) return false;
+  *a = sipg::ApplyLaunch<double>{c->mesh, t.n, t.apply, c->cg_p, nullptr, c->cg_q, sipg::APPLY_PLAIN, c->partial,
+                                 nullptr, 0, sipg::apply_launch_epb(c->mesh.E, t.n, t.apply_epb)};
+  return true;
+}
+
+void fcg_apply_update(sipg_ctx *c) {
+  op_apply<double>(c, c->L, c->cg_p, c->cg_q, c->partial);
+  fcg_after_apply(c, c->stream);
 }
 
 void fcg_confirm(sipg_ctx *c, double *x, const double *b) {

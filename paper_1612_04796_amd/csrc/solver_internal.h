@@ -9,6 +9,7 @@
 
 #include <string>
 
+#include "kernels.h"
 #include "sipg_mg.h"
 
 namespace sipg {
@@ -21,6 +22,15 @@ void fcg_first_precond(sipg_ctx *c);
 // q = A p, p.q (FS_PQ), r -= alpha q, ||r||^2 (FS_RR); the update
 // x += alpha p is deferred to the next call that is given x
 void fcg_apply_update(sipg_ctx *c);
+// fcg_apply_update in two parts, for launching the operators of several
+// contexts together: the operator launch q = A p with its p.q partial sums
+// (returned as a launch description; false when the order has no
+// compile-time operator kernel), then the rest of the step enqueued on
+// stream st (p.q, r -= alpha q, ||r||^2).  fcg_apply_launch(c, &a) followed
+// by launch_apply_segments over such descriptions and fcg_after_apply(c, st)
+// computes exactly what fcg_apply_update does.
+bool fcg_apply_launch(sipg_ctx *c, sipg::ApplyLaunch<double> *a);
+void fcg_after_apply(sipg_ctx *c, hipStream_t st);
 // x += alpha p if pending, then ||b - A x||^2 (FS_RR), the true residual kept in q
 void fcg_confirm(sipg_ctx *c, double *x, const double *b);
 // r = true residual, q = A p again

@@ -29,7 +29,7 @@ EXPORTS = (
     "sipg_last_error", "sipg_host_table", "sipg_time_kernel", "sipg_autotune", "sipg_tuning",
     "sipg_set_option", "sipg_traced_kernel_ms",
     "sipg_server_create", "sipg_server_submit", "sipg_server_progress", "sipg_server_status",
-    "sipg_server_fetch", "sipg_server_destroy",
+    "sipg_server_fetch", "sipg_server_destroy", "sipg_server_set_option", "sipg_server_stats",
 )
 REQ_QUEUED, REQ_ACTIVE, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 KERNELS = {"residual": 0, "schwarz_solve": 1, "schwarz_assemble": 2, "restrict": 3, "prolong": 4}
@@ -108,6 +108,8 @@ def lib():
                                            P(ctypes.c_int64)]),
             "sipg_server_fetch": (c_int, [vp, ctypes.c_int64, vp, vp]),
             "sipg_server_destroy": (c_int, [vp]),
+            "sipg_server_set_option": (c_int, [vp, c_int, c_int]),
+            "sipg_server_stats": (c_int, [vp, P(ctypes.c_int64), P(ctypes.c_int64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -391,6 +393,17 @@ class Server:
         if st.value == REQ_FAILED:
             out["error"] = lib().sipg_last_error().decode(errors="replace")
         return out
+
+    def set_option(self, option, value):
+        """SIPG_SERVER_FUSE_APPLY (0): batch the operator launches of
+        same-order requests (1, the default) or not (0)."""
+        _check(lib().sipg_server_set_option(self._h, int(option), int(value)))
+
+    def stats(self):
+        """(fused operator launches, requests they served) so far."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().sipg_server_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def fetch(self, rid, u):
         import torch

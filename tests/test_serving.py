@@ -117,3 +117,63 @@ def test_memory_budget_limits_admission():
         # the budget holds one request at a time: active intervals are disjoint
         spans = sorted((x["t_admit"], x["t_done"]) for x in st)
         assert all(spans[i][1] <= spans[i + 1][0] for i in range(len(spans) - 1)), spans
+
+
+# same order, same launch shape and size class: their flexible-CG iterations
+# are batched into one operator launch when they are ready together
+SAME_ORDER = [
+    dict(ne=(6, 6, 6), length=(1.0, 1.0, 1.0), P=4, overlap="max", omega=0.08),
+    dict(ne=(6, 5, 7), length=(2.0, 1.0, 1.0), P=4, overlap="max", omega=0.08),
+    dict(ne=(7, 6, 6), length=(1.0, 1.0, 1.0), P=4, overlap="rel", omega=0.08),
+    dict(ne=(5, 6, 6), length=(1.0, 3.0, 1.0), P=4, overlap="max", omega=0.08),
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("bits", [32, 64])
+def test_batched_operator_launches_keep_results(bits):
+    """Same-order requests served with batched operator launches give, bitwise,
+    the results of the same solves run alone, and the batching happened."""
+    from _gpu import announce, host, zeros
+    announce("serving batched", bits)
+    alone = []
+    for i, prm in enumerate(SAME_ORDER):
+        k, phi, amp = fourier_modes(200 + i, 3)
+        with sipg.Solver(precond_bits=bits, **prm) as s:
+            b = zeros(s.ndof())
+            s.rhs_fourier(k, phi, amp, b)
+            x = zeros(s.ndof())
+            it, rr = s.pcg_solve(x, b, rtol=1e-10, maxit=100)
+            alone.append((host(x), it))
+    for fuse in (1, 0):
+        with sipg.Server(64 << 30, max_active=4) as srv:
+            srv.set_option(0, fuse)
+            ids = []
+            for i, prm in enumerate(SAME_ORDER):
+                k, phi, amp = fourier_modes(200 + i, 3)
+                ids.append(srv.submit(k, phi, amp, rtol=1e-10, maxit=100, precond_bits=bits, **prm))
+            for _ in range(100000):
+                a, q, _c = srv.progress(wait_ms=50)
+                if a == 0 and q == 0:
+                    break
+            launches, served = srv.stats()
+            if fuse:
+                assert launches >= 1 and served >= 2 * launches, (launches, served)
+            else:
+                assert launches == 0 and served == 0
+            for i, rid in enumerate(ids):
+                st = srv.status(rid)
+                assert st["state"] == sipg.REQ_DONE, st
+                u = zeros(st["ndof"])
+                srv.fetch(rid, u)
+                xs, it = alone[i]
+                assert st["iters"] == it
+                assert np.array_equal(host(u), xs), (fuse, i)
+
+
+def test_server_options_validated():
+    with sipg.Server(1 << 30, 4) as srv:
+        assert srv.stats() == (0, 0)
+        srv.set_option(0, 0)
+        with pytest.raises(sipg.SipgError):
+            srv.set_option(5, 1)
