@@ -171,6 +171,36 @@ enum FcgScalar { FS_RZ = 0, FS_PQ = 1, FS_RR = 2, FS_ZQ = 3, FS_RZNEW = 4, FS_AL
 //   r -= alpha q, partial = r.r, r32 = (float) r when given   (alpha = s[RZ] / s[PQ])
 hipError_t launch_fcg_r(double *r, const double *q, int64_t n, double *s, double *partial, float *r32,
                         hipStream_t st);
+// The finalize of several partial-sum arrays (scale 1, optional publish) and
+// the residual update of several flexible-CG states, each in one launch
+// (at most kMaxApplySegments); every segment computes exactly what its own
+// launch_finalize / launch_fcg_r would.
+struct FinalizeSeg {
+  const double *partial;
+  int np;
+  double *out;
+  const double *pub_src;
+  double *pub_dst;
+  int pub_n;
+};
+struct FinalizeSegs {
+  FinalizeSeg s[kMaxApplySegments];
+  int n;
+};
+hipError_t launch_finalize_segments(const FinalizeSegs &segs, hipStream_t st);
+struct FcgRSeg {
+  double *r;
+  const double *q;
+  int64_t n;
+  double *s;
+  double *partial;
+  float *r32;
+};
+struct FcgRSegs {
+  FcgRSeg s[kMaxApplySegments];
+  int n;
+};
+hipError_t launch_fcg_r_segments(const FcgRSegs &segs, hipStream_t st);
 //   partial = z.q and r.z (z in the preconditioner's precision)
 template <typename TZ>
 hipError_t launch_fcg_dot2(const TZ *z, const double *q, const double *r, int64_t n, double *partial,

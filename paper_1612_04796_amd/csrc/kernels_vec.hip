@@ -19,6 +19,13 @@ __device__ __forceinline__ void chunk_of(int64_t n, int64_t &lo, int64_t &hi) {
   hi = lo + chunk < n ? lo + chunk : n;
 }
 
+// the same partition for block b of nb
+__device__ __forceinline__ void chunk_of(int64_t n, int b, int nb, int64_t &lo, int64_t &hi) {
+  const int64_t chunk = (n + nb - 1) / nb;
+  lo = chunk * b;
+  hi = lo + chunk < n ? lo + chunk : n;
+}
+
 // Streaming loops issue the loads of kUnroll iterations before using any,
 // and accumulate in a fixed order (deterministic).
 constexpr int kUnroll = 4;
@@ -57,10 +64,22 @@ sum_partials_kernel(const T *__restrict__ x, int64_t n, double *__restrict__ par
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// SEG: block k finalizes segment k of `segs` (the other operands unused)
+template <bool SEG>
 __global__ void __launch_bounds__(1024)
 finalize_kernel(const double *__restrict__ partial, int np, double scale, double *out, const double *pub_src,
-                double *pub_dst, int pub_n) {
+                double *pub_dst, int pub_n, FinalizeSegs segs) {
   __shared__ double red[16];
+  if constexpr (SEG) {
+    const FinalizeSeg &a = segs.s[blockIdx.x];
+    partial = a.partial;
+    np = a.np;
+    scale = 1.0;
+    out = a.out;
+    pub_src = a.pub_src;
+    pub_dst = a.pub_dst;
+    pub_n = a.pub_dst ? a.pub_n : 0;
+  }
   double s = 0.0;
   for (int i = threadIdx.x; i < np; i += blockDim.x) s += partial[i];
   s = block_reduce_sum(s, red);
@@ -110,13 +129,27 @@ __global__ void __launch_bounds__(1024) fcg_finalize2_kernel(const double *__res
 
 // alpha = s[RZ] / s[PQ]; r -= alpha q; partial = r.r; r32 = (float) r when
 // given (the input of a single-precision preconditioner)
+// SEG: blocks [k kDotBlocks, (k + 1) kDotBlocks) run segment k of `segs`
+template <bool SEG>
 __global__ void __launch_bounds__(256)
 fcg_r_kernel(double *__restrict__ r, const double *__restrict__ q, int64_t n, double *s,
-             double *__restrict__ partial, float *__restrict__ r32) {
+             double *__restrict__ partial, float *__restrict__ r32, FcgRSegs segs) {
   __shared__ double red[16];
+  int bid = blockIdx.x;
+  if constexpr (SEG) {
+    const FcgRSeg &a = segs.s[bid / kDotBlocks];
+    bid -= (bid / kDotBlocks) * kDotBlocks;
+    r = a.r;
+    q = a.q;
+    n = a.n;
+    s = a.s;
+    partial = a.partial;
+    r32 = a.r32;
+  }
   const double alpha = s[FS_RZ] / s[FS_PQ];
   int64_t lo, hi;
-  chunk_of(n, lo, hi);
+  if constexpr (SEG) chunk_of(n, bid, kDotBlocks, lo, hi);
+  else chunk_of(n, lo, hi);
   double acc = 0.0;
   for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kUnroll * blockDim.x) {
     double rv[kUnroll], qv[kUnroll];
@@ -139,8 +172,8 @@ fcg_r_kernel(double *__restrict__ r, const double *__restrict__ q, int64_t n, do
   }
   acc = block_reduce_sum(acc, red);
   if (threadIdx.x == 0) {
-    partial[blockIdx.x] = acc;
-    if (blockIdx.x == 0) s[FS_ALPHA] = alpha;
+    partial[bid] = acc;
+    if (bid == 0) s[FS_ALPHA] = alpha;
   }
 }
 
@@ -235,7 +268,20 @@ hipError_t launch_sum_partials(const T *x, int64_t n, double *partial, hipStream
 
 hipError_t launch_finalize(const double *partial, int np, double scale, double *out, hipStream_t st,
                            const double *pub_src, double *pub_dst, int pub_n) {
-  finalize_kernel<<<1, 1024, 0, st>>>(partial, np, scale, out, pub_src, pub_dst, pub_dst ? pub_n : 0);
+  finalize_kernel<false><<<1, 1024, 0, st>>>(partial, np, scale, out, pub_src, pub_dst, pub_dst ? pub_n : 0,
+                                             FinalizeSegs{});
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_segments(const FinalizeSegs &segs, hipStream_t st) {
+  if (segs.n < 1 || segs.n > kMaxApplySegments) return hipErrorInvalidValue;
+  finalize_kernel<true><<<segs.n, 1024, 0, st>>>(nullptr, 0, 1.0, nullptr, nullptr, nullptr, 0, segs);
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_r_segments(const FcgRSegs &segs, hipStream_t st) {
+  if (segs.n < 1 || segs.n > kMaxApplySegments) return hipErrorInvalidValue;
+  fcg_r_kernel<true><<<segs.n * kDotBlocks, 256, 0, st>>>(nullptr, nullptr, 0, nullptr, nullptr, nullptr, segs);
   return hipGetLastError();
 }
 
@@ -262,7 +308,7 @@ hipError_t launch_fill(T *x, int64_t n, T v, hipStream_t st) {
 
 hipError_t launch_fcg_r(double *r, const double *q, int64_t n, double *s, double *partial, float *r32,
                         hipStream_t st) {
-  fcg_r_kernel<<<kDotBlocks, 256, 0, st>>>(r, q, n, s, partial, r32);
+  fcg_r_kernel<false><<<kDotBlocks, 256, 0, st>>>(r, q, n, s, partial, r32, FcgRSegs{});
   return hipGetLastError();
 }
 

@@ -20,7 +20,8 @@
 // its preconditioners on the members' own streams, then one operator launch
 // q = A p over all members (launch_apply_segments, each member's workgroups
 // computing exactly what its own launch would) on a server stream that waits
-// for every member, followed by each member's remaining step on that stream.
+// for every member, followed by the members' remaining steps (one launch per
+// kernel for all of them) on that stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -291,8 +292,11 @@ std::vector<Request *> iterate_batched(sipg_server *s, const std::vector<Request
            hipStreamWaitEvent(s->fuse_stream, r->ev, 0) == hipSuccess;
     }
     ok = ok && sipg::launch_apply_segments<double>(a.data(), (int)a.size(), s->fuse_stream) == hipSuccess;
-    if (ok)
-      for (Request *r : g) sipg::detail::fcg_after_apply(r->ctx, s->fuse_stream);
+    if (ok) {
+      std::vector<sipg_ctx *> cs;
+      for (Request *r : g) cs.push_back(r->ctx);
+      sipg::detail::fcg_after_apply_batched(cs.data(), (int)cs.size(), s->fuse_stream);
+    }
   } catch (const std::exception &e) {
     sipg::detail::set_error(e.what());
     ok = false;

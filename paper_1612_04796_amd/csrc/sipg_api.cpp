@@ -833,6 +833,26 @@ void fcg_after_apply(sipg_ctx *c, hipStream_t st) {
   c->x_pending = true;
 }
 
+void fcg_after_apply_batched(sipg_ctx *const *cs, int k, hipStream_t st) {
+  sipg::FinalizeSegs pq{}, rr{};
+  sipg::FcgRSegs up{};
+  pq.n = rr.n = up.n = k;
+  for (int i = 0; i < k; ++i) {
+    sipg_ctx *c = cs[i];
+    pq.s[i] = sipg::FinalizeSeg{c->partial,
+                                sipg::apply_num_blocks(c->mesh.E, c->t64[c->L].n, c->t64[c->L].apply_epb),
+                                c->scal + sipg::FS_PQ, nullptr, nullptr, 0};
+    up.s[i] = sipg::FcgRSeg{c->cg_r, c->cg_q, level_ndof(c->H, c->L), c->scal, c->partial,
+                            c->H.prm.precond_bits != 64 ? c->w32.fL : nullptr};
+    rr.s[i] = sipg::FinalizeSeg{c->partial, sipg::kDotBlocks, c->scal + sipg::FS_RR, c->scal, c->host_scal_dev,
+                                sipg::FS_COUNT};
+  }
+  check(sipg::launch_finalize_segments(pq, st), "dot");
+  check(sipg::launch_fcg_r_segments(up, st), "fcg update");
+  check(sipg::launch_finalize_segments(rr, st), "dot");
+  for (int i = 0; i < k; ++i) cs[i]->x_pending = true;
+}
+
 bool fcg_apply_launch(sipg_ctx *c, sipg::ApplyLaunch<double> *a) {
   const LevelTabs<double> &t = c->t64[c->L];
   if (sipg::apply_is_large(t.n)) return false;

@@ -31,6 +31,9 @@ void fcg_apply_update(sipg_ctx *c);
 // computes exactly what fcg_apply_update does.
 bool fcg_apply_launch(sipg_ctx *c, sipg::ApplyLaunch<double> *a);
 void fcg_after_apply(sipg_ctx *c, hipStream_t st);
+// fcg_after_apply of k contexts (k <= kMaxApplySegments) with one launch per
+// kernel instead of one per context
+void fcg_after_apply_batched(sipg_ctx *const *cs, int k, hipStream_t st);
 // x += alpha p if pending, then ||b - A x||^2 (FS_RR), the true residual kept in q
 void fcg_confirm(sipg_ctx *c, double *x, const double *b);
 // r = true residual, q = A p again
