@@ -39,6 +39,36 @@ __device__ __forceinline__ int elem_index(const Mesh &g, int ex, int ey, int ez)
   return (ez * g.ne[1] + ey) * g.ne[0] + ex;
 }
 
+// First element of the group of EPB consecutive elements that workgroup
+// `blk` owns.  When the groups tile the x rows (ne_x divisible by EPB) they
+// are visited in column tiles of about 8 x 8 elements in x and y, each tile
+// marching along z: a tile's z neighbours were read a tile layer (a few
+// hundred KB) earlier and are still in the XCD's L2, where in plain linear
+// order they were a whole xy plane (megabytes) earlier and came back from
+// memory.  Used when an xy plane of the vector exceeds half an L2 (2 MB);
+// otherwise, or when the groups do not tile the rows, linear order.  Both
+// orders are bijections onto the groups.  Used by the operator kernel and
+// the FP16 local solves; the same order for the FP64/FP32 local solves and
+// the assembly was slower (their neighbour reads are already served by
+// linear order).
+__device__ __forceinline__ int group_first_element(const Mesh &g, int blk, int epb, bool tiled) {
+  if (!tiled || g.ne[0] % epb != 0) return blk * epb;
+  constexpr int TY = 8;
+  const int ngx = g.ne[0] / epb, tgx = epb >= 8 ? 1 : 8 / epb;
+  const int n1 = g.ne[1], n2 = g.ne[2];
+  const int row = ngx * TY * n2;  // groups in a full row of tiles
+  const int ty = blk / row;
+  int q = blk - ty * row;
+  const int h = min(TY, n1 - ty * TY);
+  const int tx = q / (tgx * h * n2);
+  q -= tx * tgx * h * n2;
+  const int w = min(tgx, ngx - tx * tgx);
+  const int ez = q / (w * h);
+  q -= ez * w * h;
+  const int y = q / w, x = q - y * w;
+  return elem_index(g, (tx * tgx + x) * epb, ty * TY + y, ez);
+}
+
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // 1D operator data of one level (eq. (A)): per direction the element diagonal

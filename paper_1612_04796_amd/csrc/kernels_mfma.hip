@@ -212,7 +212,7 @@ __device__ __forceinline__ void gather_rows(const Mesh &g, const float *__restri
 // capped so that as many wavefronts per SIMD are resident as the LDS allows.
 template <int N, int M, int WPB>
 __global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(MShape<N, M>::eu_waves(WPB))))
-schwarz_fdm_mfma(Mesh g, MfmaTabs tb, const float *__restrict__ r, float *__restrict__ C) {
+schwarz_fdm_mfma(Mesh g, MfmaTabs tb, const float *__restrict__ r, float *__restrict__ C, bool tiled) {
   using Sh = MShape<N, M>;
   constexpr int PY = Sh::PY, PZ = Sh::PZ, TILES = Sh::TILES;
   __shared__ __align__(16) _Float16 tile[WPB][Sh::BUF];
@@ -221,7 +221,7 @@ schwarz_fdm_mfma(Mesh g, MfmaTabs tb, const float *__restrict__ r, float *__rest
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int l = threadIdx.x & 63, q = l >> 4, c = l & 15;
   _Float16 *buf = tile[w];
-  const int s = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+  const int s = group_first_element(g, xcd_block(blockIdx.x, gridDim.x), WPB, tiled) + w;
   if (s >= g.E) return;  // wavefronts never wait for each other
 
   auto lane_tab = [&](const _Float16 *p) { return reinterpret_cast<const h4 *>(p)[l]; };
@@ -335,7 +335,10 @@ constexpr int kWpb = 4;
 template <int N, int M>
 hipError_t launch_mfma(const Mesh &mesh, const MfmaTabs &tb, const float *r, float *C, hipStream_t st) {
   if ((int64_t)mesh.E * N * N * N >= ((int64_t)1 << 30)) return hipErrorInvalidValue;
-  schwarz_fdm_mfma<N, M, kWpb><<<(mesh.E + kWpb - 1) / kWpb, 64 * kWpb, 0, st>>>(mesh, tb, r, C);
+  // column-tile visiting order when an xy plane of r exceeds half an L2 (the
+  // gather of R_s r then finds the z neighbours' layers still in L2)
+  const bool tiled = (int64_t)mesh.ne[0] * mesh.ne[1] * N * N * N * (int64_t)sizeof(float) >= (2 << 20);
+  schwarz_fdm_mfma<N, M, kWpb><<<(mesh.E + kWpb - 1) / kWpb, 64 * kWpb, 0, st>>>(mesh, tb, r, C, tiled);
   return hipGetLastError();
 }
 
