@@ -277,9 +277,10 @@ int sipg_server_fetch(sipg_server *s, int64_t id, double *u, void *hip_stream);
  * requests of the same order, the same operator launch shape and a similar
  * size (unknowns within a factor of 8) are ready for a flexible-CG iteration
  * at the same time, their outer operator applications q = A p (with the p.q
- * partial sums) run as one launch over all of them (at most 8), on a server
- * stream that waits for each member's preconditioner; the rest of each
- * member's step follows on that stream.  Every member computes exactly what
+ * partial sums) run as one launch over all of them (at most 8), on a stream
+ * of the server (one per such class of requests) that waits for each
+ * member's preconditioner; the rest of the members' steps follows on that
+ * stream, and members stay in phase from step to step.  Every member computes exactly what
  * it computes alone.  0: every request steps on its own stream only. */
 typedef enum { SIPG_SERVER_FUSE_APPLY = 0 } sipg_server_option;
 int sipg_server_set_option(sipg_server *s, int option, int value);

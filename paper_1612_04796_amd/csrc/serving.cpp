@@ -19,9 +19,9 @@
 // size class (unknowns within a factor of 8).  A group of two or more runs
 // its preconditioners on the members' own streams, then one operator launch
 // q = A p over all members (launch_apply_segments, each member's workgroups
-// computing exactly what its own launch would) on a server stream that waits
-// for every member, followed by the members' remaining steps (one launch per
-// kernel for all of them) on that stream.
+// computing exactly what its own launch would) on a stream of the key that
+// waits for every member, followed by the members' remaining steps (one
+// launch per kernel for all of them) on that stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,6 +44,10 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 enum Phase { PH_START = 0, PH_ITER = 1, PH_CONFIRM = 2 };
+
+// batching key: order (nodes per direction), elements per operator
+// workgroup, size class (unknowns in [8^k, 8^(k+1)))
+using BatchKey = std::tuple<int, int, int>;
 
 struct Request {
   int64_t id = 0;
@@ -72,7 +76,10 @@ struct sipg_server {
   size_t budget = 0, used = 0;
   int max_active = 1;
   bool fuse = true;
-  hipStream_t fuse_stream = nullptr;  // fused operator launches and what follows them (created on first use)
+  // per batching key: the stream of its batched launches and joins (created
+  // on first use; one per key, so cohorts of different keys never wait for
+  // each other)
+  std::map<BatchKey, hipStream_t> fuse_streams;
   int64_t fused_launches = 0, fused_requests = 0;
   Clock::time_point t0 = Clock::now();
   int64_t next_id = 1;
@@ -281,7 +288,7 @@ bool iterate_alone(sipg_server *s, Request *r) {
 // One iteration of every member of a group with one operator launch; on a
 // failure the members not yet enqueued fall back to iterate_alone.  Returns
 // the members that left the active set.
-std::vector<Request *> iterate_batched(sipg_server *s, const std::vector<Request *> &g,
+std::vector<Request *> iterate_batched(sipg_server *s, hipStream_t fs, const std::vector<Request *> &g,
                                        const std::vector<sipg::ApplyLaunch<double>> &a) {
   std::vector<Request *> left;
   bool ok = true;
@@ -289,13 +296,13 @@ std::vector<Request *> iterate_batched(sipg_server *s, const std::vector<Request
     for (Request *r : g) {
       sipg::detail::fcg_precond_update(r->ctx, r->x);
       ok = ok && hipEventRecord(r->ev, r->stream) == hipSuccess &&
-           hipStreamWaitEvent(s->fuse_stream, r->ev, 0) == hipSuccess;
+           hipStreamWaitEvent(fs, r->ev, 0) == hipSuccess;
     }
-    ok = ok && sipg::launch_apply_segments<double>(a.data(), (int)a.size(), s->fuse_stream) == hipSuccess;
+    ok = ok && sipg::launch_apply_segments<double>(a.data(), (int)a.size(), fs) == hipSuccess;
     if (ok) {
       std::vector<sipg_ctx *> cs;
       for (Request *r : g) cs.push_back(r->ctx);
-      sipg::detail::fcg_after_apply_batched(cs.data(), (int)cs.size(), s->fuse_stream);
+      sipg::detail::fcg_after_apply_batched(cs.data(), (int)cs.size(), fs);
     }
   } catch (const std::exception &e) {
     sipg::detail::set_error(e.what());
@@ -308,7 +315,7 @@ std::vector<Request *> iterate_batched(sipg_server *s, const std::vector<Request
       continue;
     }
     r->iters += 1;
-    if (hipEventRecord(r->ev, s->fuse_stream) != hipSuccess) {
+    if (hipEventRecord(r->ev, fs) != hipSuccess) {
       finish(s, r, SIPG_REQ_FAILED, "event record failed");
       left.push_back(r);
     }
@@ -320,28 +327,28 @@ std::vector<Request *> iterate_batched(sipg_server *s, const std::vector<Request
   return left;
 }
 
-// Enqueues the plain iterations: batched by (order, elements per workgroup,
-// size class) where two or more requests share them, alone otherwise.
-// Returns the requests that left the active set.
-using BatchKey = std::tuple<int, int, int>;
-
-// The batching key of a request (order, elements per operator workgroup,
-// size class); false when its operator cannot be batched or batching is off.
+// The batching key of a request and its operator launch; false when its
+// operator cannot be batched or batching is off.
 bool batch_key(sipg_server *s, Request *r, BatchKey *key, sipg::ApplyLaunch<double> *a) {
-  if (!s->fuse) return false;
-  if (!s->fuse_stream && hipStreamCreateWithFlags(&s->fuse_stream, hipStreamNonBlocking) != hipSuccess) {
-    s->fuse_stream = nullptr;
-    return false;
-  }
-  if (!sipg::detail::fcg_apply_launch(r->ctx, a)) return false;
+  if (!s->fuse || !sipg::detail::fcg_apply_launch(r->ctx, a)) return false;
   int cls = 0;
-  while ((r->ndof >> (3 * (cls + 1))) > 0) ++cls;  // unknowns in [8^cls, 8^(cls+1))
+  while ((r->ndof >> (3 * (cls + 1))) > 0) ++cls;
   *key = std::make_tuple(a->n, a->epb, cls);
   return true;
 }
 
+// the stream of a batching key (nullptr if it cannot be created)
+hipStream_t key_stream(sipg_server *s, const BatchKey &key) {
+  auto it = s->fuse_streams.find(key);
+  if (it != s->fuse_streams.end()) return it->second;
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  s->fuse_streams[key] = st;
+  return st;
+}
+
 // Keeps batchable requests that stepped in the same pass in phase: each one's
-// step-complete event is re-recorded on the server stream after all of their
+// step-complete event is re-recorded on its key's stream after all of their
 // steps, so they become ready together and their next iterations batch.
 void join_cohorts(sipg_server *s, const std::vector<Request *> &stepped) {
   std::map<BatchKey, std::vector<Request *>> groups;
@@ -353,11 +360,15 @@ void join_cohorts(sipg_server *s, const std::vector<Request *> &stepped) {
   for (auto &kv : groups) {
     const std::vector<Request *> &g = kv.second;
     if (g.size() < 2) continue;
-    for (Request *r : g) (void)hipStreamWaitEvent(s->fuse_stream, r->ev, 0);
-    for (Request *r : g) (void)hipEventRecord(r->ev, s->fuse_stream);
+    hipStream_t fs = key_stream(s, kv.first);
+    if (!fs) continue;
+    for (Request *r : g) (void)hipStreamWaitEvent(fs, r->ev, 0);
+    for (Request *r : g) (void)hipEventRecord(r->ev, fs);
   }
 }
 
+// Enqueues the plain iterations: batched where two or more requests share a
+// key, alone otherwise.  Returns the requests that left the active set.
 std::vector<Request *> iterate(sipg_server *s, const std::vector<Request *> &ready) {
   std::vector<Request *> left;
   std::map<BatchKey, std::vector<std::pair<Request *, sipg::ApplyLaunch<double>>>> groups;
@@ -374,8 +385,10 @@ std::vector<Request *> iterate(sipg_server *s, const std::vector<Request *> &rea
     auto &v = kv.second;
     for (size_t i0 = 0; i0 < v.size(); i0 += sipg::kMaxApplySegments) {
       const size_t i1 = std::min(v.size(), i0 + sipg::kMaxApplySegments);
-      if (i1 - i0 == 1) {
-        if (!iterate_alone(s, v[i0].first)) left.push_back(v[i0].first);
+      hipStream_t fs = i1 - i0 > 1 ? key_stream(s, kv.first) : nullptr;
+      if (!fs) {
+        for (size_t i = i0; i < i1; ++i)
+          if (!iterate_alone(s, v[i].first)) left.push_back(v[i].first);
         continue;
       }
       std::vector<Request *> g;
@@ -384,7 +397,7 @@ std::vector<Request *> iterate(sipg_server *s, const std::vector<Request *> &rea
         g.push_back(v[i].first);
         a.push_back(v[i].second);
       }
-      for (Request *r : iterate_batched(s, g, a)) left.push_back(r);
+      for (Request *r : iterate_batched(s, fs, g, a)) left.push_back(r);
     }
   }
   return left;
@@ -535,7 +548,7 @@ int sipg_server_destroy(sipg_server *s) {
   if (!s) return SIPG_OK;
   (void)hipDeviceSynchronize();
   for (auto &kv : s->all) release_all(s, kv.second.get());
-  if (s->fuse_stream) (void)hipStreamDestroy(s->fuse_stream);
+  for (auto &kv : s->fuse_streams) (void)hipStreamDestroy(kv.second);
   delete s;
   return SIPG_OK;
 }
