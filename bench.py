@@ -118,7 +118,7 @@ def level_geometry(s, l):
     return n, m, info["ndof"]
 
 
-def cpu_baseline(wl, cycles, k, phi, amp):
+def cpu_baseline(wl, cycles, k, phi, amp, nsample=5):
     """The FP64 oracle on the host: time a sample of V-cycles plus their
     residual norms of the same solve, scale to the solve's cycle count."""
     import numpy as np
@@ -136,7 +136,6 @@ def cpu_baseline(wl, cycles, k, phi, amp):
     X = np.zeros_like(B)
     lev = h.top
     t0 = time.perf_counter()
-    nsample = 5
     for _ in range(nsample):
         float(np.linalg.norm(B - lev.A(X)))
         X = _vcycle_global(X, B, h)
@@ -466,6 +465,15 @@ def main():
         log("cpu baseline: oracle sample ...")
         out["cpu_baseline"] = cpu_baseline(wl, cyc, k, phi, amp)
         log(f"cpu baseline {out['cpu_baseline']['value']:.4g} unknowns/s")
+        try:  # the same sample with one BLAS thread (the paper times one core)
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                one = cpu_baseline(wl, cyc, k, phi, amp, nsample=2)
+            detail["cpu_baseline_one_thread"] = {"value": one["value"], "unit": one["unit"], "cores": 1,
+                                                 "sample": one["sample"]}
+            log(f"cpu baseline, one thread: {one['value']:.4g} unknowns/s")
+        except ImportError:
+            pass
     s.close()
     print(json.dumps(out), flush=True)
 
