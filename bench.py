@@ -383,7 +383,10 @@ def main():
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VALU_PEAK_TFLOPS,
                 "traffic": pmc_traffic() if (n, m) == (9, (13, 13, 13)) else None,
-                "kernel": f"schwarz_fdm_fixed<double, {n}, {m[0]}, {m[1]}, {m[2]}>",
+                # a tuned subdomains-per-workgroup count exists only for the
+                # compile-time-shape kernel
+                "kernel": (f"schwarz_fdm_fixed<double, {n}, {m[0]}, {m[1]}, {m[2]}>" if tuning[f"level{L}"][1] > 0
+                           else f"local solves (n = {n}, m = {m[0]} x {m[1]} x {m[2]})"),
                 "work_per_launch": work, "ms_per_launch": traced_ms, "launches_timed": traced_n,
                 "timing": "HIP events around each launch of the kernel inside the last timed solve",
                 "ms_per_launch_isolated": kern[dominant]}
