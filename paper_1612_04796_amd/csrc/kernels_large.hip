@@ -238,78 +238,90 @@ __device__ __forceinline__ T gather_node(const Mesh &g, int n, const T *__restri
 // phase 1: block (s, c): gather the z-slab, x and y forward
 template <typename T, bool TL>
 __global__ void __launch_bounds__(256)
-wide_slab1(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restrict__ W) {
+wide_slab1(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restrict__ W, int ppb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *P = reinterpret_cast<T *>(smem_raw);
   const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
   const T *Ax = stage_table<T, TL>(P + pad4(mx * my), tb.S[0], mx);
   const T *Ay = stage_table<T, TL>(P + pad4(mx * my) + mx * pad4(mx), tb.S[1], my);
+  const int nchunk = (mz + ppb - 1) / ppb;
   const int blk = blockIdx.x;
-  const int s = blk / mz, c = blk - s * mz;
+  const int s = blk / nchunk, c0 = (blk - s * nchunk) * ppb, c1 = min(mz, c0 + ppb);
   const int ex = s % g.ne[0], rest = s / g.ne[0];
   const int ey = rest % g.ne[1], ez = rest / g.ne[1];
-  batched_copy<T>(
-      mx * my, threadIdx.x, blockDim.x,
-      [&](int idx) {
-        const int a = idx % mx, b = idx / mx;
-        return gather_node(g, n, r, ex, ey, ez, a - tb.no[0], b - tb.no[1], c - tb.no[2]);
-      },
-      [&](int idx, T v) { P[idx] = v; });
-  __syncthreads();
-  contract<T, TL, true>(P, mx, my, mx, Ax);
-  contract<T, TL, false>(P, mx, mx, my, Ay);
-  T *Ws = W + ((size_t)s * mz + c) * mx * my;
-  batched_copy<T>(
-      mx * my, threadIdx.x, blockDim.x, [&](int idx) { return P[idx]; }, [&](int idx, T v) { Ws[idx] = v; });
+  for (int c = c0; c < c1; ++c) {
+    if (c > c0) __syncthreads();  // the previous plane has been stored
+    batched_copy<T>(
+        mx * my, threadIdx.x, blockDim.x,
+        [&](int idx) {
+          const int a = idx % mx, b = idx / mx;
+          return gather_node(g, n, r, ex, ey, ez, a - tb.no[0], b - tb.no[1], c - tb.no[2]);
+        },
+        [&](int idx, T v) { P[idx] = v; });
+    __syncthreads();
+    contract<T, TL, true>(P, mx, my, mx, Ax);
+    contract<T, TL, false>(P, mx, mx, my, Ay);
+    T *Ws = W + ((size_t)s * mz + c) * mx * my;
+    batched_copy<T>(
+        mx * my, threadIdx.x, blockDim.x, [&](int idx) { return P[idx]; }, [&](int idx, T v) { Ws[idx] = v; });
+  }
 }
 
 // phase 2: block (s, b): the xz plane, z forward, scaling, z backward
 template <typename T, bool TL>
 __global__ void __launch_bounds__(256)
-wide_slab2(int E, SchwarzTabs<T> tb, const T *__restrict__ ilam, T *__restrict__ W) {
+wide_slab2(int E, SchwarzTabs<T> tb, const T *__restrict__ ilam, T *__restrict__ W, int ppb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *P = reinterpret_cast<T *>(smem_raw);
   const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
   const T *Af = stage_table<T, TL>(P + pad4(mx * mz), tb.S[2], mz);
   const T *Ab = stage_table<T, TL>(P + pad4(mx * mz) + mz * pad4(mz), tb.WST[2], mz);
+  const int nchunk = (my + ppb - 1) / ppb;
   const int blk = blockIdx.x;
-  const int s = blk / my, b = blk - s * my;
+  const int s = blk / nchunk, b0 = (blk - s * nchunk) * ppb, b1 = min(my, b0 + ppb);
   T *Ws = W + (size_t)s * mx * my * mz;
-  batched_copy<T>(
-      mx * mz, threadIdx.x, blockDim.x,
-      [&](int idx) { return Ws[((size_t)(idx / mx) * my + b) * mx + idx % mx]; },
-      [&](int idx, T v) { P[idx] = v; });
-  __syncthreads();
-  contract<T, TL, false>(P, mx, mx, mz, Af);
-  batched_copy<T>(
-      mx * mz, threadIdx.x, blockDim.x,
-      [&](int idx) { return ilam[((size_t)(idx / mx) * my + b) * mx + idx % mx]; },
-      [&](int idx, T v) { P[idx] *= v; });
-  __syncthreads();
-  contract<T, TL, false>(P, mx, mx, mz, Ab);
-  batched_copy<T>(
-      mx * mz, threadIdx.x, blockDim.x, [&](int idx) { return P[idx]; },
-      [&](int idx, T v) { Ws[((size_t)(idx / mx) * my + b) * mx + idx % mx] = v; });
+  for (int b = b0; b < b1; ++b) {
+    if (b > b0) __syncthreads();  // the previous plane has been stored
+    batched_copy<T>(
+        mx * mz, threadIdx.x, blockDim.x,
+        [&](int idx) { return Ws[((size_t)(idx / mx) * my + b) * mx + idx % mx]; },
+        [&](int idx, T v) { P[idx] = v; });
+    __syncthreads();
+    contract<T, TL, false>(P, mx, mx, mz, Af);
+    batched_copy<T>(
+        mx * mz, threadIdx.x, blockDim.x,
+        [&](int idx) { return ilam[((size_t)(idx / mx) * my + b) * mx + idx % mx]; },
+        [&](int idx, T v) { P[idx] *= v; });
+    __syncthreads();
+    contract<T, TL, false>(P, mx, mx, mz, Ab);
+    batched_copy<T>(
+        mx * mz, threadIdx.x, blockDim.x, [&](int idx) { return P[idx]; },
+        [&](int idx, T v) { Ws[((size_t)(idx / mx) * my + b) * mx + idx % mx] = v; });
+  }
 }
 
 // phase 3: block (s, c): y and x backward
 template <typename T, bool TL>
-__global__ void __launch_bounds__(256) wide_slab3(int E, SchwarzTabs<T> tb, T *__restrict__ W) {
+__global__ void __launch_bounds__(256) wide_slab3(int E, SchwarzTabs<T> tb, T *__restrict__ W, int ppb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *P = reinterpret_cast<T *>(smem_raw);
   const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
   const T *Ay = stage_table<T, TL>(P + pad4(mx * my), tb.WST[1], my);
   const T *Ax = stage_table<T, TL>(P + pad4(mx * my) + my * pad4(my), tb.WST[0], mx);
+  const int nchunk = (mz + ppb - 1) / ppb;
   const int blk = blockIdx.x;
-  const int s = blk / mz, c = blk - s * mz;
-  T *Ws = W + ((size_t)s * mz + c) * mx * my;
-  batched_copy<T>(
-      mx * my, threadIdx.x, blockDim.x, [&](int idx) { return Ws[idx]; }, [&](int idx, T v) { P[idx] = v; });
-  __syncthreads();
-  contract<T, TL, false>(P, mx, mx, my, Ay);
-  contract<T, TL, true>(P, mx, my, mx, Ax);
-  batched_copy<T>(
-      mx * my, threadIdx.x, blockDim.x, [&](int idx) { return P[idx]; }, [&](int idx, T v) { Ws[idx] = v; });
+  const int s = blk / nchunk, c0 = (blk - s * nchunk) * ppb, c1 = min(mz, c0 + ppb);
+  for (int c = c0; c < c1; ++c) {
+    if (c > c0) __syncthreads();  // the previous plane has been stored
+    T *Ws = W + ((size_t)s * mz + c) * mx * my;
+    batched_copy<T>(
+        mx * my, threadIdx.x, blockDim.x, [&](int idx) { return Ws[idx]; }, [&](int idx, T v) { P[idx] = v; });
+    __syncthreads();
+    contract<T, TL, false>(P, mx, mx, my, Ay);
+    contract<T, TL, true>(P, mx, my, mx, Ax);
+    batched_copy<T>(
+        mx * my, threadIdx.x, blockDim.x, [&](int idx) { return P[idx]; }, [&](int idx, T v) { Ws[idx] = v; });
+  }
 }
 
 inline int nblk(int64_t n) { return (int)((n + 255) / 256); }
@@ -379,9 +391,13 @@ hipError_t launch_wide_tl(const SchwarzLaunch<T> &a, size_t s13, size_t s2, hipS
   if ((e = allow_lds(wide_slab2<T, TL>, s2)) != hipSuccess) return e;
   if ((e = allow_lds(wide_slab3<T, TL>, s13)) != hipSuccess) return e;
   const int *m = a.tabs.m;
-  wide_slab1<T, TL><<<a.mesh.E * m[2], 256, s13, st>>>(a.mesh, a.n, a.tabs, a.r, a.C);
-  wide_slab2<T, TL><<<a.mesh.E * m[1], 256, s2, st>>>(a.mesh.E, a.tabs, a.ilam, a.C);
-  wide_slab3<T, TL><<<a.mesh.E * m[2], 256, s13, st>>>(a.mesh.E, a.tabs, a.C);
+  // planes per workgroup (the tables are staged once per workgroup): as
+  // many as keep at least 4096 workgroups, at most 8
+  auto ppb_for = [&](int planes) { return std::max(1, std::min(8, a.mesh.E * planes / 4096)); };
+  const int pz = ppb_for(m[2]), py = ppb_for(m[1]);
+  wide_slab1<T, TL><<<a.mesh.E * ((m[2] + pz - 1) / pz), 256, s13, st>>>(a.mesh, a.n, a.tabs, a.r, a.C, pz);
+  wide_slab2<T, TL><<<a.mesh.E * ((m[1] + py - 1) / py), 256, s2, st>>>(a.mesh.E, a.tabs, a.ilam, a.C, py);
+  wide_slab3<T, TL><<<a.mesh.E * ((m[2] + pz - 1) / pz), 256, s13, st>>>(a.mesh.E, a.tabs, a.C, pz);
   return hipGetLastError();
 }
 
