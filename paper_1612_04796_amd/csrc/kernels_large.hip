@@ -237,7 +237,7 @@ __device__ __forceinline__ T gather_node(const Mesh &g, int n, const T *__restri
 
 // phase 1: block (s, c): gather the z-slab, x and y forward
 template <typename T, bool TL>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 wide_slab1(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restrict__ W, int ppb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *P = reinterpret_cast<T *>(smem_raw);
@@ -269,7 +269,7 @@ wide_slab1(Mesh g, int n, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restr
 
 // phase 2: block (s, b): the xz plane, z forward, scaling, z backward
 template <typename T, bool TL>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 wide_slab2(int E, SchwarzTabs<T> tb, const T *__restrict__ ilam, T *__restrict__ W, int ppb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *P = reinterpret_cast<T *>(smem_raw);
@@ -302,7 +302,7 @@ wide_slab2(int E, SchwarzTabs<T> tb, const T *__restrict__ ilam, T *__restrict__
 
 // phase 3: block (s, c): y and x backward
 template <typename T, bool TL>
-__global__ void __launch_bounds__(256) wide_slab3(int E, SchwarzTabs<T> tb, T *__restrict__ W, int ppb) {
+__global__ void __launch_bounds__(512) wide_slab3(int E, SchwarzTabs<T> tb, T *__restrict__ W, int ppb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *P = reinterpret_cast<T *>(smem_raw);
   const int mx = tb.m[0], my = tb.m[1], mz = tb.m[2];
@@ -395,9 +395,9 @@ hipError_t launch_wide_tl(const SchwarzLaunch<T> &a, size_t s13, size_t s2, hipS
   // many as keep at least 4096 workgroups, at most 8
   auto ppb_for = [&](int planes) { return std::max(1, std::min(8, a.mesh.E * planes / 4096)); };
   const int pz = ppb_for(m[2]), py = ppb_for(m[1]);
-  wide_slab1<T, TL><<<a.mesh.E * ((m[2] + pz - 1) / pz), 256, s13, st>>>(a.mesh, a.n, a.tabs, a.r, a.C, pz);
-  wide_slab2<T, TL><<<a.mesh.E * ((m[1] + py - 1) / py), 256, s2, st>>>(a.mesh.E, a.tabs, a.ilam, a.C, py);
-  wide_slab3<T, TL><<<a.mesh.E * ((m[2] + pz - 1) / pz), 256, s13, st>>>(a.mesh.E, a.tabs, a.C, pz);
+  wide_slab1<T, TL><<<a.mesh.E * ((m[2] + pz - 1) / pz), 512, s13, st>>>(a.mesh, a.n, a.tabs, a.r, a.C, pz);
+  wide_slab2<T, TL><<<a.mesh.E * ((m[1] + py - 1) / py), 512, s2, st>>>(a.mesh.E, a.tabs, a.ilam, a.C, py);
+  wide_slab3<T, TL><<<a.mesh.E * ((m[2] + pz - 1) / pz), 512, s13, st>>>(a.mesh.E, a.tabs, a.C, pz);
   return hipGetLastError();
 }
 
