@@ -392,8 +392,10 @@ hipError_t launch_wide_tl(const SchwarzLaunch<T> &a, size_t s13, size_t s2, hipS
   if ((e = allow_lds(wide_slab3<T, TL>, s13)) != hipSuccess) return e;
   const int *m = a.tabs.m;
   // planes per workgroup (the tables are staged once per workgroup): as
-  // many as keep at least 4096 workgroups, at most 8
-  auto ppb_for = [&](int planes) { return std::max(1, std::min(8, a.mesh.E * planes / 4096)); };
+  // many as keep at least 8192 workgroups, at most 4 (measured on the
+  // 23 x 51 x 51 subdomains: 1 plane 15.9 ms, 3 planes 15.3 ms, 6-16 planes
+  // slower)
+  auto ppb_for = [&](int planes) { return std::max(1, std::min(4, a.mesh.E * planes / 8192)); };
   const int pz = ppb_for(m[2]), py = ppb_for(m[1]);
   wide_slab1<T, TL><<<a.mesh.E * ((m[2] + pz - 1) / pz), 512, s13, st>>>(a.mesh, a.n, a.tabs, a.r, a.C, pz);
   wide_slab2<T, TL><<<a.mesh.E * ((m[1] + py - 1) / py), 512, s2, st>>>(a.mesh.E, a.tabs, a.ilam, a.C, py);
