@@ -179,3 +179,50 @@ def test_discretization_order(P, nes):
         errs.append(math.sqrt(np.dot(M, e * e)))
     order = math.log(errs[0] / errs[1]) / math.log(nes[1] / nes[0])
     assert order >= P + 1 - 0.2, (order, errs)
+
+
+# ---- variable V-cycle (Table 2: N_S,l = (1,1) x 3^(L-l)) ------------------
+# Smoothing steps per level written out from Table 2: one pre- and one
+# post-smoothing step on the top level, three times as many on each coarser
+# level.  Level 0 is solved, not smoothed.
+VAR_COUNTS = {2: {2: 1, 1: 3},            # P = 4: levels 1, 2, 4
+              3: {3: 1, 2: 3, 1: 9}}      # P = 8: levels 1, 2, 4, 8
+
+
+def _vcycle_from_steps(u, f, h, counts):
+    """Algorithm 1 composed from the oracle's level operations with explicit
+    smoothing counts per level."""
+    L = h.L
+    us, fs = {L: u}, {L: f}
+    for l in range(L, 0, -1):
+        if l < L:
+            us[l] = np.zeros_like(fs[l])
+        us[l] = oracle.smoother(us[l], fs[l], h, l, counts[l])
+        fs[l - 1] = oracle.restrict(fs[l] - oracle.apply_level(us[l], h, l), h, l)
+    us[0] = oracle.coarse_solve(fs[0], h)
+    for l in range(1, L + 1):
+        us[l] = us[l] + oracle.prolong(us[l - 1], h, l)
+        us[l] = oracle.smoother(us[l], fs[l], h, l, counts[l])
+    return us[L]
+
+
+@pytest.mark.parametrize("P", [4, 8])
+def test_variable_vcycle_smoothing_counts(P):
+    h = oracle.Hierarchy((3, 3, 3), (4.0, 2.0, 1.0), P, overlap="max", omega=0.08, growth=3)
+    counts = VAR_COUNTS[h.L]
+    assert [h.ns1[l] for l in range(1, h.L + 1)] == [counts[l] for l in range(1, h.L + 1)]
+    assert [h.ns2[l] for l in range(1, h.L + 1)] == [counts[l] for l in range(1, h.L + 1)]
+    k, phi, amp = fourier_modes(9, 3)
+    b = oracle.fourier_rhs(k, phi, amp, h)
+    u = uniform_vector(4, b.size)
+    got = oracle.vcycle(u, b, h)
+    want = _vcycle_from_steps(u, b, h, counts)
+    assert np.linalg.norm(got - want) <= 1e-13 * np.linalg.norm(want)
+    # the fixed cycle (growth 1) is the same composition with one step everywhere
+    h1 = oracle.Hierarchy((3, 3, 3), (4.0, 2.0, 1.0), P, overlap="max", omega=0.08)
+    ones = {l: 1 for l in range(1, h1.L + 1)}
+    assert np.linalg.norm(oracle.vcycle(u, b, h1) - _vcycle_from_steps(u, b, h1, ones)) \
+        <= 1e-13 * np.linalg.norm(want)
+    # and the counts matter: the reversed assignment 3^l gives another cycle
+    rev = {l: counts[h.L + 1 - l] for l in range(1, h.L + 1)}
+    assert np.linalg.norm(got - _vcycle_from_steps(u, b, h, rev)) > 1e-6 * np.linalg.norm(want)

@@ -147,3 +147,67 @@ def test_schwarz_weights_partition_of_unity_3d():
                 I = _sub_index3(tabs, (ex, ey, ez), Ns)
                 np.add.at(acc, I, np.kron(tabs[2].w, np.kron(tabs[1].w, tabs[0].w)))
     assert np.allclose(acc, 1.0, atol=1e-14)
+
+
+# ---- the weight function of Fig. 2 on dense synthetic node sets ------------
+# The caption fixes: a piecewise quintic transition, 0 at the subdomain
+# boundary, 1 on the part of the core that no neighbour's subdomain overlaps;
+# the global correction is a weighted average (partition of unity).  Node sets
+# with hundreds of nodes sample the transition finely enough to see its
+# polynomial degree and where it ends.  (The C^2 smoothstep among the
+# quintics is the reading, pinned by the golden 1D values and Table 1.)
+def _dense_nodes(n):
+    # symmetric, strictly increasing, end points +-1 (Chebyshev-Lobatto)
+    return -np.cos(np.pi * np.arange(n) / (n - 1))
+
+
+def _xi_h(xi, no):
+    n = len(xi)
+    return np.concatenate((xi[n - no:] - 2.0, xi, xi[:no] + 2.0))
+
+
+@pytest.mark.parametrize("n,no", [(201, 20), (201, 57), (301, 120), (101, 4)])
+def test_weight_transition_is_quintic_and_ends_at_subdomain_boundary(n, no):
+    xi = _dense_nodes(n)
+    w = oracle.hat_weights(xi, no)
+    xh = _xi_h(xi, no)
+    assert len(w) == n + 2 * no
+    # 0 at the subdomain boundary: the first neighbour node left out of the
+    # subdomain (the discrete Dirichlet boundary of the local problem) ...
+    b = xi[n - no - 1] - 2.0
+    # ... while every node of the subdomain keeps a positive weight
+    assert np.all(w > 0.0)
+    # 1 exactly on the core nodes no neighbour subdomain reaches (index
+    # no .. n-1-no of the core), below 1 on the overlapped ones
+    core = w[no:no + n]
+    assert np.all(core[no:n - no] == 1.0)
+    assert np.all(core[:no] < 1.0) and np.all(core[n - no:] < 1.0)
+    # the left transition: halo nodes plus overlapped core nodes, a single
+    # polynomial in xi_H of degree exactly 5 that vanishes at the boundary
+    sel = xh < xi[no]                        # every node left of the first non-overlapped core node
+    xs, ws = xh[sel], w[sel]
+    assert len(xs) >= 8
+    fit = np.polynomial.Polynomial.fit          # least squares on the scaled interval
+    p5, p4 = fit(xs, ws, 5), fit(xs, ws, 4)
+    r5 = np.abs(p5(xs) - ws).max()
+    r4 = np.abs(p4(xs) - ws).max()
+    assert r5 <= 1e-10, r5                   # a quintic ...
+    assert r4 >= 1e-4, r4                    # ... not of lower degree (a cubic step fails here)
+    assert abs(p5(b)) <= 1e-9
+    # it reaches 1 where the non-overlapped core starts
+    assert abs(p5(xi[no]) - 1.0) <= 1e-9
+    # mirror symmetry and the weighted average: 1/2 at the face
+    assert abs(p5(-1.0) - 0.5) <= 1e-9
+
+
+def test_weights_full_neighbour_overlap_reading():
+    # N_O = n (a whole neighbour in the subdomain): the transition is read as
+    # spanning one element width on each side of the face (delta = 1), so the
+    # three overlapping subdomains of a node still average to one; the outer
+    # half of the included neighbour gets weight 0.
+    xi = oracle.gll(16)[0]
+    w = oracle.hat_weights(xi, 17)
+    xh = _xi_h(xi, 17)
+    assert np.all(w[np.abs(xh) >= 2.0] == 0.0)
+    assert np.all(w[np.abs(xh) < 2.0] > 0.0)
+    assert np.allclose(w[np.abs(np.abs(xh) - 1.0) < 1e-14], 0.5, atol=1e-14)
