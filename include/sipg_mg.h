@@ -98,12 +98,26 @@ int sipg_setup(const sipg_params *p, void *hip_stream, sipg_ctx **out);
 /* Frees all device and host memory of the context (NULL is accepted). */
 int sipg_destroy(sipg_ctx *c);
 
-/* Device bytes sipg_setup would allocate for *p (for admission control);
- * computed on the host without touching the device. */
+/* Device bytes sipg_setup allocates for *p (for admission control), computed
+ * on the host without touching the device: the tables, the level-0 and
+ * flexible-CG vectors, the work space of the preconditioner precision and the
+ * scratch of the outer FP64 operator, i.e. everything sipg_pcg_solve and
+ * sipg_precond use, so neither allocates after sipg_setup.  The FP64 entry
+ * points (sipg_vcycle, sipg_mg_solve, sipg_smooth, ...) on a context with
+ * precond_bits 32 or 16 allocate the FP64 work space on their first call,
+ * beyond this figure. */
 int sipg_footprint(const sipg_params *p, size_t *bytes);
+
+/* Device bytes the context holds now (sipg_footprint plus what FP64 entry
+ * points allocated on an FP32/FP16-preconditioned context). */
+int sipg_device_bytes(const sipg_ctx *c, size_t *bytes);
 
 /* Number of levels L + 1. */
 int sipg_nlevels(const sipg_ctx *c, int *nlevels);
+
+/* Unknowns E*n_l^3 of level l (level -1: the top), the length of every
+ * vector argument on that level. */
+int sipg_ndof(const sipg_ctx *c, int level, int64_t *n);
 
 /* Order P_l, overlap layers N_O per direction and unknowns E*n^3 of level l. */
 int sipg_level_info(const sipg_ctx *c, int level, int *order, int no[3], int64_t *ndof);
@@ -156,20 +170,36 @@ int sipg_vcycle(sipg_ctx *c, double *u, const double *f);
  * the preconditioner of sipg_pcg_solve. */
 int sipg_precond(sipg_ctx *c, const double *r, double *z);
 
+/* The solvers and the singular periodic problem.  A has the constants as
+ * its null space (Sec. 2; Sec. 3.2, where Algorithm 1 uses the pseudo-inverse
+ * A_0^+ on the coarse level), so A u = f is solvable only for f orthogonal
+ * to the constants.  sipg_mg_solve and sipg_pcg_solve therefore solve
+ * A u = f - mean(f) 1 (the Euclidean projection of f onto the range of A,
+ * in a copy: f itself is not modified; sipg_rhs_mean returns the mean
+ * removed) and return, on SIPG_OK, the solution of zero Euclidean mean, the
+ * minimum-norm one.  Residual norms and rtol refer to the projected f. */
+
 /* Multigrid solve: repeats V-cycles from the value in u until
- * ||f - A u||_2 <= rtol ||f - A u_start||_2.  On return *ncyc holds the
- * cycles run and *relres the final relative residual.  SIPG_ENOCONV if maxcyc
- * cycles do not reach rtol (u holds the last iterate).  Synchronizes. */
+ * ||f - A u||_2 <= rtol ||f - A u_start||_2 (f projected, see above).  On
+ * return *ncyc holds the cycles run and *relres the final relative residual;
+ * u has zero mean.  SIPG_ENOCONV if maxcyc cycles do not reach rtol (u holds
+ * the last iterate, mean removed).  Synchronizes. */
 int sipg_mg_solve(sipg_ctx *c, double *u, const double *f, double rtol, int maxcyc,
                   int *ncyc, double *relres);
 
 /* Flexible (inexact preconditioned) CG (Sec. 3.2) with one V-cycle from zero
  * as preconditioner, FP64 outer iteration, starting from the value in u,
- * until the residual satisfies ||r||_2 <= rtol ||r_0||_2, confirmed by a
- * recomputed FP64 residual.  *iters: operator applications in the loop.
- * SIPG_ENOCONV / SIPG_EBREAKDOWN leave the last iterate in u.  Synchronizes. */
+ * until the residual of the projected f satisfies ||r||_2 <= rtol ||r_0||_2,
+ * confirmed by a recomputed FP64 residual of the iterate with its mean
+ * removed.  *iters: operator applications in the loop.  SIPG_ENOCONV /
+ * SIPG_EBREAKDOWN leave the last iterate in u (its mean not removed).
+ * Allocates nothing (see sipg_footprint).  Synchronizes. */
 int sipg_pcg_solve(sipg_ctx *c, double *u, const double *f, double rtol, int maxit,
                    int *iters, double *relres);
+
+/* Euclidean mean of f removed by the last sipg_mg_solve / sipg_pcg_solve
+ * (0 before any solve). */
+int sipg_rhs_mean(const sipg_ctx *c, double *mean);
 
 /* Residual norms of the last mg/pcg solve (index 0 = start); copies at most
  * cap values to the HOST array out and sets *n to the number available. */
@@ -252,7 +282,11 @@ int sipg_server_create(size_t memory_budget, int max_active, sipg_server **out);
 
 /* Queues a solve to rel. residual rtol within maxit iterations; k/phi/amp are
  * HOST arrays as in sipg_rhs_fourier (copied).  *id identifies the request.
- * SIPG_EINVAL for invalid parameters (nothing is queued). */
+ * SIPG_EINVAL for invalid parameters, SIPG_ENOMEM when the request's footprint
+ * (sipg_footprint plus its two vectors) exceeds the whole memory budget, so
+ * that it could never be admitted (nothing is queued in either case).  An
+ * admitted request's solution stays reserved in the budget until it is
+ * fetched: a client that never fetches can keep later requests queued. */
 int sipg_server_submit(sipg_server *s, const sipg_params *p, int nmodes, const int32_t *k, const double *phi,
                        const double *amp, double rtol, int maxit, int64_t *id);
 

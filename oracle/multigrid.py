@@ -204,10 +204,18 @@ def vcycle(u, f, hier):
     return _e(_vcycle_global(_g(u, hier), _g(f, hier), hier), hier)
 
 
+def _project(B):
+    """b - mean(b): the Euclidean projection onto the range of the singular
+    periodic operator (its null space is the constants, Sec. 3.2)."""
+    return B - B.mean()
+
+
 def mg_solve(b, hier, tol=1e-10, maxcyc=100, x0=None):
-    """Repeated V-cycles until ||b - A x|| <= tol ||b - A x0||.
-    Returns (x, cycles, relres, history of residual norms)."""
-    B = _g(b, hier)
+    """Repeated V-cycles until ||b - A x|| <= tol ||b - A x0|| for b projected
+    onto the range of A.  Returns (x, cycles, relres, history of residual
+    norms) with x of zero Euclidean mean (the minimum-norm solution, as the
+    pseudo-inverse of Algorithm 1)."""
+    B = _project(_g(b, hier))
     X = np.zeros_like(B) if x0 is None else _g(x0, hier)
     lev = hier.top
     hist = []
@@ -218,21 +226,24 @@ def mg_solve(b, hier, tol=1e-10, maxcyc=100, x0=None):
         if r0 is None:
             r0 = rn
         if rn <= tol * r0 or c == maxcyc:
-            return _e(X, hier), c, rn / r0, hist
+            return _e(X - X.mean(), hier), c, rn / r0, hist
         X = _vcycle_global(X, B, hier)
 
 
 def fcg_solve(b, hier, tol=1e-10, maxit=200, x0=None):
     """Flexible (inexact preconditioned) CG with one V-cycle from zero as the
-    preconditioner.  Returns (x, iterations, relres, history)."""
-    B = _g(b, hier)
+    preconditioner, for b projected onto the range of A.  Returns
+    (x, iterations, relres, history); a converged x has zero Euclidean mean
+    (the mean is removed before the recomputed residual confirms
+    convergence)."""
+    B = _project(_g(b, hier))
     X = np.zeros_like(B) if x0 is None else _g(x0, hier)
     lev = hier.top
     R = B - lev.A(X)
     r0 = float(np.linalg.norm(R))
     hist = [r0]
     if r0 == 0.0:
-        return _e(X, hier), 0, 0.0, hist
+        return _e(X - X.mean(), hier), 0, 0.0, hist
     Z = _vcycle_global(np.zeros_like(B), R, hier)
     Pd = Z.copy()
     rz = float(np.vdot(R, Z))
@@ -245,6 +256,7 @@ def fcg_solve(b, hier, tol=1e-10, maxit=200, x0=None):
         it += 1
         rn = float(np.linalg.norm(R))
         if rn <= tol * r0:
+            X = X - X.mean()
             Rt = B - lev.A(X)
             rt = float(np.linalg.norm(Rt))
             if rt <= tol * r0:

@@ -154,9 +154,12 @@ hipError_t launch_finalize(const double *partial, int np, double scale, double *
 // partial[b] = sum over block b of x[i], kDotBlocks blocks
 template <typename T>
 hipError_t launch_sum_partials(const T *x, int64_t n, double *partial, hipStream_t st);
-// y[i] = a[i] - (*s)
+// y[i] -= (*s)
 template <typename T>
 hipError_t launch_sub_scalar(T *y, int64_t n, const double *s, hipStream_t st);
+// y[i] = x[i] - (*s)
+template <typename T>
+hipError_t launch_sub_scalar_copy(const T *x, T *y, int64_t n, const double *s, hipStream_t st);
 template <typename TO, typename TI>
 hipError_t launch_convert(const TI *x, TO *y, int64_t n, hipStream_t st);
 template <typename T>
@@ -164,8 +167,9 @@ hipError_t launch_fill(T *x, int64_t n, T v, hipStream_t st);
 
 // Flexible CG scalars live in device memory: see kernels_vec.hip.
 enum FcgScalar { FS_RZ = 0, FS_PQ = 1, FS_RR = 2, FS_ZQ = 3, FS_RZNEW = 4, FS_ALPHA = 5, FS_BETA = 6,
-                 FS_MEAN = 7,  // mean of a generated right-hand side
-                 FS_COUNT = 8 };
+                 FS_MEAN = 7,  // Euclidean mean removed from a right-hand side
+                 FS_XMEAN = 8, // Euclidean mean removed from a solution
+                 FS_COUNT = 9 };
 // One flexible-CG iteration is split so that no vector is read twice where
 // it can be avoided:
 //   r -= alpha q, partial = r.r, r32 = (float) r when given   (alpha = s[RZ] / s[PQ])

@@ -90,10 +90,11 @@ finalize_kernel(const double *__restrict__ partial, int np, double scale, double
   }
 }
 
+// y = x - s[0]; y may equal x
 template <typename T>
-__global__ void __launch_bounds__(256) sub_scalar(T *__restrict__ y, int64_t n, const double *__restrict__ s) {
+__global__ void __launch_bounds__(256) sub_scalar(const T *x, T *y, int64_t n, const double *__restrict__ s) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (T)((double)y[i] - s[0]);
+  if (i < n) y[i] = (T)((double)x[i] - s[0]);
 }
 
 template <typename TO, typename TI>
@@ -288,7 +289,14 @@ hipError_t launch_fcg_r_segments(const FcgRSegs &segs, hipStream_t st) {
 template <typename T>
 hipError_t launch_sub_scalar(T *y, int64_t n, const double *s, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  sub_scalar<T><<<nblocks(n), 256, 0, st>>>(y, n, s);
+  sub_scalar<T><<<nblocks(n), 256, 0, st>>>(y, y, n, s);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sub_scalar_copy(const T *x, T *y, int64_t n, const double *s, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  sub_scalar<T><<<nblocks(n), 256, 0, st>>>(x, y, n, s);
   return hipGetLastError();
 }
 
@@ -355,6 +363,7 @@ template hipError_t launch_fcg_xp<double>(double *, double *, const double *, in
 template hipError_t launch_fcg_xp<float>(double *, double *, const float *, int64_t, const double *, bool,
                                          hipStream_t);
 template hipError_t launch_sub_scalar<double>(double *, int64_t, const double *, hipStream_t);
+template hipError_t launch_sub_scalar_copy<double>(const double *, double *, int64_t, const double *, hipStream_t);
 template hipError_t launch_sub_scalar<float>(float *, int64_t, const double *, hipStream_t);
 template hipError_t launch_sum_partials<double>(const double *, int64_t, double *, hipStream_t);
 template hipError_t launch_sum_partials<float>(const float *, int64_t, double *, hipStream_t);

@@ -232,7 +232,7 @@ int advance(sipg_server *s, Request *r) {
       }
       r->relres = rn / r->r0;
       if (rn <= r->rtol * r->r0) {
-        sipg::detail::fcg_confirm(r->ctx, r->x, r->b);
+        sipg::detail::fcg_confirm(r->ctx, r->x);
         r->phase = PH_CONFIRM;
       } else if (r->iters >= r->maxit) {
         finish(s, r, SIPG_REQ_FAILED, "tolerance not reached");
@@ -425,6 +425,12 @@ int sipg_server_submit(sipg_server *s, const sipg_params *p, int nmodes, const i
   size_t fp = 0;
   int rc = sipg_footprint(p, &fp);  // validates the parameters
   if (rc != SIPG_OK) return rc;
+  // a request that could never be admitted would block the FIFO for good
+  const int64_t n = (int64_t)p->P + 1;
+  const size_t need = fp + 2 * (size_t)((int64_t)p->ne[0] * p->ne[1] * p->ne[2] * n * n * n) * sizeof(double);
+  if (need > s->budget)
+    return fail(SIPG_ENOMEM, "request needs " + std::to_string(need) + " device bytes, more than the server's budget of " +
+                                 std::to_string(s->budget));
   auto r = std::make_unique<Request>();
   r->id = s->next_id++;
   r->prm = *p;

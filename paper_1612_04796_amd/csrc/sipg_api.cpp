@@ -95,6 +95,8 @@ struct sipg_ctx {
   Work<float> w32;
   // flexible CG vectors (FP64, top level) and device scalars
   double *cg_r = nullptr, *cg_p = nullptr, *cg_q = nullptr, *cg_z = nullptr;
+  double *cg_b = nullptr;               // the solvers' right side, projected onto 1^perp
+  double f_mean = 0.0;                  // Euclidean mean removed from f by the last solve
   double *scal = nullptr;               // the FS_COUNT slots of FcgScalar
   double *partial = nullptr;            // 2 * kDotBlocks
   double *host_scal = nullptr;          // pinned host mirror
@@ -162,7 +164,8 @@ int64_t level_ndof(const sipg::HierarchyHost &H, int l) {
   return E * n * n * n;
 }
 
-// Bytes of one precision's V-cycle work space.
+// Bytes of one precision's V-cycle work space (without the scratch of the
+// large-element operator, big_bytes).
 size_t work_bytes(const sipg::HierarchyHost &H, size_t eb) {
   const int L = (int)H.lev.size() - 1;
   const int64_t E = (int64_t)H.prm.ne[0] * H.prm.ne[1] * H.prm.ne[2];
@@ -170,9 +173,28 @@ size_t work_bytes(const sipg::HierarchyHost &H, size_t eb) {
   for (int l = 0; l < L; ++l) b += 2 * (size_t)level_ndof(H, l) * eb;
   b += 3 * (size_t)level_ndof(H, L) * eb;  // r plus an internal top-level u, f pair
   b += (size_t)E * max_sub(H) * eb;
-  const int nt = H.lev[L].n;
-  if (sipg::apply_is_large(nt)) b += (size_t)E * ((size_t)nt * nt * nt + (size_t)nt * nt * H.lev[L - 1].n) * eb;
   return b;
+}
+
+// Values of the scratch of the top level's large-element operator passes
+// and transfers (0 when the top order fits the LDS kernels).
+size_t big_count(const sipg::HierarchyHost &H) {
+  const int L = (int)H.lev.size() - 1;
+  const int64_t E = (int64_t)H.prm.ne[0] * H.prm.ne[1] * H.prm.ne[2];
+  const int nt = H.lev[L].n;
+  if (L == 0 || !sipg::apply_is_large(nt)) return 0;
+  return (size_t)E * ((size_t)nt * nt * nt + (size_t)nt * nt * H.lev[L - 1].n);
+}
+
+// the large-element scratch of precision T (allocated on first use)
+template <typename T>
+T *ensure_big(sipg_ctx *c) {
+  Work<T> &w = work_of<T>(c);
+  if (!w.big) {
+    const size_t n = big_count(c->H);
+    if (n) w.big = c->alloc<T>(n);
+  }
+  return w.big;
 }
 
 template <typename T>
@@ -190,11 +212,7 @@ void ensure_work(sipg_ctx *c) {
   w.fL = c->alloc<T>(level_ndof(H, c->L));
   w.r = c->alloc<T>(level_ndof(H, c->L));
   w.C = c->alloc<T>((size_t)c->mesh.E * max_sub(H));
-  const int nt = H.lev[c->L].n;
-  if (sipg::apply_is_large(nt)) {
-    const int nc = H.lev[c->L - 1].n;
-    w.big = c->alloc<T>((size_t)c->mesh.E * ((size_t)nt * nt * nt + (size_t)nt * nt * nc));
-  }
+  ensure_big<T>(c);
   w.ready = true;
 }
 
@@ -293,19 +311,33 @@ MfmaHost build_mfma_tables(const sipg::LevelHost &lv) {
   return h;
 }
 
-void upload_tables(sipg_ctx *c) {
-  const sipg::HierarchyHost &H = c->H;
+// Offsets of one level's tables in the arena.
+struct TabOff {
+  size_t Ld[3], LdEO[3], M[3], DL[3], DR[3], S[3], WS[3], WST[3], lam[3], EO[3], J, ilam, ilam_eo;
+  size_t mf[3], mb[3], mil;
+  double kout;
+  bool mfma;
+};
+
+// Every device table of a context, staged on the host (built by
+// build_table_arena, uploaded by upload_tables; its size is part of
+// sipg_footprint).
+struct TableArena {
   Arena A;
-  struct Off {
-    size_t Ld[3], LdEO[3], M[3], DL[3], DR[3], S[3], WS[3], WST[3], lam[3], EO[3], J, ilam, ilam_eo;
-    size_t mf[3], mb[3], mil;
-    double kout;
-    bool mfma;
-  };
-  std::vector<Off> o64(c->L + 1), o32(c->L + 1);
-  auto put_level = [&](auto tag, std::vector<Off> &off) {
+  std::vector<TabOff> o64, o32;
+  size_t cS[3], cC[3], cL[3], oxi, omass[3];
+};
+
+TableArena build_table_arena(const sipg::HierarchyHost &H, int64_t E) {
+  const int L = (int)H.lev.size() - 1;
+  TableArena T_;
+  Arena &A = T_.A;
+  std::vector<TabOff> &o64 = T_.o64, &o32 = T_.o32;
+  o64.assign(L + 1, TabOff{});
+  o32.assign(L + 1, TabOff{});
+  auto put_level = [&](auto tag, std::vector<TabOff> &off) {
     using T = decltype(tag);
-    for (int l = 0; l <= c->L; ++l) {
+    for (int l = 0; l <= L; ++l) {
       const sipg::LevelHost &lv = H.lev[l];
       for (int d = 0; d < 3; ++d) {
         const sipg::Dir1D &D = lv.dir[d];
@@ -344,7 +376,7 @@ void upload_tables(sipg_ctx *c) {
         off[l].ilam_eo = A.put<T>(il);
         const int m3[3] = {X.m, Y.m, Z.m};
         off[l].mfma = std::is_same<T, float>::value && sipg::mfma_fdm_supported(lv.n, m3) &&
-                      (int64_t)c->mesh.E * lv.n * lv.n * lv.n < ((int64_t)1 << 30);
+                      E * lv.n * lv.n * lv.n < ((int64_t)1 << 30);
         if (off[l].mfma) {
           const MfmaHost mh = build_mfma_tables(lv);
           for (int d = 0; d < 3; ++d) {
@@ -359,7 +391,7 @@ void upload_tables(sipg_ctx *c) {
   };
   put_level(double(), o64);
   put_level(float(), o32);
-  size_t cS[3], cC[3], cL[3];
+  size_t *cS = T_.cS, *cC = T_.cC, *cL = T_.cL;
   for (int d = 0; d < 3; ++d) {
     const int N = H.coarse.N[d];
     std::vector<double> cs(N, 0.0);
@@ -369,16 +401,24 @@ void upload_tables(sipg_ctx *c) {
     cC[d] = A.put<double>(cs);
     cL[d] = A.put<double>(H.coarse.lam[d]);
   }
-  const size_t oxi = A.put<double>(H.lev[c->L].dir[0].xi);
-  size_t omass[3];
-  for (int d = 0; d < 3; ++d) omass[d] = A.put<double>(H.lev[c->L].dir[d].mass);
+  T_.oxi = A.put<double>(H.lev[L].dir[0].xi);
+  for (int d = 0; d < 3; ++d) T_.omass[d] = A.put<double>(H.lev[L].dir[d].mass);
+  return T_;
+}
+
+void upload_tables(sipg_ctx *c) {
+  const sipg::HierarchyHost &H = c->H;
+  TableArena T_ = build_table_arena(H, c->mesh.E);
+  Arena &A = T_.A;
+  std::vector<TabOff> &o64 = T_.o64, &o32 = T_.o32;
+  const size_t *cS = T_.cS, *cC = T_.cC, *cL = T_.cL, oxi = T_.oxi, *omass = T_.omass;
 
   c->tab_dev = c->alloc<unsigned char>(A.host.size());
   check(hipMemcpyAsync(c->tab_dev, A.host.data(), A.host.size(), hipMemcpyHostToDevice, c->stream),
         "table upload");
   check(hipStreamSynchronize(c->stream), "table upload");
 
-  auto fill = [&](auto tag, std::vector<Off> &off, auto &dst) {
+  auto fill = [&](auto tag, std::vector<TabOff> &off, auto &dst) {
     using T = decltype(tag);
     dst.assign(c->L + 1, {});
     for (int l = 0; l <= c->L; ++l) {
@@ -456,8 +496,7 @@ void trace_end(sipg_ctx *c, int k) {
 template <typename T>
 void run_apply(sipg_ctx *c, const sipg::ApplyLaunch<T> &a, const char *what) {
   if (sipg::apply_is_large(a.n)) {
-    ensure_work<T>(c);
-    check(sipg::launch_apply_large<T>(a, work_of<T>(c).big, c->stream), what);
+    check(sipg::launch_apply_large<T>(a, ensure_big<T>(c), c->stream), what);
   } else {
     check(sipg::launch_apply<T>(a, c->stream), what);
   }
@@ -530,8 +569,7 @@ void op_prolong(sipg_ctx *c, int l, const TC *uc, bool with_mean, T *uf) {
                                sipg::coarse_num_partials(c->coarse), 1.0 / (double)N0, uf};
   const int k = trace_begin<T>(c, SIPG_KERNEL_PROLONG, l);
   if (sipg::apply_is_large(t.n)) {
-    ensure_work<T>(c);
-    check(sipg::launch_prolong_large<T, TC>(a, work_of<T>(c).big, c->stream), "prolong");
+    check(sipg::launch_prolong_large<T, TC>(a, ensure_big<T>(c), c->stream), "prolong");
   } else {
     check(sipg::launch_prolong<T, TC>(a, c->stream), "prolong");
   }
@@ -639,9 +677,10 @@ void fcg_precond(sipg_ctx *c) {
     return;
   }
   if (!c->precond_graph) {
-    // every work buffer exists before the capture (no allocation inside it)
-    ensure_work<double>(c);
-    if (c->H.prm.precond_bits != 64) ensure_work<float>(c);
+    // every work buffer of the preconditioner exists before the capture (no
+    // allocation inside it)
+    if (c->H.prm.precond_bits == 64) ensure_work<double>(c);
+    else ensure_work<float>(c);
     check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "graph capture");
     hipGraph_t g = nullptr;
     c->capturing = true;
@@ -680,6 +719,27 @@ void dot(sipg_ctx *c, const double *x, const double *y, int64_t n, int slot) {
   check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0, c->scal + slot, c->stream), "dot");
 }
 
+// The periodic problem is singular with null space the constants (Sec. 3.2):
+// the solvers work on f projected onto the range 1^perp, cg_b = f - mean(f)
+// (the mean in scal[FS_MEAN]), and return the solution of zero Euclidean mean
+// (the minimum-norm one, as the coarse pseudo-inverse of Algorithm 1).
+void project_rhs(sipg_ctx *c, const double *f) {
+  const int64_t N = level_ndof(c->H, c->L);
+  check(sipg::launch_sum_partials<double>(f, N, c->partial, c->stream), "rhs mean");
+  check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0 / (double)N, c->scal + sipg::FS_MEAN, c->stream),
+        "rhs mean");
+  check(sipg::launch_sub_scalar_copy<double>(f, c->cg_b, N, c->scal + sipg::FS_MEAN, c->stream), "rhs mean");
+}
+
+// x -= mean(x) (the mean in scal[FS_XMEAN])
+void remove_mean(sipg_ctx *c, double *x) {
+  const int64_t N = level_ndof(c->H, c->L);
+  check(sipg::launch_sum_partials<double>(x, N, c->partial, c->stream), "solution mean");
+  check(sipg::launch_finalize(c->partial, sipg::kDotBlocks, 1.0 / (double)N, c->scal + sipg::FS_XMEAN, c->stream),
+        "solution mean");
+  check(sipg::launch_sub_scalar<double>(x, N, c->scal + sipg::FS_XMEAN, c->stream), "solution mean");
+}
+
 // MG solve.  When the convergence rate observed so far predicts that the
 // current iterate cannot have converged yet, the next V-cycle is enqueued
 // before the host reads the residual norm, so the device does not wait for the
@@ -689,6 +749,8 @@ int mg_solve_impl(sipg_ctx *c, double *u, const double *f, double rtol, int maxc
                   double *relres) {
   const int64_t N = level_ndof(c->H, c->L);
   ensure_work<double>(c);
+  project_rhs(c, f);
+  f = c->cg_b;
   // two iterate buffers: the caller's u and a work vector free during FP64
   // V-cycles; a speculative cycle writes the new iterate into the other one
   double *cur = u, *alt = c->w64.uL;
@@ -709,12 +771,13 @@ int mg_solve_impl(sipg_ctx *c, double *u, const double *f, double rtol, int maxc
     check(hipEventSynchronize(ev), "residual norm");
     const double rn = std::sqrt(c->host_scal[sipg::FS_RR]);
     c->hist.push_back(rn);
-    if (r0 < 0) r0 = rn;
+    if (r0 < 0) r0 = rn, c->f_mean = c->host_scal[sipg::FS_MEAN];
     if (ncyc) *ncyc = cyc;
     if (relres) *relres = r0 > 0 ? rn / r0 : 0.0;
     if (!std::isfinite(rn) || rn <= rtol * r0 || cyc >= maxcyc) {
       // the checked iterate is cur; a speculative cycle's result is dropped
       if (cur != u) check(sipg::launch_convert<double, double>(cur, u, N, c->stream), "result copy");
+      if (std::isfinite(rn)) remove_mean(c, u);
       check(hipStreamSynchronize(c->stream), "mg_solve");
       if (!std::isfinite(rn)) return fail(SIPG_ENOTFINITE, "residual norm is not finite");
       if (rn <= rtol * r0) return SIPG_OK;
@@ -735,10 +798,15 @@ int pcg_solve_impl(sipg_ctx *c, double *x, const double *b, double rtol, int max
   sipg::detail::fcg_start(c, x, b);
   check(hipStreamSynchronize(c->stream), "fcg");
   const double r0 = std::sqrt(c->host_scal[sipg::FS_RR]);
+  c->f_mean = c->host_scal[sipg::FS_MEAN];
   c->hist.push_back(r0);
   if (!std::isfinite(r0)) return fail(SIPG_ENOTFINITE, "initial residual is not finite");
   if (relres) *relres = 0.0;
-  if (r0 == 0.0) return SIPG_OK;
+  if (r0 == 0.0) {
+    remove_mean(c, x);
+    check(hipStreamSynchronize(c->stream), "fcg");
+    return SIPG_OK;
+  }
   sipg::detail::fcg_first_precond(c);
   for (int it = 1; it <= maxit; ++it) {
     sipg::detail::fcg_apply_update(c);
@@ -752,7 +820,7 @@ int pcg_solve_impl(sipg_ctx *c, double *x, const double *b, double rtol, int max
     }
     if (!std::isfinite(rn)) return fail(SIPG_ENOTFINITE, "residual norm is not finite");
     if (rn <= rtol * r0) {
-      sipg::detail::fcg_confirm(c, x, b);
+      sipg::detail::fcg_confirm(c, x);
       check(hipStreamSynchronize(c->stream), "fcg");
       const double rt = std::sqrt(c->host_scal[sipg::FS_RR]);
       if (rt <= rtol * r0) {
@@ -798,7 +866,10 @@ int guarded(F &&fn) {
 namespace sipg {
 namespace detail {
 
-void fcg_start(sipg_ctx *c, double *x, const double *b) { residual_norm2(c, x, b, c->cg_r, sipg::FS_RR, true); }
+void fcg_start(sipg_ctx *c, double *x, const double *b) {
+  project_rhs(c, b);
+  residual_norm2(c, x, c->cg_b, c->cg_r, sipg::FS_RR, true);
+}
 
 void fcg_first_precond(sipg_ctx *c) {
   const int64_t N = level_ndof(c->H, c->L);
@@ -866,11 +937,13 @@ void fcg_apply_update(sipg_ctx *c) {
   fcg_after_apply(c, c->stream);
 }
 
-void fcg_confirm(sipg_ctx *c, double *x, const double *b) {
+void fcg_confirm(sipg_ctx *c, double *x) {
   const int64_t N = level_ndof(c->H, c->L);
   if (c->x_pending) check(sipg::launch_fcg_x(x, c->cg_p, N, c->scal, c->stream), "fcg update");
   c->x_pending = false;
-  residual_norm2(c, x, b, c->cg_q, sipg::FS_RR, true);
+  // the returned iterate has zero mean (A 1 = 0: the residual is unchanged)
+  remove_mean(c, x);
+  residual_norm2(c, x, c->cg_b, c->cg_q, sipg::FS_RR, true);
 }
 
 void fcg_restart_from_true(sipg_ctx *c) {
@@ -990,6 +1063,39 @@ void tune_level(sipg_ctx *c, int l, int reps) {
 
 }  // namespace
 
+namespace {
+
+// Device bytes sipg_setup allocates for hierarchy H: the table arena, the
+// level-0 and flexible-CG vectors, the scalars and partial sums, the
+// preconditioner's work space and the FP64 large-element scratch (every
+// buffer sipg_pcg_solve and sipg_precond use; FP64 entry points on a context
+// with precond_bits 32 or 16 add the FP64 work space on first use).
+size_t context_bytes(const sipg::HierarchyHost &H) {
+  auto al = [](size_t count, size_t eb) { return std::max<size_t>(count, 1) * eb; };
+  const int L = (int)H.lev.size() - 1;
+  const int64_t E = (int64_t)H.prm.ne[0] * H.prm.ne[1] * H.prm.ne[2];
+  const int64_t N0 = level_ndof(H, 0), N = level_ndof(H, L);
+  sipg::CoarseLaunch cl{};
+  for (int d = 0; d < 3; ++d) cl.ne[d] = H.prm.ne[d], cl.N[d] = H.coarse.N[d];
+  const size_t np = (size_t)sipg::coarse_num_partials(cl);
+  size_t b = al(build_table_arena(H, E).A.host.size(), 1);
+  b += 2 * al(N0, 8) + 2 * al(np, 8) + al(4, 8);                     // u0, coarse work, plane sums
+  b += 5 * al(N, 8);                                                 // r, p, q, z, projected b
+  b += al(sipg::FS_COUNT, 8);
+  b += al(std::max<size_t>(2 * sipg::kDotBlocks, sipg::apply_num_blocks((int)E, H.lev[L].n, 1)), 8);
+  b += al(64 * 3, 4) + al(64 * 3, 8) + al(64, 8);                    // Fourier modes
+  const size_t eb = H.prm.precond_bits == 64 ? 8 : 4;
+  if (L > 0) {
+    b += work_bytes(H, eb) + (big_count(H) ? big_count(H) * eb : 0);
+    if (eb != 8 && big_count(H)) b += big_count(H) * 8;
+  } else {
+    b += work_bytes(H, eb);
+  }
+  return b;
+}
+
+}  // namespace
+
 extern "C" {
 
 void sipg_default_params(sipg_params *p) {
@@ -1014,14 +1120,7 @@ int sipg_footprint(const sipg_params *p, size_t *bytes) {
   return guarded([&]() {
     sipg::HierarchyHost H;
     sipg::build_hierarchy(*p, H);
-    const int L = (int)H.lev.size() - 1;
-    const int64_t N = level_ndof(H, L);
-    size_t b = work_bytes(H, p->precond_bits != 64 ? sizeof(float) : sizeof(double));
-    if (p->precond_bits != 64) b += (size_t)level_ndof(H, 0) * sizeof(double);
-    b += 4 * (size_t)N * sizeof(double);                 // flexible CG vectors
-    b += (size_t)level_ndof(H, 0) * sizeof(double) * 3;  // coarse work
-    b += 1 << 20;                                        // tables and scalars (bound)
-    *bytes = b;
+    *bytes = context_bytes(H);
     return (int)SIPG_OK;
   });
 }
@@ -1048,6 +1147,7 @@ int sipg_setup(const sipg_params *p, void *hip_stream, sipg_ctx **out) {
     c->cg_p = c->alloc<double>(N);
     c->cg_q = c->alloc<double>(N);
     c->cg_z = c->alloc<double>(N);
+    c->cg_b = c->alloc<double>(N);
     c->scal = c->alloc<double>(sipg::FS_COUNT);
     // partial sums: the reductions use 2 * kDotBlocks, the fused p.Ap of the
     // top-level apply one per apply workgroup
@@ -1061,8 +1161,11 @@ int sipg_setup(const sipg_params *p, void *hip_stream, sipg_ctx **out) {
       throw std::bad_alloc();
     check(hipHostGetDevicePointer((void **)&c->host_scal_dev, c->host_scal, 0), "host mirror");
     check(sipg::launch_fill<double>(c->scal, sipg::FS_COUNT, 0.0, c->stream), "init");
+    // the preconditioner's work space, and the FP64 large-element scratch of
+    // the outer operator (so that sipg_pcg_solve allocates nothing)
     if (p->precond_bits == 64) ensure_work<double>(c.get());
     else ensure_work<float>(c.get());
+    ensure_big<double>(c.get());
     check(hipStreamSynchronize(c->stream), "setup");
     return (int)SIPG_OK;
   });
@@ -1093,6 +1196,26 @@ int sipg_level_info(const sipg_ctx *c, int level, int *order, int no[3], int64_t
   if (no)
     for (int d = 0; d < 3; ++d) no[d] = c->H.lev[l].dir[d].no;
   if (ndof) *ndof = level_ndof(c->H, l);
+  return SIPG_OK;
+}
+
+int sipg_ndof(const sipg_ctx *c, int level, int64_t *n) {
+  if (!c || !n) return fail(SIPG_EINVAL, "null argument");
+  const int l = resolve_level(c, level);
+  if (l < 0) return fail(SIPG_EINVAL, "level out of range");
+  *n = level_ndof(c->H, l);
+  return SIPG_OK;
+}
+
+int sipg_rhs_mean(const sipg_ctx *c, double *mean) {
+  if (!c || !mean) return fail(SIPG_EINVAL, "null argument");
+  *mean = c->f_mean;
+  return SIPG_OK;
+}
+
+int sipg_device_bytes(const sipg_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return fail(SIPG_EINVAL, "null argument");
+  *bytes = c->bytes;
   return SIPG_OK;
 }
 

@@ -15,6 +15,7 @@
 namespace sipg {
 namespace detail {
 
+// b projected onto 1^perp into the context (its mean in FS_MEAN), then
 // r = b - A x and ||r||^2 (FS_RR)
 void fcg_start(sipg_ctx *c, double *x, const double *b);
 // z = B r, rz = r.z, p = z
@@ -34,8 +35,9 @@ void fcg_after_apply(sipg_ctx *c, hipStream_t st);
 // fcg_after_apply of k contexts (k <= kMaxApplySegments) with one launch per
 // kernel instead of one per context
 void fcg_after_apply_batched(sipg_ctx *const *cs, int k, hipStream_t st);
-// x += alpha p if pending, then ||b - A x||^2 (FS_RR), the true residual kept in q
-void fcg_confirm(sipg_ctx *c, double *x, const double *b);
+// x += alpha p if pending, x -= mean(x), then ||b - A x||^2 (FS_RR) with the
+// projected b of fcg_start, the true residual kept in q
+void fcg_confirm(sipg_ctx *c, double *x);
 // r = true residual, q = A p again
 void fcg_restart_from_true(sipg_ctx *c);
 // z = B r, beta = -alpha (z.q) / rz, rz = r.z, x += alpha p if pending, p = z + beta p

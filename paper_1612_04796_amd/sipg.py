@@ -27,7 +27,7 @@ EXPORTS = (
     "sipg_smooth", "sipg_restrict", "sipg_prolong_add", "sipg_coarse_solve", "sipg_vcycle",
     "sipg_precond", "sipg_mg_solve", "sipg_pcg_solve", "sipg_residual_history",
     "sipg_last_error", "sipg_host_table", "sipg_time_kernel", "sipg_autotune", "sipg_tuning",
-    "sipg_set_option", "sipg_traced_kernel_ms",
+    "sipg_set_option", "sipg_traced_kernel_ms", "sipg_ndof", "sipg_rhs_mean", "sipg_device_bytes",
     "sipg_server_create", "sipg_server_submit", "sipg_server_progress", "sipg_server_status",
     "sipg_server_fetch", "sipg_server_destroy", "sipg_server_set_option", "sipg_server_stats",
 )
@@ -80,6 +80,9 @@ def lib():
             "sipg_footprint": (c_int, [P(Params), P(ctypes.c_size_t)]),
             "sipg_nlevels": (c_int, [vp, P(c_int)]),
             "sipg_level_info": (c_int, [vp, c_int, P(c_int), P(c_int), P(ctypes.c_int64)]),
+            "sipg_ndof": (c_int, [vp, c_int, P(ctypes.c_int64)]),
+            "sipg_rhs_mean": (c_int, [vp, P(c_double)]),
+            "sipg_device_bytes": (c_int, [vp, P(ctypes.c_size_t)]),
             "sipg_rhs_fourier": (c_int, [vp, c_int, P(ctypes.c_int32), P(c_double), P(c_double), vp]),
             "sipg_apply_A": (c_int, [vp, c_int, vp, vp]),
             "sipg_residual": (c_int, [vp, c_int, vp, vp, vp]),
@@ -210,7 +213,21 @@ class Solver:
         return {"order": order.value, "no": tuple(no), "ndof": nd.value}
 
     def ndof(self, level=-1):
-        return self.level_info(level)["ndof"]
+        n = ctypes.c_int64()
+        _check(lib().sipg_ndof(self._h, level, ctypes.byref(n)))
+        return n.value
+
+    def rhs_mean(self):
+        """Euclidean mean of f removed by the last mg_solve / pcg_solve."""
+        m = ctypes.c_double()
+        _check(lib().sipg_rhs_mean(self._h, ctypes.byref(m)))
+        return m.value
+
+    def device_bytes(self):
+        """Device bytes the context holds now."""
+        b = ctypes.c_size_t()
+        _check(lib().sipg_device_bytes(self._h, ctypes.byref(b)))
+        return b.value
 
     def _vec(self, t, level, name):
         import torch

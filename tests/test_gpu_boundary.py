@@ -1,0 +1,100 @@
+"""The solvers' treatment of the singular periodic problem (Sec. 3.2: the
+null space of A is the constants; Algorithm 1 uses the pseudo-inverse) and
+the memory figure the serving loop admits by.
+
+* sipg_mg_solve / sipg_pcg_solve solve for f projected onto the range of A
+  (its Euclidean mean removed) and return the zero-mean solution; compared
+  with the oracle, which does the same, and with the exact discrete solution.
+* sipg_footprint covers every buffer a context holds after a graph-captured
+  flexible-CG solve (the path the server runs), for every preconditioner
+  precision and for order 32 (large-element scratch).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_04796_amd import sipg
+from paper_1612_04796_amd.workloads import fourier_modes
+
+from _gpu import announce, dev, host, pair, rel, torch_cuda, zeros
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("solver,bits", [("mg", 64), ("fcg", 64), ("fcg", 32)])
+def test_right_side_with_mean_is_projected(solver, bits):
+    announce("projection", solver, bits)
+    ne, length, P = (4, 3, 5), (2.0, 1.0, 0.5), 4
+    h, s = pair(ne, length, P, overlap="rel", precond_bits=bits)
+    k, phi, amp = fourier_modes(7, 3)
+    b0 = oracle.fourier_rhs(k, phi, amp, h)
+    shift = 2.5 * np.abs(b0).max()
+    b = b0 + shift                                    # not in the range of A
+    x = zeros(h.ndof())
+    if solver == "mg":
+        it, rr = s.mg_solve(x, dev(b), rtol=1e-10, maxcyc=60)
+        xo, ito, _, _ = oracle.mg_solve(b, h, tol=1e-10, maxcyc=60)
+    else:
+        it, rr = s.pcg_solve(x, dev(b), rtol=1e-10, maxit=60)
+        xo, ito, _, _ = oracle.fcg_solve(b, h, tol=1e-10, maxit=60)
+    xh = host(x)
+    assert rr <= 1e-10
+    assert abs(s.rhs_mean() - b.mean()) <= 1e-14 * abs(b.mean())
+    assert abs(xh.mean()) <= 1e-14 * np.linalg.norm(xh)
+    if bits == 64:
+        assert it == ito
+        assert rel(xh, xo) <= 1e-10
+    assert rel(xh, oracle.exact_solution(b0, h)) <= 1e-8
+    s.close()
+
+
+def test_nonzero_start_returns_zero_mean():
+    announce("projection start")
+    ne, length, P = (4, 4, 4), (1.0, 1.0, 1.0), 4
+    h, s = pair(ne, length, P, overlap="min")
+    k, phi, amp = fourier_modes(8, 3)
+    b = oracle.fourier_rhs(k, phi, amp, h)
+    for solve in (s.mg_solve, s.pcg_solve):
+        x = dev(np.full(h.ndof(), 3.0))               # a start far from the zero-mean gauge
+        solve(x, dev(b), 1e-10, 60)
+        xh = host(x)
+        assert abs(xh.mean()) <= 1e-14 * np.linalg.norm(xh)
+        assert rel(xh, oracle.exact_solution(b, h)) <= 1e-8
+    s.close()
+
+
+@pytest.mark.parametrize("P,ne,overlap,bits", [
+    (8, (4, 4, 4), "rel", 64), (8, (4, 4, 4), "rel", 32), (8, (4, 4, 4), "rel", 16),
+    (7, (5, 4, 4), "rel", 16), (32, (3, 3, 3), "max", 32), (32, (3, 3, 3), "max", 64),
+])
+def test_footprint_covers_a_served_solve(P, ne, overlap, bits):
+    torch = torch_cuda()
+    announce("footprint", P, ne, overlap, bits)
+    prm = dict(ne=ne, P=P, overlap=overlap, precond_bits=bits)
+    fp = sipg.footprint(**prm)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        s = sipg.Solver(stream=stream, **prm)
+        s.set_option(0, 1)                            # graph-captured preconditioner
+        assert s.device_bytes() == fp
+        k, phi, amp = fourier_modes(3, 3)
+        b = zeros(s.ndof())
+        s.rhs_fourier(k, phi, amp, b)
+        x = zeros(s.ndof())
+        it, rr = s.pcg_solve(x, b, rtol=1e-10, maxit=100)
+        assert rr <= 1e-10
+        assert s.device_bytes() == fp, (s.device_bytes(), fp)
+        s.close()
+    stream.synchronize()
+
+
+def test_ndof_per_level():
+    torch_cuda()
+    with sipg.Solver(ne=(4, 3, 5), P=7, overlap="rel") as s:
+        for l in range(s.nlevels):
+            n = (s.level_info(l)["order"] + 1) ** 3 * 60
+            assert s.ndof(l) == n
+        assert s.ndof(-1) == 60 * 8 ** 3
+        with pytest.raises(sipg.SipgError):
+            s.ndof(s.nlevels)

@@ -207,7 +207,7 @@ def test_solvers_match_oracle(ne, length, P, overlap, solver):
         xo, ito, rro, _ = oracle.fcg_solve(b, h, tol=1e-10, maxit=60)
     assert it == ito
     assert rr <= 1e-10
-    assert rel(x - x.mean(), xo - xo.mean()) <= 1e-10
+    assert rel(x, xo) <= 1e-10
     hist = s.residual_history()
     assert len(hist) == it + 1
     s.close()
@@ -230,7 +230,7 @@ def test_fp32_preconditioner(ne, length, P, overlap):
     h, s, b, x, it, rr = _solve_case(ne, length, P, overlap, "fcg", precond_bits=32)
     assert rr <= 1e-10
     xs = oracle.exact_solution(b, h)
-    assert rel(x - x.mean(), xs) <= 1e-8
+    assert rel(x, xs) <= 1e-8
     s.close()
 
 
@@ -278,5 +278,5 @@ def test_order32_vcycle_and_fcg():
     it, rr = s.pcg_solve(x, dev(b), rtol=1e-10, maxit=40)
     assert rr <= 1e-10
     xh = host(x)
-    assert rel(xh - xh.mean(), oracle.exact_solution(b, h)) <= 1e-8
+    assert rel(xh, oracle.exact_solution(b, h)) <= 1e-8
     s.close()

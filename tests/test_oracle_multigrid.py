@@ -108,8 +108,34 @@ def test_solvers_converge_to_exact_solution(ne, length, P, overlap, solver):
     else:
         x, it, rr, hist = oracle.fcg_solve(b, h, tol=1e-10, maxit=40)
     assert rr <= 1e-10
-    x = x - x.mean()
+    assert abs(x.mean()) <= 1e-14 * np.linalg.norm(x)
     assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("solver", ["mg", "fcg"])
+def test_solvers_project_a_right_side_with_mean(solver):
+    # Sec. 3.2: the periodic problem is singular (null space: the constants),
+    # so a right side with a nonzero mean has no solution; the solvers return
+    # the minimum-norm least-squares solution A^+ b.  Pinned against lstsq on
+    # the dense Kronecker matrix of a 3 x 3 x 3 mesh at P = 2.
+    ne, length, P = (3, 3, 3), (1.0, 1.0, 1.0), 2
+    h = oracle.Hierarchy(ne, length, P, overlap="min")
+    dx, dy, dz = h.top.discs
+    A = (np.kron(np.diag(dz.M), np.kron(np.diag(dy.M), dx.L))
+         + np.kron(np.diag(dz.M), np.kron(dy.L, np.diag(dx.M)))
+         + np.kron(dz.L, np.kron(np.diag(dy.M), np.diag(dx.M))))
+    rng = np.random.default_rng(11)
+    bg = rng.standard_normal(A.shape[0]) + 3.0          # mean about 3
+    u_ls = np.linalg.lstsq(A, bg, rcond=None)[0]
+    b = oracle.to_element(bg.reshape(dz.N, dy.N, dx.N), ne, P + 1)
+    if solver == "mg":
+        x, it, rr, _ = oracle.mg_solve(b, h, tol=1e-12, maxcyc=60)
+    else:
+        x, it, rr, _ = oracle.fcg_solve(b, h, tol=1e-12, maxit=60)
+    assert rr <= 1e-12
+    xg = oracle.to_global(x, ne, P + 1).reshape(-1)
+    assert np.linalg.norm(xg - u_ls) <= 1e-9 * np.linalg.norm(u_ls)
+    assert abs(xg.mean()) <= 1e-14 * np.linalg.norm(xg)
 
 
 def test_config1_iteration_counts():

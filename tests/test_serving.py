@@ -96,7 +96,7 @@ def test_served_solution_matches_oracle():
         u = zeros(st["ndof"])
         srv.fetch(rid, u)
     x = host(u)
-    assert rel(x - x.mean(), oracle.exact_solution(b, h)) <= 1e-8
+    assert rel(x, oracle.exact_solution(b, h)) <= 1e-8
 
 
 @pytest.mark.gpu
@@ -169,6 +169,39 @@ def test_batched_operator_launches_keep_results(bits):
                 xs, it = alone[i]
                 assert st["iters"] == it
                 assert np.array_equal(host(u), xs), (fuse, i)
+
+
+def test_submit_rejects_a_request_larger_than_the_budget():
+    # a request whose footprint exceeds the whole budget could never be
+    # admitted and would block the FIFO: it is refused at submit
+    prm = dict(ne=(8, 8, 8), P=8, overlap="min")
+    need = sipg.footprint(**prm) + 2 * 8 ** 3 * 9 ** 3 * 8
+    with sipg.Server(need - 1, 4) as srv:
+        k, phi, amp = fourier_modes(0, 3)
+        with pytest.raises(sipg.SipgError) as ei:
+            srv.submit(k, phi, amp, **prm)
+        assert ei.value.code == sipg.ENOMEM
+    with sipg.Server(need, 4) as srv:
+        srv.submit(*fourier_modes(0, 3), **prm)
+
+
+@pytest.mark.gpu
+def test_oversized_request_does_not_block_the_queue():
+    from _gpu import announce, torch_cuda
+    torch_cuda()
+    announce("serving oversized")
+    small = dict(ne=(4, 4, 4), P=4, overlap="min")
+    budget = sipg.footprint(**small) + 2 * 8000 * 8
+    with sipg.Server(budget, max_active=4) as srv:
+        with pytest.raises(sipg.SipgError) as ei:
+            srv.submit(*fourier_modes(1, 3), ne=(8, 8, 8), P=8, overlap="min")
+        assert ei.value.code == sipg.ENOMEM
+        rid = srv.submit(*fourier_modes(2, 3), **small)
+        for _ in range(100000):
+            a, q, _c = srv.progress(wait_ms=50)
+            if a == 0 and q == 0:
+                break
+        assert srv.status(rid)["state"] == sipg.REQ_DONE
 
 
 def test_server_options_validated():
