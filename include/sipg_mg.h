@@ -145,6 +145,19 @@ int sipg_residual(sipg_ctx *c, int level, const double *u, const double *f, doub
  * problem solved by fast diagonalization.  In place on u. */
 int sipg_schwarz(sipg_ctx *c, int level, const double *r, double *u);
 
+/* sipg_schwarz for callers that cannot allocate device memory at call time
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same computation and kernels, async, in place on u, with
+ * the per-subdomain corrections kept in a fixed device array of the library
+ * (96 MiB per device, held until the process ends) instead of the context's
+ * work space, and no allocation of any kind (sipg_schwarz allocates the FP64
+ * work space on its first call on a context with precond_bits 32 or 16).
+ * SIPG_EINVAL when level l needs more than 96 MiB of corrections (E times
+ * m_x m_y m_z doubles).  The array is shared by every call on a device:
+ * calls that overlap on one device (several streams or threads) race and
+ * must be serialized by the caller. */
+int sipg_schwarz_noalloc(sipg_ctx *c, int level, const double *r, double *u);
+
 /* nsteps smoothing steps on level l >= 1, in place on u, async: each step is
  * r = f - A_l u followed by sipg_schwarz. */
 int sipg_smooth(sipg_ctx *c, int level, double *u, const double *f, int nsteps);

@@ -140,6 +140,16 @@ template <typename TI>
 hipError_t launch_coarse(const CoarseLaunch &a, const TI *f0, double *u0, bool subtract_mean,
                          hipStream_t st);
 
+// ---- fixed scratch of the allocation-free Schwarz step (scratch_noalloc.hip)
+// Bytes of the file-scope device array (per device, held until the process
+// ends).
+constexpr size_t kNoallocScratchBytes = (size_t)96 << 20;
+// Looks up the array's address on `device` (once per device; makes the device
+// current for the lookup and restores the previous one).
+hipError_t noalloc_scratch_init(int device);
+// The address found by noalloc_scratch_init (nullptr before it).
+void *noalloc_scratch(int device);
+
 // ---- vector kernels (kernels_vec.hip) -------------------------------------
 constexpr int kDotBlocks = 1024;
 // partial[b] = sum over block b of x[i]*y[i] (fixed partition, deterministic)

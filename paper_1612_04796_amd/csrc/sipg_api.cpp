@@ -83,6 +83,7 @@ struct Arena {
 struct sipg_ctx {
   sipg::HierarchyHost H;
   hipStream_t stream = nullptr;
+  int device = 0;                       // device current at sipg_setup
   int L = 0;
   sipg::Mesh mesh{};
   std::vector<void *> allocs;
@@ -545,11 +546,12 @@ const sipg::MfmaTabs *mfma_of(const sipg_ctx *c, const LevelTabs<T> &t) {
   return std::is_same<T, float>::value && c->H.prm.precond_bits == 16 && t.has_mfma ? &t.mfma : nullptr;
 }
 
+// C: the corrections' scratch (default: the context's work space)
 template <typename T>
-void op_schwarz(sipg_ctx *c, int l, const T *r, const T *u_in, T *u_out) {
+void op_schwarz(sipg_ctx *c, int l, const T *r, const T *u_in, T *u_out, T *C = nullptr) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
-  sipg::SchwarzLaunch<T> a{c->mesh, t.n, t.schwarz, r, work_of<T>(c).C, t.ilam, u_in, u_out, mfma_of(c, t),
-                          t.schwarz_spb};
+  sipg::SchwarzLaunch<T> a{c->mesh, t.n, t.schwarz, r, C ? C : work_of<T>(c).C, t.ilam, u_in, u_out,
+                          mfma_of(c, t), t.schwarz_spb};
   int k = trace_begin<T>(c, SIPG_KERNEL_SCHWARZ_SOLVE, l);
   check(sipg::launch_schwarz_local<T>(a, c->stream), "schwarz");
   trace_end(c, k);
@@ -1133,6 +1135,9 @@ int sipg_setup(const sipg_params *p, void *hip_stream, sipg_ctx **out) {
   int rc = guarded([&]() {
     sipg::build_hierarchy(*p, c->H);
     c->stream = static_cast<hipStream_t>(hip_stream);
+    check(hipGetDevice(&c->device), "hipGetDevice");
+    // address of the fixed scratch of sipg_schwarz_noalloc on this device
+    check(sipg::noalloc_scratch_init(c->device), "scratch address");
     c->L = (int)c->H.lev.size() - 1;
     for (int d = 0; d < 3; ++d) c->mesh.ne[d] = p->ne[d];
     c->mesh.E = p->ne[0] * p->ne[1] * p->ne[2];
@@ -1288,6 +1293,25 @@ int sipg_schwarz(sipg_ctx *c, int level, const double *r, double *u) {
   return guarded([&]() {
     ensure_work<double>(c);
     op_schwarz<double>(c, l, r, u, u);
+    return (int)SIPG_OK;
+  });
+}
+
+int sipg_schwarz_noalloc(sipg_ctx *c, int level, const double *r, double *u) {
+  if (!c || !r || !u) return fail(SIPG_EINVAL, "null argument");
+  if (r == u) return fail(SIPG_EINVAL, "r and u must not alias");
+  const int l = resolve_level(c, level);
+  if (l < 1) return fail(SIPG_EINVAL, "Schwarz smoothing needs level >= 1");
+  const sipg::SchwarzTabs<double> &t = c->t64[l].schwarz;
+  const size_t need = (size_t)c->mesh.E * t.m[0] * t.m[1] * t.m[2] * sizeof(double);
+  if (need > sipg::kNoallocScratchBytes)
+    return fail(SIPG_EINVAL, "sipg_schwarz_noalloc: level " + std::to_string(l) + " needs " + std::to_string(need) +
+                                 " bytes of correction scratch, more than its fixed " +
+                                 std::to_string(sipg::kNoallocScratchBytes) + " bytes");
+  double *C = static_cast<double *>(sipg::noalloc_scratch(c->device));
+  if (!C) return fail(SIPG_EHIP, "sipg_schwarz_noalloc: scratch address unknown on this device");
+  return guarded([&]() {
+    op_schwarz<double>(c, l, r, u, u, C);
     return (int)SIPG_OK;
   });
 }

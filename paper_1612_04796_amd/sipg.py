@@ -28,6 +28,7 @@ EXPORTS = (
     "sipg_precond", "sipg_mg_solve", "sipg_pcg_solve", "sipg_residual_history",
     "sipg_last_error", "sipg_host_table", "sipg_time_kernel", "sipg_autotune", "sipg_tuning",
     "sipg_set_option", "sipg_traced_kernel_ms", "sipg_ndof", "sipg_rhs_mean", "sipg_device_bytes",
+    "sipg_schwarz_noalloc",
     "sipg_server_create", "sipg_server_submit", "sipg_server_progress", "sipg_server_status",
     "sipg_server_fetch", "sipg_server_destroy", "sipg_server_set_option", "sipg_server_stats",
 )
@@ -87,6 +88,7 @@ def lib():
             "sipg_apply_A": (c_int, [vp, c_int, vp, vp]),
             "sipg_residual": (c_int, [vp, c_int, vp, vp, vp]),
             "sipg_schwarz": (c_int, [vp, c_int, vp, vp]),
+            "sipg_schwarz_noalloc": (c_int, [vp, c_int, vp, vp]),
             "sipg_smooth": (c_int, [vp, c_int, vp, vp, c_int]),
             "sipg_restrict": (c_int, [vp, c_int, vp, vp]),
             "sipg_prolong_add": (c_int, [vp, c_int, vp, vp]),
@@ -262,6 +264,10 @@ class Solver:
 
     def schwarz(self, r, u, level=-1):
         _check(lib().sipg_schwarz(self._h, level, self._vec(r, level, "r"), self._vec(u, level, "u")))
+        return u
+
+    def schwarz_noalloc(self, r, u, level=-1):
+        _check(lib().sipg_schwarz_noalloc(self._h, level, self._vec(r, level, "r"), self._vec(u, level, "u")))
         return u
 
     def smooth(self, u, f, nsteps=1, level=-1):
