@@ -262,13 +262,18 @@ typedef enum {
   SIPG_OPT_GRAPH = 0,       /* value 1: capture the flexible-CG preconditioner V-cycle into a
                                HIP graph on its first use and replay it afterwards (needs a
                                non-NULL stream at sipg_setup; kernel nodes only) */
-  SIPG_OPT_TRACE_KERNEL = 1 /* value k in SIPG_KERNEL_RESIDUAL..SIPG_KERNEL_PROLONG: from now
+  SIPG_OPT_TRACE_KERNEL = 1,/* value k in SIPG_KERNEL_RESIDUAL..SIPG_KERNEL_PROLONG: from now
                                on every launch of that kernel on the top level in FP64
                                (inside sipg_mg_solve, sipg_vcycle, ...) is bracketed by a
                                pair of HIP events on the context's stream (at most 1024
                                launches are kept; later ones are not timed); -1 stops.
                                Setting it drops the launches recorded so far.  Allocates
                                the events when first set (not inside the solves). */
+  SIPG_OPT_WIDE_PLANES = 2  /* value 1..16: the local solves of subdomains too large for one
+                               workgroup's LDS process that many 2D planes per wave (matrix-core
+                               kernels) or per workgroup (vector plane kernels); 0 (default):
+                               chosen from the mesh size.  Results do not depend on it (a launch
+                               shape only).  Drops a captured preconditioner graph. */
 } sipg_option;
 int sipg_set_option(sipg_ctx *c, int option, int value);
 /* Launch durations recorded under SIPG_OPT_TRACE_KERNEL: waits for the last

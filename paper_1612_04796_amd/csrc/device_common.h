@@ -104,6 +104,12 @@ struct SchwarzTabs {
   // 1 / (lam_x + lam_y + lam_z) with each direction's modes in even-odd order
   const T *EO[3];
   const T *ilam_eo;
+  // matrix-core form of the forward (S, [0]) and weighted backward
+  // ((W S)^T, [1]) tables of subdomains wider than the LDS kernels take:
+  // fragment-major, entry (ot*KS + ks)*64 + lane = F[4 ks + lane/16][16 ot +
+  // lane%16] with F = S or (W S)^T, zero beyond m, KS = ceil(m/4); null when
+  // the level has none
+  const T *frag[2][3];
 };
 
 template <typename T>

@@ -104,6 +104,9 @@ struct SchwarzLaunch {
   const MfmaTabs *mfma = nullptr;  // FP32 levels: local solves in FP16 on the matrix cores
   int spb = 0;                     // subdomains per workgroup of the compile-time-shape kernel
                                    // (0: its default)
+  int wide_planes = 0;             // subdomains wider than the LDS kernels: planes per wave
+                                   // (matrix-core kernels) or per workgroup (vector plane
+                                   // kernels); 0: automatic
 };
 // Largest subdomains-per-workgroup of the compile-time-shape local-solve
 // kernel for (n, m) (0 when there is none).
@@ -121,6 +124,13 @@ bool schwarz_fits_lds(const int m[3], size_t elem_bytes);
 bool schwarz_is_wide(const int m[3]);
 template <typename T>
 hipError_t launch_schwarz_wide(const SchwarzLaunch<T> &a, hipStream_t st);
+// the wide local solves on the matrix cores (kernels_wide_mfma.hip): for
+// subdomains up to 64 nodes per direction with SchwarzTabs::frag set;
+// hipErrorNotSupported (nothing launched) otherwise
+bool wide_mfma_supported(const int m[3]);
+int wide_mfma_frag_count(int m);  // values of one fragment-major table
+template <typename T>
+hipError_t launch_schwarz_wide_mfma(const SchwarzLaunch<T> &a, hipStream_t st);
 
 // Level-0 pseudo-inverse by global fast diagonalization; see kernels_coarse.hip.
 struct CoarseLaunch {

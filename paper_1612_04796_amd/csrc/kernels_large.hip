@@ -396,7 +396,8 @@ hipError_t launch_wide_tl(const SchwarzLaunch<T> &a, size_t s13, size_t s2, hipS
   // 23 x 51 x 51 subdomains: 1 plane 15.9 ms, 3 planes 15.3 ms, 6-16 planes
   // slower)
   auto ppb_for = [&](int planes) { return std::max(1, std::min(4, a.mesh.E * planes / 8192)); };
-  const int pz = ppb_for(m[2]), py = ppb_for(m[1]);
+  const int pz = a.wide_planes > 0 ? a.wide_planes : ppb_for(m[2]);
+  const int py = a.wide_planes > 0 ? a.wide_planes : ppb_for(m[1]);
   wide_slab1<T, TL><<<a.mesh.E * ((m[2] + pz - 1) / pz), 512, s13, st>>>(a.mesh, a.n, a.tabs, a.r, a.C, pz);
   wide_slab2<T, TL><<<a.mesh.E * ((m[1] + py - 1) / py), 512, s2, st>>>(a.mesh.E, a.tabs, a.ilam, a.C, py);
   wide_slab3<T, TL><<<a.mesh.E * ((m[2] + pz - 1) / pz), 512, s13, st>>>(a.mesh.E, a.tabs, a.C, pz);
@@ -405,6 +406,10 @@ hipError_t launch_wide_tl(const SchwarzLaunch<T> &a, size_t s13, size_t s2, hipS
 
 template <typename T>
 hipError_t launch_schwarz_wide(const SchwarzLaunch<T> &a, hipStream_t st) {
+  {
+    const hipError_t e = launch_schwarz_wide_mfma<T>(a, st);
+    if (e != hipErrorNotSupported) return e;
+  }
   const int *m = a.tabs.m;
   const size_t e = sizeof(T);
   const size_t p13 = (size_t)m[0] * m[1] * e, p2 = (size_t)m[0] * m[2] * e;

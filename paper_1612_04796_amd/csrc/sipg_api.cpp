@@ -107,6 +107,7 @@ struct sipg_ctx {
   const double *xi_top = nullptr, *mass_top[3] = {nullptr, nullptr, nullptr};
   std::vector<double> hist;
   size_t bytes = 0;
+  int wide_planes = 0;                  // SIPG_OPT_WIDE_PLANES (0: automatic)
   bool use_graph = false;               // replay the preconditioner from a captured graph
   hipGraphExec_t precond_graph = nullptr;
   bool graph_failed = false;
@@ -318,7 +319,25 @@ struct TabOff {
   size_t mf[3], mb[3], mil;
   double kout;
   bool mfma;
+  size_t frag[2][3];
+  bool wide_mfma;
 };
+
+// Fragment-major matrix-core table of one direction (see SchwarzTabs::frag):
+// F[a][o] = S[a][o] (forward) or w[o] S[o][a] (weighted backward).
+std::vector<double> wide_frag_table(const sipg::Dir1D &D, bool backward) {
+  const int m = D.m, OT = (m + 15) / 16, KS = (m + 3) / 4;
+  std::vector<double> t((size_t)sipg::wide_mfma_frag_count(m), 0.0);
+  for (int ot = 0; ot < OT; ++ot)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int a = 4 * ks + lane / 16, o = 16 * ot + lane % 16;
+        if (a < m && o < m)
+          t[((size_t)ot * KS + ks) * 64 + lane] =
+              backward ? D.wsub[o] * D.S[(size_t)o * m + a] : D.S[(size_t)a * m + o];
+      }
+  return t;
+}
 
 // Every device table of a context, staged on the host (built by
 // build_table_arena, uploaded by upload_tables; its size is part of
@@ -376,6 +395,10 @@ TableArena build_table_arena(const sipg::HierarchyHost &H, int64_t E) {
               il[((size_t)cz * Y.m + by) * X.m + ax] = 1.0 / (X.lam_eo[ax] + Y.lam_eo[by] + Z.lam_eo[cz]);
         off[l].ilam_eo = A.put<T>(il);
         const int m3[3] = {X.m, Y.m, Z.m};
+        off[l].wide_mfma = !sipg::schwarz_fits_lds(m3, sizeof(double)) && sipg::wide_mfma_supported(m3);
+        if (off[l].wide_mfma)
+          for (int k = 0; k < 2; ++k)
+            for (int d = 0; d < 3; ++d) off[l].frag[k][d] = A.put<T>(wide_frag_table(lv.dir[d], k == 1));
         off[l].mfma = std::is_same<T, float>::value && sipg::mfma_fdm_supported(lv.n, m3) &&
                       E * lv.n * lv.n * lv.n < ((int64_t)1 << 30);
         if (off[l].mfma) {
@@ -449,6 +472,10 @@ void upload_tables(sipg_ctx *c) {
         t.J = reinterpret_cast<const T *>(c->tab_dev + off[l].J);
         t.ilam = reinterpret_cast<const T *>(c->tab_dev + off[l].ilam);
         t.schwarz.ilam_eo = reinterpret_cast<const T *>(c->tab_dev + off[l].ilam_eo);
+        for (int k = 0; k < 2; ++k)
+          for (int d = 0; d < 3; ++d)
+            t.schwarz.frag[k][d] =
+                off[l].wide_mfma ? reinterpret_cast<const T *>(c->tab_dev + off[l].frag[k][d]) : nullptr;
         t.has_mfma = off[l].mfma;
         if (t.has_mfma) {
           for (int d = 0; d < 3; ++d) {
@@ -551,7 +578,7 @@ template <typename T>
 void op_schwarz(sipg_ctx *c, int l, const T *r, const T *u_in, T *u_out, T *C = nullptr) {
   const LevelTabs<T> &t = tabs_of<T>(c, l);
   sipg::SchwarzLaunch<T> a{c->mesh, t.n, t.schwarz, r, C ? C : work_of<T>(c).C, t.ilam, u_in, u_out,
-                          mfma_of(c, t), t.schwarz_spb};
+                          mfma_of(c, t), t.schwarz_spb, c->wide_planes};
   int k = trace_begin<T>(c, SIPG_KERNEL_SCHWARZ_SOLVE, l);
   check(sipg::launch_schwarz_local<T>(a, c->stream), "schwarz");
   trace_end(c, k);
@@ -1488,6 +1515,15 @@ int sipg_set_option(sipg_ctx *c, int option, int value) {
   if (!c) return fail(SIPG_EINVAL, "null context");
   if (option == SIPG_OPT_GRAPH) {
     c->use_graph = value != 0;
+    return SIPG_OK;
+  }
+  if (option == SIPG_OPT_WIDE_PLANES) {
+    if (value < 0 || value > 16) return fail(SIPG_EINVAL, "wide planes must be in 0..16");
+    c->wide_planes = value;
+    if (c->precond_graph) {  // captured with the previous launch shapes
+      (void)hipGraphExecDestroy(c->precond_graph);
+      c->precond_graph = nullptr;
+    }
     return SIPG_OK;
   }
   if (option != SIPG_OPT_TRACE_KERNEL) return fail(SIPG_EINVAL, "unknown option");

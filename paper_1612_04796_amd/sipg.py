@@ -336,8 +336,14 @@ class Solver:
 
     def set_option(self, option, value):
         """SIPG_OPT_GRAPH (0): replay the flexible-CG preconditioner from a
-        captured HIP graph (needs a non-default stream)."""
+        captured HIP graph (needs a non-default stream); SIPG_OPT_WIDE_PLANES
+        (2): planes per wave / workgroup of the wide local solves (0 = auto)."""
         _check(lib().sipg_set_option(self._h, int(option), int(value)))
+
+    def wide_planes(self, k):
+        """Planes per wave (matrix-core) or workgroup (vector) of the local
+        solves of subdomains too large for the LDS kernels; 0 = automatic."""
+        self.set_option(2, k)
 
     def trace_kernel(self, kernel):
         """Bracket every later top-level FP64 launch of `kernel` (a KERNELS
