@@ -13,7 +13,8 @@ float64, with dense 1D matrices and Kronecker-structured 3D operators, and no
 blocking or fusion beyond what the method's definitions state.
 
 Modules
-  basis      GLL nodes, weights, Lagrange derivative and interpolation (Sec. 2)
+  basis      GLL and GL nodes and weights, Lagrange derivative, end values and
+             interpolation (Sec. 2)
   sipg       1D mass/stiffness, 3D Kronecker operator eq. (A), and an
              independent element+face quadrature of the interior penalty form
   schwarz    overlap layers, restricted 1D eigenpairs, hat weights and the
@@ -29,7 +30,7 @@ level sequence for P not a power of two, right-hand-side projection, flexible
 CG details).
 """
 
-from .basis import gll, diff_matrix, interp_matrix, lagrange_eval
+from .basis import gll, gl, rule, end_values, diff_matrix, interp_matrix, lagrange_eval
 from .sipg import Discretization1D, apply_A, to_global, to_element, assemble_ip_dense
 from .schwarz import overlap_layers, SubdomainTables, hat_weights, schwarz_correction
 from .multigrid import (Hierarchy, level_orders, vcycle, smoother, mg_solve, fcg_solve,
@@ -38,7 +39,7 @@ from .problem import (fourier_rhs, manufactured, manufactured_rhs, exact_solutio
                       residual_norm, rate_metrics, node_coordinates)
 
 __all__ = [
-    "gll", "diff_matrix", "interp_matrix", "lagrange_eval",
+    "gll", "gl", "rule", "end_values", "diff_matrix", "interp_matrix", "lagrange_eval",
     "Discretization1D", "apply_A", "to_global", "to_element", "assemble_ip_dense",
     "overlap_layers", "SubdomainTables", "hat_weights", "schwarz_correction",
     "Hierarchy", "level_orders", "apply_level", "schwarz_step_correction",

@@ -1,5 +1,6 @@
-"""1D nodal building blocks (paper Sec. 2, eq. (u_h)): GLL points and weights,
-the Lagrange derivative matrix, and interpolation between two GLL node sets.
+"""1D nodal building blocks (paper Sec. 2, eq. (u_h)): Gauss-Lobatto-Legendre
+(GLL) and Gauss-Legendre (GL) points and weights, the Lagrange derivative
+matrix, and interpolation between two node sets.
 
 Test infrastructure only (see the package docstring).
 
@@ -42,6 +43,32 @@ def gll(p):
     return xi, w
 
 
+def gl(p):
+    """Gauss-Legendre nodes xi_0 < ... < xi_p on (-1, 1) and weights: the
+    p + 1 zeros of P_{p+1}, w_i = 2 / ((1 - xi_i^2) P_{p+1}'(xi_i)^2); the
+    rule integrates polynomials of degree up to 2p + 1 exactly.  Neither end
+    point is a node, so element traces are combinations of all nodal values
+    (Sec. 2, the GL basis of Table 1)."""
+    if p < 0:
+        raise ValueError("order p must be >= 0")
+    c = _legendre_coeffs(p + 1)
+    dc = npleg.legder(c)
+    x = np.sort(npleg.legroots(c).real)
+    for _ in range(4):  # Newton polish on P_{p+1}
+        x = x - npleg.legval(x, c) / npleg.legval(x, dc)
+    w = 2.0 / ((1.0 - x ** 2) * npleg.legval(x, dc) ** 2)
+    return x, w
+
+
+def rule(basis, p):
+    """(nodes, weights) of the nodal basis 'gll' or 'gl' of order p."""
+    if basis == "gll":
+        return gll(p)
+    if basis == "gl":
+        return gl(p)
+    raise ValueError(f"unknown basis {basis!r}")
+
+
 def _vander_and_deriv(x, p):
     V = npleg.legvander(x, p)
     Vd = np.empty_like(V)
@@ -59,6 +86,18 @@ def diff_matrix(xi):
     p = len(xi) - 1
     V, Vd = _vander_and_deriv(xi, p)
     return np.linalg.solve(V.T, Vd.T).T
+
+
+def end_values(xi):
+    """Values phi_j(-1), phi_j(+1) and derivatives phi_j'(-1), phi_j'(+1) of
+    the Lagrange basis on the nodes xi, through the Legendre Vandermonde
+    route: returns (phi_m, phi_p, dphi_m, dphi_p)."""
+    p = len(xi) - 1
+    V = npleg.legvander(np.asarray(xi, dtype=float), p)
+    E, Ed = _vander_and_deriv(np.array([-1.0, 1.0]), p)
+    phi = np.linalg.solve(V.T, E.T).T
+    dphi = np.linalg.solve(V.T, Ed.T).T
+    return phi[0], phi[1], dphi[0], dphi[1]
 
 
 def interp_matrix(xi_from, x_to):

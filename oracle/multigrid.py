@@ -48,13 +48,16 @@ def level_orders(P):
 
 
 class Level:
-    def __init__(self, p, ne, length, cmu, overlap, omega, smoothed):
+    def __init__(self, p, ne, length, cmu, overlap, omega, smoothed, basis="gll", overlap_floor=0):
         self.p = p
         self.n = p + 1
-        self.discs = tuple(Discretization1D(p, ne[d], length[d], cmu) for d in range(3))
+        self.discs = tuple(Discretization1D(p, ne[d], length[d], cmu, basis=basis) for d in range(3))
         h = tuple(length[d] / ne[d] for d in range(3))
-        self.no = tuple(overlap_layers(self.discs[d].xi, overlap_delta(overlap, omega, h, d))
+        floor = overlap_floor if overlap != "min" else 0
+        self.no = tuple(overlap_layers(self.discs[d].xi, overlap_delta(overlap, omega, h, d), basis, floor)
                         for d in range(3))
+        if overlap == "min":  # one node layer from each neighbour, for either basis
+            self.no = (1, 1, 1)
         self.tabs = None
         if smoothed:
             self.tabs = tuple(SubdomainTables(self.discs[d], self.no[d]) for d in range(3))
@@ -70,16 +73,19 @@ class Hierarchy:
     P: top order; cmu: penalty factor; overlap in {'min', 'rel', 'max'} with
     width omega; (ns_pre, ns_post) smoothing steps on the top level, scaled by
     growth^(L - l) on level l (growth = 3 gives the variable V-cycle of
-    Table 2).
+    Table 2); basis 'gll' or 'gl' (Table 1); overlap_floor: lower bound of
+    the overlap layers on every level (Table 1 rows 13-14 use 1).
     """
 
     def __init__(self, ne, length, P, cmu=1.0, overlap="min", omega=0.08,
-                 ns_pre=1, ns_post=1, growth=1):
+                 ns_pre=1, ns_post=1, growth=1, basis="gll", overlap_floor=0):
         self.ne = tuple(int(v) for v in ne)
         self.length = tuple(float(v) for v in length)
+        self.basis = basis
         self.orders = level_orders(P)
         self.L = len(self.orders) - 1
-        self.levels = [Level(p, self.ne, self.length, cmu, overlap, omega, smoothed=(l > 0))
+        self.levels = [Level(p, self.ne, self.length, cmu, overlap, omega, smoothed=(l > 0), basis=basis,
+                             overlap_floor=overlap_floor)
                        for l, p in enumerate(self.orders)]
         self.ns1 = [ns_pre * growth ** (self.L - l) for l in range(self.L + 1)]
         self.ns2 = [ns_post * growth ** (self.L - l) for l in range(self.L + 1)]

@@ -13,8 +13,9 @@ Readings where the paper is silent:
 
 * N_O from a geometric overlap width delta_O: the number of neighbour nodes j
   whose distance from the shared face, (1 + xi_j)/2 in units of the element
-  width, is at most delta_O / h (with a 1e-12 tolerance).  This reproduces
-  every N_O column of Table 1 for the GLL rows.
+  width, is at most delta_O / h for GLL nodes and below it for GL nodes
+  (with a 1e-12 tolerance), optionally bounded below (Table 1 rows 13-14).
+  This reproduces every N_O column of Table 1, GLL and GL rows.
 * delta_O / h per direction: 0 for the minimal overlap (N_O = 1), omega for
   the relative overlap, and min(omega * max_k h_k, h_d) / h_d for the
   "max" overlap of Table 2.
@@ -49,16 +50,30 @@ def overlap_delta(mode, omega, h, d):
     raise ValueError(f"unknown overlap mode {mode!r}")
 
 
-def overlap_layers(xi, delta_rel):
-    """N_O: neighbour nodes within delta_O of the shared face (inclusive)."""
-    return int(np.count_nonzero((1.0 + np.asarray(xi)) / 2.0 <= delta_rel + 1e-12))
+def overlap_layers(xi, delta_rel, basis="gll", floor=0):
+    """N_O: neighbour nodes within delta_O of the shared face.  GLL counts
+    the nodes at distance <= delta_O (a node exactly at the distance is
+    included), GL those at distance < delta_O (excluded); both with a 1e-12
+    tolerance.  Table 1 fixes the tie: at delta_O = 0.5 dx the middle node of
+    an odd node count is counted for GLL (row 5: 2, 3, 5, 9, 17 layers for
+    P = 2 .. 32) and not for GL (row 11: 1, 2, 4, 8, 16).  With the GL basis
+    the count can be 0 (row 9 at P = 2); `floor` is the lower bound of rows
+    13-14 (N_O >= 1)."""
+    d = (1.0 + np.asarray(xi)) / 2.0
+    if basis == "gll":
+        no = int(np.count_nonzero(d <= delta_rel + 1e-12))
+    else:
+        no = int(np.count_nonzero(d < delta_rel - 1e-12))
+    return max(no, int(floor))
 
 
 def hat_weights(xi, no):
-    """1D weights of the m = n + 2 N_O subdomain nodes (left halo, core, right halo)."""
+    """1D weights of the m = n + 2 N_O subdomain nodes (left halo, core,
+    right halo).  N_O = 0 (possible with GL nodes) leaves the element alone,
+    with weight 1 on every node."""
     n = len(xi)
     p = n - 1
-    xi_h = np.concatenate((xi[n - no:] - 2.0, xi, xi[:no] + 2.0))
+    xi_h = np.concatenate((xi[n - no:] - 2.0, xi, xi[:no] + 2.0)) if no > 0 else np.asarray(xi, dtype=float)
     delta = min(1.0, 1.0 + xi[no]) if no <= p else 1.0
     t = np.clip((1.0 + delta - np.abs(xi_h)) / (2.0 * delta), 0.0, 1.0)
     return 10 * t ** 3 - 15 * t ** 4 + 6 * t ** 5
@@ -72,8 +87,8 @@ class SubdomainTables:
     element e (periodic wrap)."""
 
     def __init__(self, disc, no):
-        if not 1 <= no <= disc.n:
-            raise ValueError("overlap layers must be in 1..n")
+        if not 0 <= no <= disc.n:
+            raise ValueError("overlap layers must be in 0..n")
         self.disc, self.no = disc, no
         self.n = disc.n
         self.m = disc.n + 2 * no

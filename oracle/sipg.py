@@ -11,9 +11,12 @@ symmetric interior penalty form that the paper cites for it (Arnold et al.):
               - int_Gamma ( {grad v} . [[u]] + [[v]] . {grad u} )
               + int_Gamma mu [[v]] . [[u]]
 
-with the GLL quadrature of the nodal basis.  This yields the properties the
-paper states after eq. (A): M diagonal positive, L symmetric positive
-semi-definite and block tridiagonal (block cyclic on the periodic mesh).
+with the quadrature rule of the nodal basis (GLL or GL, Sec. 2 and Table 1).
+This yields the properties the paper states after eq. (A): M diagonal
+positive, L symmetric positive semi-definite and block tridiagonal (block
+cyclic on the periodic mesh).  For the GL basis the element traces and
+normal derivatives at a face are combinations of all nodes of the element
+line (the end points are not nodes), so the face coupling blocks are full.
 
 Reading of the penalty.  The paper sets mu = 2 mu_min with
 mu_min,x = P(P+1)/dx and calls mu_min the stability threshold; for the
@@ -29,29 +32,34 @@ index (ez*n + k, ey*n + j, ex*n + i).
 
 import numpy as np
 
-from .basis import gll, diff_matrix, lagrange_eval
+from .basis import rule, diff_matrix, end_values, lagrange_eval
 
 
 class Discretization1D:
     """1D mass and SIPG stiffness of one direction on the periodic mesh of
-    ``ne`` equal elements of width h = length/ne, order p (eq. (A) factors).
+    ``ne`` equal elements of width h = length/ne, order p (eq. (A) factors),
+    nodal basis 'gll' (the default) or 'gl'.
 
-    Attributes: xi, w (GLL rule), D (derivative matrix), h, mu, n = p+1,
-    N = ne*n, M (global diagonal, length N), L (global dense N x N).
+    Attributes: xi, w (the rule), D (derivative matrix), h, mu, n = p+1,
+    N = ne*n, M (global diagonal, length N), L (global dense N x N).  The
+    mass matrix is diagonal for both bases: the n-point rule integrates the
+    products of two basis functions exactly for GL (degree 2p <= 2p + 1) and
+    is the collocated (lumped) mass for GLL, as in the paper.
     """
 
-    def __init__(self, p, ne, length, cmu=1.0):
+    def __init__(self, p, ne, length, cmu=1.0, basis="gll"):
         if ne < 2:
             raise ValueError("need at least two elements per direction")
         self.p, self.ne, self.length, self.cmu = p, ne, float(length), float(cmu)
+        self.basis = basis
         self.n = p + 1
         self.N = ne * self.n
         self.h = self.length / ne
         self.mu = self.cmu * p * (p + 1) / self.h
-        self.xi, self.w = gll(p)
+        self.xi, self.w = rule(basis, p)
         self.D = diff_matrix(self.xi)
         n, h = self.n, self.h
-        # element mass (diagonal, GLL collocation) and volume stiffness
+        # element mass (diagonal) and volume stiffness
         self.M_elem = 0.5 * h * self.w
         self.K_elem = (2.0 / h) * self.D.T @ np.diag(self.w) @ self.D
         M = np.tile(self.M_elem, ne)
@@ -59,12 +67,18 @@ class Discretization1D:
         for e in range(ne):
             s = slice(e * n, (e + 1) * n)
             L[s, s] += self.K_elem
-        # face between element e (minus side, xi=+1) and e+1 (plus side, xi=-1)
-        jump = np.zeros(2 * n)
-        jump[n - 1] = 1.0   # [[v]] = v^- - v^+   (normal of the minus side is +x)
-        jump[n] = -1.0
-        avg = np.concatenate((0.5 * (2.0 / h) * self.D[n - 1, :],
-                              0.5 * (2.0 / h) * self.D[0, :]))   # {v'}
+        # face between element e (minus side, xi=+1) and e+1 (plus side,
+        # xi=-1); the traces are phi(+1) of e and phi(-1) of e+1 (unit
+        # vectors for GLL, full vectors for GL)
+        if basis == "gll":  # the end points are the first and last nodes
+            phi_m, phi_p = np.eye(n)[0], np.eye(n)[n - 1]
+            dphi_m, dphi_p = self.D[0, :], self.D[n - 1, :]
+        else:
+            phi_m, phi_p, dphi_m, dphi_p = end_values(self.xi)
+        self.trace_m, self.trace_p, self.dtrace_m, self.dtrace_p = phi_m, phi_p, dphi_m, dphi_p
+        jump = np.concatenate((phi_p, -phi_m))   # [[v]] = v^- - v^+ (normal of the minus side is +x)
+        avg = np.concatenate((0.5 * (2.0 / h) * dphi_p,
+                              0.5 * (2.0 / h) * dphi_m))   # {v'}
         F = -np.outer(avg, jump) - np.outer(jump, avg) + self.mu * np.outer(jump, jump)
         for e in range(ne):
             e1 = (e + 1) % ne
@@ -111,8 +125,8 @@ def apply_A(u, discs):
     return to_element(apply_A_global(G, dx, dy, dz), ne, dx.n)
 
 
-def assemble_ip_dense(ne, length, p, cmu=1.0):
-    """Dense 3D system matrix by direct GLL quadrature of the interior penalty
+def assemble_ip_dense(ne, length, p, cmu=1.0, basis="gll"):
+    """Dense 3D system matrix by direct quadrature (the basis' own rule) of the interior penalty
     form, element by element and face by face, in global lexicographic DOF
     numbering.  Independent of the Kronecker form: it evaluates the Lagrange
     polynomials by their product formula and never forms 1D L or M.  For small
@@ -122,7 +136,7 @@ def assemble_ip_dense(ne, length, p, cmu=1.0):
     n = p + 1
     Nx, Ny, Nz = nex * n, ney * n, nez * n
     N = Nx * Ny * Nz
-    xi, w = gll(p)
+    xi, w = rule(basis, p)
     phi, dphi = lagrange_eval(xi, xi)            # at the quadrature points
     phib, dphib = lagrange_eval(xi, [-1.0, 1.0])  # at the element ends
     mu = [cmu * p * (p + 1) / h[d] for d in range(3)]

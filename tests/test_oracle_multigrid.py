@@ -252,3 +252,62 @@ def test_variable_vcycle_smoothing_counts(P):
     # and the counts matter: the reversed assignment 3^l gives another cycle
     rev = {l: counts[h.L + 1 - l] for l in range(1, h.L + 1)}
     assert np.linalg.norm(got - _vcycle_from_steps(u, b, h, rev)) > 1e-6 * np.linalg.norm(want)
+
+
+# ---- the GL basis (Table 1 rows 7-14) --------------------------------------
+GOLDEN_GL = os.path.join(os.path.dirname(__file__), "golden", "table1_gl.txt")
+GL_METHODS = {7: ("mg", "min", 0.0, 0), 8: ("fcg", "min", 0.0, 0), 9: ("mg", "rel", 0.08, 0),
+              10: ("fcg", "rel", 0.08, 0), 11: ("mg", "rel", 0.5, 0), 12: ("fcg", "rel", 0.5, 0),
+              13: ("mg", "rel", 0.09, 1), 14: ("fcg", "rel", 0.09, 1)}
+
+
+def _gl_table1():
+    rows = {}
+    with open(GOLDEN_GL) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                t = line.split()
+                rows[int(t[0])] = [float(v) for v in t[8:12]]
+    return rows
+
+
+def _gl_rate(ne, P, row, ncyc=12):
+    solver, overlap, omega, floor = GL_METHODS[row]
+    h = oracle.Hierarchy((ne,) * 3, (1.0, 1.0, 1.0), P, overlap=overlap, omega=omega, basis="gl",
+                         overlap_floor=floor)
+    k, phi, amp = fourier_modes(0, 3)
+    b = oracle.fourier_rhs(k, phi, amp, h)
+    x0 = uniform_vector(7, b.size)
+    if solver == "mg":
+        _, _, _, hist = oracle.mg_solve(b, h, tol=1e-11, maxcyc=ncyc, x0=x0)
+    else:
+        _, _, _, hist = oracle.fcg_solve(b, h, tol=1e-11, maxit=ncyc, x0=x0)
+    return oracle.rate_metrics(hist)["neg_lg_rho"]
+
+
+@pytest.mark.parametrize("row", [8, 9, 10, 11, 12, 13, 14])
+def test_table1_gl_rates_p4(row):
+    # P = 4 on 6^3 elements (the rates are mesh independent at this size;
+    # the paper's mesh is 32^3): within 0.12 of the paper's cells.  Row 7
+    # is not pinned: its P = 4 cell (0.73) repeats row 9's, while rows 7 and
+    # 13 have the same N_O column at P = 4 and row 13 reads 1.36; the oracle
+    # gives 1.34 for both.
+    paper = _gl_table1()[row][0]
+    got = _gl_rate(6, 4, row)
+    assert abs(got - paper) <= 0.12, (row, got, paper)
+
+
+@pytest.mark.parametrize("P,nes", [(1, (8, 16)), (2, (4, 8)), (3, (8, 12)), (4, (4, 8))])
+def test_discretization_order_gl(P, nes):
+    errs = []
+    for ne in nes:
+        h = oracle.Hierarchy((ne,) * 3, (1.0, 1.0, 1.0), P, basis="gl")
+        b, u = oracle.manufactured(h)
+        uh = oracle.exact_solution(b, h)
+        M = oracle.to_element(
+            np.einsum('k,j,i->kji', *(d.M for d in reversed(h.top.discs))), h.ne, P + 1)
+        e = uh - u
+        e = e - np.dot(M, e) / M.sum()
+        errs.append(math.sqrt(np.dot(M, e * e)))
+    order = math.log(errs[0] / errs[1]) / math.log(nes[1] / nes[0])
+    assert order >= P + 1 - 0.2, (order, errs)

@@ -211,3 +211,48 @@ def test_weights_full_neighbour_overlap_reading():
     assert np.all(w[np.abs(xh) >= 2.0] == 0.0)
     assert np.all(w[np.abs(xh) < 2.0] > 0.0)
     assert np.allclose(w[np.abs(np.abs(xh) - 1.0) < 1e-14], 0.5, atol=1e-14)
+
+
+# ---- GL basis: overlap layers and weights (Table 1 rows 7-14) -------------
+GOLDEN_GL = os.path.join(os.path.dirname(__file__), "golden", "table1_gl.txt")
+
+
+def _gl_rows():
+    rows = {}
+    with open(GOLDEN_GL) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                t = line.split()
+                rows[int(t[0])] = (t[2], [int(v) for v in t[3:8]])
+    return rows
+
+
+GL_OVERLAP = {"rel08": (0.08, 0), "rel50": (0.5, 0), "rel09f": (0.09, 1)}
+
+
+@pytest.mark.parametrize("row", [9, 10, 11, 12, 13, 14])
+def test_gl_overlap_layers_match_table1(row):
+    # strict count (a node exactly at delta_O is not included: the middle
+    # node at 0.5 dx, row 11), possibly zero (row 9 at P = 2), and the lower
+    # bound of rows 13-14
+    spec, want = _gl_rows()[row]
+    omega, floor = GL_OVERLAP[spec]
+    got = [overlap_layers(oracle.gl(p)[0], omega, "gl", floor) for p in (2, 4, 8, 16, 32)]
+    assert got == want
+
+
+@pytest.mark.parametrize("p,no", [(2, 0), (4, 1), (4, 2), (8, 1), (8, 4), (16, 3), (16, 17)])
+def test_gl_weights_partition_of_unity(p, no):
+    xi = oracle.gl(p)[0]
+    n = len(xi)
+    w = oracle.hat_weights(xi, no)
+    assert len(w) == n + 2 * no
+    # own weights plus the left and right neighbours' halo weights on the
+    # element's nodes sum to one
+    tot = w[no:no + n].copy()
+    if no:
+        tot[:no] += w[-no:]           # the left neighbour's right halo
+        tot[n - no:] += w[:no]        # the right neighbour's left halo
+    assert np.allclose(tot, 1.0, atol=1e-14)
+    if no == 0:
+        assert np.all(w == 1.0)
