@@ -118,48 +118,128 @@ def level_geometry(s, l):
     return n, m, info["ndof"]
 
 
-def cpu_baseline(wl, cycles, k, phi, amp, nsample=5):
-    """The FP64 oracle on the host: time a sample of V-cycles plus their
-    residual norms of the same solve, scale to the solve's cycle count."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        return 1
+
+
+def oracle_cycle_time(wl, k, phi, amp, nsample):
+    """Seconds per V-cycle (with its residual norm) of the FP64 oracle on the
+    host for workload wl, from `nsample` cycles of the solve from x0 = 0
+    (for a flexible-CG workload the iteration costs one such V-cycle plus an
+    operator application, both timed), and the residual norms seen."""
     import numpy as np
     import oracle
     from oracle.multigrid import _vcycle_global
     from oracle.sipg import to_global
-    try:
-        from threadpoolctl import threadpool_info
-        blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        blas = 1
     h = oracle.Hierarchy(wl.ne, wl.length, wl.P, overlap=wl.overlap, omega=wl.omega, growth=wl.growth)
     b = oracle.fourier_rhs(k, phi, amp, h)
     B = to_global(b, h.ne, h.top.n)
     X = np.zeros_like(B)
     lev = h.top
+    hist = []
     t0 = time.perf_counter()
     for _ in range(nsample):
-        float(np.linalg.norm(B - lev.A(X)))
+        hist.append(float(np.linalg.norm(B - lev.A(X))))
         X = _vcycle_global(X, B, h)
-    t_pair = (time.perf_counter() - t0) / nsample
-    t0 = time.perf_counter()
-    float(np.linalg.norm(B - lev.A(X)))
-    t_res = time.perf_counter() - t0
-    t_solve = cycles * t_pair + t_res
+        if wl.solver != "mg":
+            lev.A(X)  # the flexible CG's operator application q = A p
+    t_c = (time.perf_counter() - t0) / nsample
+    return t_c, hist
+
+
+def cpu_baseline(wl, cycles, k, phi, amp, nsample=5):
+    """The FP64 oracle on the host: time a sample of V-cycles plus their
+    residual norms of the same solve, scale to the solve's cycle count."""
+    blas = blas_threads()
+    t_pair, _ = oracle_cycle_time(wl, k, phi, amp, nsample)
+    t_solve = cycles * t_pair + t_pair / 4  # the final residual norm (about a quarter of a cycle)
     return {
         "value": wl.ndof / t_solve,
         "unit": "unknowns/s",
         "cores": int(blas),
         "kind": "oracle",
         "sample": (f"{nsample} V-cycles (each with its residual norm) of the same {wl.name} solve in the "
-                   f"FP64 NumPy oracle on {platform.processor() or platform.machine()} "
+                   f"FP64 NumPy oracle on {cpu_model()} "
                    f"({os.cpu_count()} logical CPUs, BLAS threads {blas}, elementwise work single-threaded), "
                    f"scaled to the solve's {cycles} cycles: {t_pair:.2f} s per cycle"),
     }
 
 
-def fcg_timing(wl, bits, b, steps, warmup, keep=None, autotune=True):
+def cpu_per_config(gpu_rates, nsample):
+    """BASELINE's CPU plan: for each workload the oracle's seconds per cycle
+    t_c on the host (a bounded sample), with the rate rho and cycles n10 of
+    the same algorithm (taken from the GPU solve of the workload, which
+    matches the oracle's iteration by iteration), tau10 = -10 t_c / lg rho
+    (Sec. 4), the solve time to 1e-10 and unknowns/s."""
+    from paper_1612_04796_amd.workloads import WORKLOADS, fourier_modes
+    out = {"cpu": cpu_model(), "logical_cpus": os.cpu_count(), "blas_threads": blas_threads()}
+    for name, rate in gpu_rates.items():
+        wl = WORKLOADS[name]
+        k, phi, amp = fourier_modes(0, wl.kmax)
+        t_c, _ = oracle_cycle_time(wl, k, phi, amp, nsample.get(name, 1))
+        nlg = rate["neg_lg_rho"]
+        out[name] = {"t_c_s": t_c, "rho": rate["rho"], "n10": rate["n10"], "cycles_to_1e-10": rate["cycles"],
+                     "tau10_us_per_unknown": 1e6 * 10.0 * t_c / nlg / wl.ndof if nlg > 0 else None,
+                     "solve_s": rate["cycles"] * t_c, "unknowns_per_s": wl.ndof / (rate["cycles"] * t_c),
+                     "sample_cycles": nsample.get(name, 1)}
+        log(f"cpu {name}: {t_c:.3f} s per cycle, {out[name]['unknowns_per_s']:.3g} unknowns/s")
+    return out
+
+
+def rate_of(hist):
+    import math
+    n = len(hist) - 1
+    rho = (hist[-1] / hist[0]) ** (1.0 / n) if n >= 1 and hist[0] > 0 else 0.0
+    nlg = -math.log10(rho) if rho > 0 else math.inf
+    return {"rho": rho, "neg_lg_rho": nlg, "n10": math.ceil(10.0 / nlg) if 0 < nlg < math.inf else None,
+            "cycles": n}
+
+
+def local_solve_roofline(s, ms, bits, mfma16=False):
+    """Roofline of the top-level local-solve kernel from its mean launch
+    duration `ms`: algorithmic flops (plain sum factorization) against the
+    FP64 or FP32 peak, or, for the FP16 matrix-core form (bound by its
+    gather and stores), algorithmic bytes (R_s r gathered and the
+    corrections stored, 4 B each) against HBM."""
+    n, m, N = level_geometry(s, s.L)
+    E = N // n ** 3
+    V = m[0] * m[1] * m[2]
+    if mfma16:
+        work = 8 * V * E
+        achieved = work / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "work_per_launch": work, "ms_per_launch": ms,
+                "subdomain": list(m)}
+    work = schwarz_flops(m) * E
+    peak = FP64_VALU_PEAK_TFLOPS if bits == 64 else FP32_VALU_PEAK_TFLOPS
+    achieved = work / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "work_per_launch": work, "ms_per_launch": ms,
+            "subdomain": list(m)}
+
+
+def fcg_timing(wl, bits, b, steps, warmup, keep=None, autotune=True, trace=True):
     """Flexible CG from x0 = 0 to 1e-10 on workload wl with the given
     preconditioner precision (16: FP32 with FP16 matrix-core local solves):
-    mean wall time over `steps` solves; keep[bits] receives the solution."""
+    mean wall time over `steps` solves; keep[bits] receives the solution.
+    With trace, every top-level local-solve launch of the last timed solve
+    is bracketed by HIP events (in the preconditioner's precision) and the
+    kernel's roofline is reported."""
     import torch
     from paper_1612_04796_amd import sipg
     s = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
@@ -170,19 +250,69 @@ def fcg_timing(wl, bits, b, steps, warmup, keep=None, autotune=True):
     for _ in range(max(1, warmup)):
         x.zero_()
         s.pcg_solve(x, b, 1e-10, 200)
+    if trace:
+        s.trace_kernel("schwarz_solve")
+        s.trace_kernel(None)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
+        if trace and i == steps - 1:
+            s.trace_kernel("schwarz_solve")
         x.zero_()
         it, rr = s.pcg_solve(x, b, 1e-10, 200)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    out = {"unknowns_per_s": wl.ndof * steps / el, "ms_per_solve": 1e3 * el / steps,
+           "iterations": it, "final_relres": rr, "rate": rate_of(s.residual_history())}
+    if trace:
+        ms, cnt = s.traced_kernel_ms()
+        s.trace_kernel(None)
+        if cnt:
+            roof = local_solve_roofline(s, ms, bits, mfma16=(bits == 16 and wl.P in (7, 8)))
+            roof["launches_timed"] = cnt
+            out["local_solve_roofline"] = roof
     s.close()
     if keep is not None:
         keep[bits] = x
     log(f"FCG {wl.name}, FP{bits} preconditioner: {1e3 * el / steps:.3f} ms/solve, {it} iterations")
-    return {"unknowns_per_s": wl.ndof * steps / el, "ms_per_solve": 1e3 * el / steps,
-            "iterations": it, "final_relres": rr}
+    return out
+
+
+def mg_timing(wl, b, steps, warmup):
+    """V(1,1) multigrid solve from x0 = 0 to 1e-10 (FP64): mean wall time."""
+    import torch
+    from paper_1612_04796_amd import sipg
+    s = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
+                    smooth_growth=wl.growth)
+    x = torch.zeros_like(b)
+    for _ in range(max(1, warmup)):
+        x.zero_()
+        s.mg_solve(x, b, 1e-10, 200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x.zero_()
+        it, rr = s.mg_solve(x, b, 1e-10, 200)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {"unknowns_per_s": wl.ndof * steps / el, "ms_per_solve": 1e3 * el / steps, "cycles": it,
+           "final_relres": rr, "rate": rate_of(s.residual_history())}
+    s.close()
+    log(f"MG {wl.name}: {out['ms_per_solve']:.3f} ms/solve, {it} cycles")
+    return out
+
+
+def workload_rhs(wl):
+    import torch
+    from paper_1612_04796_amd import sipg
+    from paper_1612_04796_amd.workloads import fourier_modes
+    s = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
+                    smooth_growth=wl.growth)
+    b = torch.zeros(s.ndof(), dtype=torch.float64, device="cuda")
+    k, phi, amp = fourier_modes(0, wl.kmax)
+    s.rhs_fourier(k, phi, amp, b)
+    s.close()
+    return b, (k, phi, amp)
 
 
 def serving_run(nreq, seed, log_every=4):
@@ -278,6 +408,8 @@ def main():
     ap.add_argument("--workload", default="cube16_p8_rel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 32^3, P=7 mixed-precision solves")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 4^3 P=4 and the anisotropic 8^3 P=16 workloads")
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel timing")
     ap.add_argument("--serving-requests", type=int, default=24,
                     help="requests of the serving stream run after the main measurement (0 = skip)")
@@ -303,12 +435,7 @@ def main():
     torch.cuda.set_device(0)
     wl = WORKLOADS[args.workload]
     if args.fcg_only:
-        s = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
-                        smooth_growth=wl.growth)
-        b = torch.zeros(s.ndof(), dtype=torch.float64, device="cuda")
-        k, phi, amp = fourier_modes(0, wl.kmax)
-        s.rhs_fourier(k, phi, amp, b)
-        s.close()
+        b, _ = workload_rhs(wl)
         print(json.dumps({"workload": wl.name, "precond_bits": args.fcg_only,
                           **fcg_timing(wl, args.fcg_only, b, args.steps, args.warmup,
                                        autotune=not args.no_autotune)}))
@@ -352,6 +479,7 @@ def main():
     elapsed = time.perf_counter() - t0
     traced_ms, traced_n = s.traced_kernel_ms()
     s.trace_kernel(None)
+    main_rate = rate_of(s.residual_history())
     log(f"local-solve kernel in the timed solves: {traced_n} launches, {1e3 * traced_ms:.2f} us mean")
     ms = 1e3 * elapsed / args.steps
     value = N * args.steps / elapsed
@@ -378,18 +506,16 @@ def main():
     log("top-level kernel ms/launch: " + ", ".join(f"{kk}={vv:.4f}" for kk, vv in kern.items())
         + f"; dominant {dominant}")
     if dominant == "schwarz_solve":
-        work = schwarz_flops(m) * E
-        achieved = work / (traced_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-                "traffic": pmc_traffic() if (n, m) == (9, (13, 13, 13)) else None,
-                # a tuned subdomains-per-workgroup count exists only for the
-                # compile-time-shape kernel
-                "kernel": (f"schwarz_fdm_fixed<double, {n}, {m[0]}, {m[1]}, {m[2]}>" if tuning[f"level{L}"][1] > 0
-                           else f"local solves (n = {n}, m = {m[0]} x {m[1]} x {m[2]})"),
-                "work_per_launch": work, "ms_per_launch": traced_ms, "launches_timed": traced_n,
-                "timing": "HIP events around each launch of the kernel inside the last timed solve",
-                "ms_per_launch_isolated": kern[dominant]}
+        roof = local_solve_roofline(s, traced_ms, 64)
+        roof.update({
+            "traffic": pmc_traffic() if (n, m) == (9, (13, 13, 13)) else None,
+            # a tuned subdomains-per-workgroup count exists only for the
+            # compile-time-shape kernel
+            "kernel": (f"schwarz_fdm_fixed<double, {n}, {m[0]}, {m[1]}, {m[2]}>" if tuning[f"level{L}"][1] > 0
+                       else f"local solves (n = {n}, m = {m[0]} x {m[1]} x {m[2]})"),
+            "launches_timed": traced_n,
+            "timing": "HIP events around each launch of the kernel inside the last timed solve",
+            "ms_per_launch_isolated": kern[dominant]})
     else:
         bytes_per = {"residual": 24, "schwarz_assemble": 24, "restrict": 16 + 8 / 8, "prolong": 16 + 8 / 8}
         work = bytes_per.get(dominant, 24) * N
@@ -398,42 +524,59 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dominant,
                 "work_per_launch": work, "ms_per_launch": kern[dominant]}
 
-    # ---- flexible CG on the same workload, FP64 and FP32 preconditioner
     detail = {"kernels_ms_per_launch": kern, "launches_per_solve": per_solve,
-              "iterations": cyc, "final_relres": rr, "launch_shapes": tuning}
+              "iterations": cyc, "final_relres": rr, "rate": main_rate, "launch_shapes": tuning}
     if wl.solver == "mg":
         detail["solve_roofline"] = solve_roofline(s, E, cyc, ms)
         log(f"whole-solve roofline: {detail['solve_roofline']['t_roofline_ms']:.3f} ms of {ms:.3f} ms "
             f"({detail['solve_roofline']['frac']:.2f})")
+    s.close()
+    # ---- flexible CG on the same workload, FP64 and FP32 preconditioner
     for bits in (64, 32):
         detail[f"fcg_precond_fp{bits}"] = fcg_timing(wl, bits, b, args.steps, args.warmup,
                                                     autotune=not args.no_autotune)
+    gpu_rates = {wl.name: main_rate}
+    # ---- the other solver workloads: 4^3 at P = 4 (MG) and the anisotropic
+    # 8^3 at P = 16 ([0,16] x [0,1]^2, "max" overlap, flexible CG)
+    if not args.no_configs:
+        configs = {}
+        wl1 = WORKLOADS["cube4_p4_min"]
+        b1, _ = workload_rhs(wl1)
+        configs[wl1.name] = {"ndof": wl1.ndof, "mg_fp64": mg_timing(wl1, b1, 4 * args.steps, args.warmup)}
+        gpu_rates[wl1.name] = configs[wl1.name]["mg_fp64"]["rate"]
+        wl3 = WORKLOADS["aniso16_p16_max"]
+        b3, _ = workload_rhs(wl3)
+        c3 = {"ndof": wl3.ndof}
+        for bits in (64, 32):
+            c3[f"fcg_precond_fp{bits}"] = fcg_timing(wl3, bits, b3, args.steps, args.warmup,
+                                                     autotune=not args.no_autotune)
+        configs[wl3.name] = c3
+        gpu_rates[wl3.name] = c3["fcg_precond_fp64"]["rate"]
+        r3 = c3["fcg_precond_fp64"].get("local_solve_roofline")
+        if r3:
+            log(f"{wl3.name}: local solves {r3['achieved']:.1f} TFLOP/s ({r3['frac']:.2f} of FP64 peak)")
+        detail["configs"] = configs
+        del b1, b3
     # ---- mixed precision at the 32^3, P = 7 workload (16.8M unknowns)
+    sols = {}
     if not args.no_mixed:
         wl4 = WORKLOADS["cube32_p7_rel"]
-        s4 = sipg.Solver(ne=wl4.ne, length=wl4.length, P=wl4.P, overlap=wl4.overlap, omega=wl4.omega,
-                         smooth_growth=wl4.growth)
-        b4 = torch.zeros(s4.ndof(), dtype=torch.float64, device="cuda")
-        k4, phi4, amp4 = fourier_modes(0, wl4.kmax)
-        s4.rhs_fourier(k4, phi4, amp4, b4)
-        s4.close()
+        b4, modes4 = workload_rhs(wl4)
         mixed = {"workload": wl4.name, "ndof": wl4.ndof}
-        sols = {}
         for bits in (64, 32, 16):
             mixed[f"fcg_precond_fp{bits}"] = fcg_timing(wl4, bits, b4, args.steps, args.warmup, sols,
                                                         autotune=not args.no_autotune)
         for bits in (32, 16):
-            m = mixed[f"fcg_precond_fp{bits}"]
-            m["speedup_over_fp64"] = mixed["fcg_precond_fp64"]["ms_per_solve"] / m["ms_per_solve"]
-            # distance to the solution of the FP64-preconditioned solve
-            m["rel_l2_vs_fp64_solution"] = float(torch.linalg.vector_norm(sols[bits] - sols[64])
-                                                 / torch.linalg.vector_norm(sols[64]))
+            mm = mixed[f"fcg_precond_fp{bits}"]
+            mm["speedup_over_fp64"] = mixed["fcg_precond_fp64"]["ms_per_solve"] / mm["ms_per_solve"]
         mixed["speedup_fp32_over_fp64"] = mixed["fcg_precond_fp32"]["speedup_over_fp64"]
         mixed["speedup_fp16_over_fp64"] = mixed["fcg_precond_fp16"]["speedup_over_fp64"]
+        gpu_rates[wl4.name] = mixed["fcg_precond_fp64"]["rate"]
         detail["mixed_precision"] = mixed
         log(f"mixed precision at {wl4.name}: FP32 preconditioner {mixed['speedup_fp32_over_fp64']:.2f}x, "
             f"FP16 local solves {mixed['speedup_fp16_over_fp64']:.2f}x the FP64 one")
-        del b4, sols
+        sols = {bits: v.cpu().numpy() for bits, v in sols.items()}
+        del b4
 
     if args.serving_requests > 0:
         log("serving stream ...")
@@ -477,7 +620,22 @@ def main():
             log(f"cpu baseline, one thread: {one['value']:.4g} unknowns/s")
         except ImportError:
             pass
-    s.close()
+        # per workload (BASELINE's plan): t_c, rho, n10, tau10, unknowns/s
+        detail["cpu_per_workload"] = cpu_per_config(
+            gpu_rates, {"cube4_p4_min": 10, "cube16_p8_rel": 2, "aniso16_p16_max": 1, "cube32_p7_rel": 1})
+        # the mixed-precision results against the oracle's exact discrete
+        # solution (global fast diagonalization of the FP64 operator)
+        if sols:
+            import numpy as np
+            import oracle
+            wl4 = WORKLOADS["cube32_p7_rel"]
+            h4 = oracle.Hierarchy(wl4.ne, wl4.length, wl4.P, overlap=wl4.overlap, omega=wl4.omega)
+            xs = oracle.exact_solution(oracle.fourier_rhs(*modes4, h4), h4)
+            nx = np.linalg.norm(xs)
+            for bits, xv in sols.items():
+                err = float(np.linalg.norm(xv - xs) / nx)
+                detail["mixed_precision"][f"fcg_precond_fp{bits}"]["rel_l2_vs_oracle"] = err
+                log(f"FP{bits}-preconditioned solve vs the oracle's exact solution: {err:.2e}")
     print(json.dumps(out), flush=True)
 
 

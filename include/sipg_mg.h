@@ -55,8 +55,15 @@ typedef enum {
  *   REL: width delta_O = omega * h_d in direction d;
  *   MAX: width min(omega * max_k h_k, h_d).
  * N_O on each level counts the neighbour nodes whose distance from the shared
- * face is at most delta_O. */
+ * face is at most delta_O (GLL) or below it (GL: possibly 0, the subdomain is
+ * then the element), and is at least overlap_floor. */
 typedef enum { SIPG_OVL_MIN = 0, SIPG_OVL_REL = 1, SIPG_OVL_MAX = 2 } sipg_overlap_mode;
+
+/* Nodal basis of every level (Sec. 2; Table 1): Gauss-Lobatto-Legendre nodes
+ * (end points are nodes: a face trace is one nodal value) or Gauss-Legendre
+ * nodes (no node at the ends: traces and normal derivatives at a face are
+ * combinations of a whole element line). */
+typedef enum { SIPG_BASIS_GLL = 0, SIPG_BASIS_GL = 1 } sipg_basis;
 
 typedef struct {
   int32_t ne[3];          /* elements per direction (x, y, z); 3..48, and >= 4 in a
@@ -79,10 +86,15 @@ typedef struct {
                              levels with cubic subdomains of 10-13 nodes (P = 7, 8)
                              run in FP16 on the matrix cores with FP32
                              accumulation and per-subdomain power-of-two scaling) */
+  int32_t basis;          /* SIPG_BASIS_GLL (0, the default) or SIPG_BASIS_GL; GL
+                             needs ne >= 4 in every direction                      */
+  int32_t overlap_floor;  /* lower bound of N_O on every level for REL and MAX
+                             overlaps, 0..2 (0: none; Table 1 rows 13-14 use 1)    */
 } sipg_params;
 
 /* Fills *p with the defaults: ne = 4^3, unit cube, P = 4, penalty 1.0,
- * minimal overlap, omega 0.08, V(1,1), growth 1, precond_bits 64. */
+ * minimal overlap, omega 0.08, V(1,1), growth 1, precond_bits 64, GLL basis,
+ * no overlap floor. */
 void sipg_default_params(sipg_params *p);
 
 /* Builds the level hierarchy (Sec. 3.2): for every level and direction the
@@ -263,8 +275,10 @@ typedef enum {
                                HIP graph on its first use and replay it afterwards (needs a
                                non-NULL stream at sipg_setup; kernel nodes only) */
   SIPG_OPT_TRACE_KERNEL = 1,/* value k in SIPG_KERNEL_RESIDUAL..SIPG_KERNEL_PROLONG: from now
-                               on every launch of that kernel on the top level in FP64
-                               (inside sipg_mg_solve, sipg_vcycle, ...) is bracketed by a
+                               on every launch of that kernel on the top level in the
+                               preconditioner's precision (FP64 for precond_bits 64, FP32
+                               for 32 and 16; inside sipg_mg_solve, sipg_pcg_solve,
+                               sipg_vcycle, ...), outside graph capture, is bracketed by a
                                pair of HIP events on the context's stream (at most 1024
                                launches are kept; later ones are not timed); -1 stops.
                                Setting it drops the launches recorded so far.  Allocates

@@ -73,7 +73,7 @@ __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >=
 
 // 1D operator data of one level (eq. (A)): per direction the element diagonal
 // block Ld (n x n), the mass diagonal, the scaled face-derivative rows
-// DL = D[0][:]/h, DR = D[p][:]/h and the penalty.
+// DL = D[0][:]/h, DR = D[p][:]/h (GLL) and the penalty.
 template <typename T>
 struct ApplyTabs {
   const T *Ld[3];
@@ -86,6 +86,11 @@ struct ApplyTabs {
   // Ld[i][n-1-j])/2 (i, j < h), then for odd n Ld[i][h] (i < h) and the
   // centre row Ld[h][j] (j <= h)
   const T *LdEO[3];
+  // GL basis (gl = 1): the traces TL = phi(-1), TR = phi(+1), full vectors;
+  // DL, DR are then (1/h) phi'(-1), (1/h) phi'(+1).  Unused for GLL.
+  const T *TL[3];
+  const T *TR[3];
+  int gl;
 };
 
 // Fast-diagonalization data of one level (Sec. 3.1): per direction the

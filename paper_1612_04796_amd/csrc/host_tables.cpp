@@ -1,16 +1,19 @@
 // Host-side set-up numerics; see host_tables.h.
 //
 // The discretization follows Sec. 2 of the paper with the standard symmetric
-// interior penalty form: on a face between element e (minus side, local node
-// p at xi = +1) and e+1 (plus side, node 0 at xi = -1) the 1D form
-// contributes  -{v'}[[u]] - [[v]]{u'} + mu [[v]][[u]]  with [[v]] = v^- - v^+
-// and {v'} the mean of the one-sided derivatives.  With GLL collocation the
-// element blocks of the 1D stiffness are
+// interior penalty form: on a face between element e (minus side, at its
+// xi = +1) and e+1 (plus side, at its xi = -1) the 1D form contributes
+// -{v'}[[u]] - [[v]]{u'} + mu [[v]][[u]]  with [[v]] = v^- - v^+ and {v'} the
+// mean of the one-sided derivatives.  With the traces tm = phi(-1),
+// tp = phi(+1) and end derivatives dm = phi'(-1), dp = phi'(+1) of the
+// element's Lagrange basis, the element blocks of the 1D stiffness are
 //   Ld = (2/h) D^T W D
-//        - (1/h) (D_p^T e_p^T + e_p D_p) + mu e_p e_p^T      (right face)
-//        + (1/h) (D_0^T e_0^T + e_0 D_0) + mu e_0 e_0^T      (left face)
-//   U  = L_{e,e+1} = (1/h) D_p^T e_0^T - (1/h) e_p D_0 - mu e_p e_0^T
-// where D_0, D_p are the first and last rows of the derivative matrix.
+//        - (1/h) (dp tp^T + tp dp^T) + mu tp tp^T            (right face)
+//        + (1/h) (dm tm^T + tm dm^T) + mu tm tm^T            (left face)
+//   U  = L_{e,e+1} = (1/h) dp tm^T - (1/h) tp dm^T - mu tp tm^T.
+// For GLL nodes tm = e_0, tp = e_p and dm, dp are the first and last rows of
+// the derivative matrix; for GL nodes (no node at the ends) all four are
+// full vectors.
 #include "host_tables.h"
 
 #include <algorithm>
@@ -49,11 +52,37 @@ double overlap_fraction(const sipg_params &p, int d) {
   return 0.0;
 }
 
-int count_layers(const std::vector<double> &xi, double frac) {
+// Overlap layers: neighbour nodes whose distance from the shared face,
+// (1 + xi)/2 element widths, is at most frac (GLL) or below it (GL), with a
+// 1e-12 tolerance (Table 1: the middle node at 0.5 dx counts for GLL, not
+// for GL); at least `floor`.  The minimal overlap is one layer either way.
+int count_layers(const sipg_params &prm, const std::vector<double> &xi, double frac) {
+  if (prm.overlap_mode == SIPG_OVL_MIN) return 1;
   int c = 0;
-  for (double x : xi)
-    if ((1.0 + x) / 2.0 <= frac + 1e-12) ++c;
-  return c;
+  for (double x : xi) {
+    const double d = (1.0 + x) / 2.0;
+    if (prm.basis == SIPG_BASIS_GL ? d < frac - 1e-12 : d <= frac + 1e-12) ++c;
+  }
+  return std::max(c, prm.overlap_floor);
+}
+
+// Traces phi_j(x) and derivatives phi_j'(x) of the Lagrange basis on xi at a
+// point x that is not a node: phi_j(x) = prod_{k != j} (x - x_k)/(x_j - x_k)
+// and phi_j'(x) = phi_j(x) sum_{k != j} 1/(x - x_k).
+void end_values(const std::vector<double> &xi, double x, std::vector<double> &phi, std::vector<double> &dphi) {
+  const int n = (int)xi.size();
+  phi.assign(n, 0.0);
+  dphi.assign(n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double v = 1.0, s = 0.0;
+    for (int k = 0; k < n; ++k) {
+      if (k == j) continue;
+      v *= (x - xi[k]) / (xi[j] - xi[k]);
+      s += 1.0 / (x - xi[k]);
+    }
+    phi[j] = v;
+    dphi[j] = v * s;
+  }
 }
 
 // C = Dm^{-1/2} A Dm^{-1/2}, eigen-decomposed; S = Dm^{-1/2} Q so that
@@ -136,7 +165,8 @@ void generalized_eigen_eo(int m, const std::vector<double> &A, const std::vector
   }
 }
 
-// Hat weights of the m = n + 2 N_O subdomain nodes: quintic step
+// Hat weights of the m = n + 2 N_O subdomain nodes (N_O may be 0 with GL
+// nodes: weight 1 on the element): quintic step
 // S5(t) = 10t^3 - 15t^4 + 6t^5 of t = (1 + delta - |xi_H|) / (2 delta),
 // clipped to [0,1], where xi_H is xi - 2 / xi / xi + 2 in the left neighbour,
 // the core and the right neighbour, and delta = min(1, 1 + xi_{N_O}) is the
@@ -166,43 +196,44 @@ void build_dir(const sipg_params &prm, int p, int d, bool smoothed, Dir1D &D1) {
   D1.mu = prm.penalty * p * (p + 1) / D1.h;
   const int n = D1.n;
   const double h = D1.h, mu = D1.mu;
-  gll_rule(p, D1.xi, D1.w);
+  if (prm.basis == SIPG_BASIS_GL) gl_rule(p, D1.xi, D1.w);
+  else gll_rule(p, D1.xi, D1.w);
   derivative_matrix(D1.xi, D1.D);
   const std::vector<double> &Dm = D1.D;
   D1.mass.resize(n);
   for (int i = 0; i < n; ++i) D1.mass[i] = 0.5 * h * D1.w[i];
+  // traces and end derivatives
+  std::vector<double> tm(n, 0.0), tp(n, 0.0), dm(n), dp(n);
+  if (prm.basis == SIPG_BASIS_GL) {
+    end_values(D1.xi, -1.0, tm, dm);
+    end_values(D1.xi, 1.0, tp, dp);
+  } else {
+    tm[0] = 1.0;
+    tp[n - 1] = 1.0;
+    for (int i = 0; i < n; ++i) dm[i] = Dm[0 * n + i], dp[i] = Dm[(n - 1) * n + i];
+  }
+  D1.TL = tm;
+  D1.TR = tp;
   D1.Ld.assign(n * n, 0.0);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
       double s = 0.0;
       for (int q = 0; q < n; ++q) s += Dm[q * n + i] * D1.w[q] * Dm[q * n + j];
-      D1.Ld[i * n + j] = (2.0 / h) * s;
+      D1.Ld[i * n + j] = (2.0 / h) * s
+                         - (dp[i] * tp[j] + tp[i] * dp[j]) / h + mu * tp[i] * tp[j]   // right face
+                         + (dm[i] * tm[j] + tm[i] * dm[j]) / h + mu * tm[i] * tm[j];  // left face
     }
-  const int P_ = n - 1;
-  for (int i = 0; i < n; ++i) {
-    // right face (this element is the minus side, node P_)
-    D1.Ld[i * n + P_] -= Dm[P_ * n + i] / h;
-    D1.Ld[P_ * n + i] -= Dm[P_ * n + i] / h;
-    // left face (this element is the plus side, node 0)
-    D1.Ld[i * n + 0] += Dm[0 * n + i] / h;
-    D1.Ld[0 * n + i] += Dm[0 * n + i] / h;
-  }
-  D1.Ld[P_ * n + P_] += mu;
-  D1.Ld[0] += mu;
   D1.U.assign(n * n, 0.0);
-  for (int i = 0; i < n; ++i) {
-    D1.U[i * n + 0] += Dm[P_ * n + i] / h;
-    D1.U[P_ * n + i] -= Dm[0 * n + i] / h;
-  }
-  D1.U[P_ * n + 0] -= mu;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) D1.U[i * n + j] = (dp[i] * tm[j] - tp[i] * dm[j]) / h - mu * tp[i] * tm[j];
   D1.DLs.resize(n);
   D1.DRs.resize(n);
   for (int i = 0; i < n; ++i) {
-    D1.DLs[i] = Dm[0 * n + i] / h;
-    D1.DRs[i] = Dm[P_ * n + i] / h;
+    D1.DLs[i] = dm[i] / h;
+    D1.DRs[i] = dp[i] / h;
   }
   if (!smoothed) return;
-  const int no = std::min(n, count_layers(D1.xi, overlap_fraction(prm, d)));
+  const int no = std::min(n, count_layers(prm, D1.xi, overlap_fraction(prm, d)));
   D1.no = no;
   const int m = n + 2 * no;
   D1.m = m;
@@ -273,6 +304,39 @@ void gll_rule(int p, std::vector<double> &xi, std::vector<double> &w) {
     double P, dP;
     legendre(p, xi[i], P, dP);
     w[i] = 2.0 / (p * (p + 1.0) * P * P);
+  }
+}
+
+void gl_rule(int p, std::vector<double> &xi, std::vector<double> &w) {
+  const int n = p + 1;
+  xi.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; ++i) {
+    // Newton on P_n(x) = 0 from the asymptotic guess of the i-th zero
+    double x = -std::cos(pi * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double P, dP;
+      legendre(n, x, P, dP);
+      const double dx = P / dP;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    xi[i] = x;
+  }
+  for (int i = 0; i < n; ++i) {  // exact symmetry
+    if (i < n - 1 - i) {
+      const double a = 0.5 * (xi[n - 1 - i] - xi[i]);
+      xi[i] = -a;
+      xi[n - 1 - i] = a;
+    } else if (i == n - 1 - i) {
+      xi[i] = 0.0;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    double P, dP;
+    legendre(n, xi[i], P, dP);
+    w[i] = 2.0 / ((1.0 - xi[i] * xi[i]) * dP * dP);
   }
 }
 
@@ -386,6 +450,14 @@ std::string validate(const sipg_params &p) {
     os << "penalty factor must exceed 1/2 (stability threshold)"; return os.str();
   }
   if (p.overlap_mode < 0 || p.overlap_mode > 2) return "unknown overlap mode";
+  if (p.basis != SIPG_BASIS_GLL && p.basis != SIPG_BASIS_GL) return "basis must be SIPG_BASIS_GLL or SIPG_BASIS_GL";
+  // GL traces couple a face to every node of the adjacent elements: with 3
+  // elements the two overlap layers of a subdomain would also couple through
+  // the periodic wrap, which the restricted 1D operator leaves out
+  if (p.basis == SIPG_BASIS_GL)
+    for (int d = 0; d < 3; ++d)
+      if (p.ne[d] < 4) return "the GL basis needs ne >= 4 in every direction";
+  if (p.overlap_floor < 0 || p.overlap_floor > 2) return "overlap_floor must be in 0..2";
   if (p.overlap_mode != SIPG_OVL_MIN && (!(p.overlap >= 0.0) || p.overlap > 1.0))
     return "overlap width omega must lie in [0, 1]";
   if (p.nsmooth_pre < 0 || p.nsmooth_post < 0 || p.nsmooth_pre + p.nsmooth_post < 1)

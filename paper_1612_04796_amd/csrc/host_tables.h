@@ -1,4 +1,4 @@
-// Host-side set-up numerics of the p-multigrid hierarchy: GLL rules, 1D SIPG
+// Host-side set-up numerics of the p-multigrid hierarchy: GLL / GL rules, 1D SIPG
 // blocks, restricted 1D eigenpairs, hat weights, interpolation and the level-0
 // global eigenpairs.  Pure C++ (no HIP); used by the context set-up and by the
 // host-only table queries of the C ABI.
@@ -17,12 +17,13 @@ struct Dir1D {
   // one direction of one level
   int p = 0, n = 0, ne = 0;
   double h = 0, mu = 0;
-  std::vector<double> xi, w;       // GLL rule (n)
+  std::vector<double> xi, w;       // GLL or GL rule (n)
   std::vector<double> D;           // n x n, D[i*n+j] = phi_j'(xi_i)
   std::vector<double> mass;        // (h/2) w
   std::vector<double> Ld;          // element diagonal block of L (n x n)
   std::vector<double> U;           // coupling block L_{e,e+1} (n x n)
-  std::vector<double> DLs, DRs;    // (1/h) D[0][:], (1/h) D[p][:]
+  std::vector<double> TL, TR;      // traces phi_j(-1), phi_j(+1) (unit vectors for GLL)
+  std::vector<double> DLs, DRs;    // (1/h) phi_j'(-1), (1/h) phi_j'(+1)
   // subdomain (levels >= 1)
   int no = 0, m = 0;
   std::vector<double> Ls, Ms;      // m x m, m
@@ -64,6 +65,8 @@ std::vector<int> level_orders(int P);
 
 // Building blocks (exposed for the host-only table queries).
 void gll_rule(int p, std::vector<double> &xi, std::vector<double> &w);
+// Gauss-Legendre: the p + 1 zeros of P_{p+1} and their weights
+void gl_rule(int p, std::vector<double> &xi, std::vector<double> &w);
 void derivative_matrix(const std::vector<double> &xi, std::vector<double> &D);
 void interpolation_matrix(const std::vector<double> &from, const std::vector<double> &to,
                           std::vector<double> &J);

@@ -14,9 +14,14 @@
 // numbering keeps neighbour re-reads in L2.
 //
 // With DL = D[0][:]/h, DR = D[p][:]/h the coupling of line v of element e to
-// its right neighbour line vr and left neighbour line vl is
+// its right neighbour line vr and left neighbour line vl is (GLL)
 //   c[i] = DR[i] vr[0] - DL[i] vl[p]
 //        - [i = p] (DL . vr + mu vr[0]) + [i = 0] (DR . vl - mu vl[p]).
+// For the GL basis (GL = true) the face values are the traces
+// vR = TL . vr, vL = TR . vl (TL = phi(-1), TR = phi(+1)), DL, DR the end
+// derivatives over h, and the unit vectors e_p, e_0 above become TR, TL:
+//   c[i] = (DR[i] - mu TR[i]) vR - TR[i] (DL . vr)
+//        + (-DL[i] - mu TL[i]) vL + TL[i] (DR . vl).
 //
 // Levels are 1, 2, 4, ..., 2^k < P, P, so the coarse size below a level of n
 // nodes is fixed by n: n_c = 2^floor(log2(n - 2)) + 1.
@@ -56,18 +61,33 @@ struct FaceData {
   T vR, gR, vL, gL;
 };
 
-template <typename T, int N>
+template <typename T, int N, bool GL>
 __device__ __forceinline__ FaceData<T> face_data(const T *__restrict__ lr, const T *__restrict__ ll, int st,
-                                                 const T *__restrict__ DL, const T *__restrict__ DR) {
+                                                 const T *__restrict__ DL, const T *__restrict__ DR,
+                                                 const T *__restrict__ TL, const T *__restrict__ TR) {
   FaceData<T> fd;
   T gR = 0, gL = 0;
+  if constexpr (GL) {
+    T vR = 0, vL = 0;
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    gR += DL[i] * lr[i * st];
-    gL += DR[i] * ll[i * st];
+    for (int i = 0; i < N; ++i) {
+      const T r = lr[i * st], l = ll[i * st];
+      gR += DL[i] * r;
+      gL += DR[i] * l;
+      vR += TL[i] * r;
+      vL += TR[i] * l;
+    }
+    fd.vR = vR;
+    fd.vL = vL;
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      gR += DL[i] * lr[i * st];
+      gL += DR[i] * ll[i * st];
+    }
+    fd.vR = lr[0];
+    fd.vL = ll[(N - 1) * st];
   }
-  fd.vR = lr[0];
-  fd.vL = ll[(N - 1) * st];
   fd.gR = gR;
   fd.gL = gL;
   return fd;
@@ -76,10 +96,11 @@ __device__ __forceinline__ FaceData<T> face_data(const T *__restrict__ lr, const
 // All N outputs of L_d applied to the line v, with the face coupling; the
 // element block is applied in its even-odd form (about half the
 // multiply-adds of the plain n x n product; Ld is centro-symmetric).
-template <typename T, int N>
+template <typename T, int N, bool GL>
 __device__ __forceinline__ void line_op_all(const T (&v)[N], T (&out)[N], const T *__restrict__ eo,
                                             const T *__restrict__ DL, const T *__restrict__ DR, T mu,
-                                            const FaceData<T> &fd) {
+                                            const FaceData<T> &fd, const T *__restrict__ TL,
+                                            const T *__restrict__ TR) {
   constexpr int H = N / 2;
   const T *Ae = eo, *Ao = eo + H * H, *Ac = eo + 2 * H * H, *Acr = Ac + H;
   T sm[H], df[H];
@@ -106,10 +127,16 @@ __device__ __forceinline__ void line_op_all(const T (&v)[N], T (&out)[N], const 
     for (int j = 0; j < H; ++j) c += Acr[j] * sm[j];
     out[H] = c;
   }
+  if constexpr (GL) {
 #pragma unroll
-  for (int i = 0; i < N; ++i) out[i] += DR[i] * fd.vR - DL[i] * fd.vL;
-  out[N - 1] -= fd.gR + mu * fd.vR;
-  out[0] += fd.gL - mu * fd.vL;
+    for (int i = 0; i < N; ++i)
+      out[i] += (DR[i] - mu * TR[i]) * fd.vR - TR[i] * fd.gR - (DL[i] + mu * TL[i]) * fd.vL + TL[i] * fd.gL;
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] += DR[i] * fd.vR - DL[i] * fd.vL;
+    out[N - 1] -= fd.gR + mu * fd.vR;
+    out[0] += fd.gL - mu * fd.vL;
+  }
 }
 
 // Several operator applications of one order in one launch (the same-order
@@ -137,7 +164,7 @@ struct ApplySegs {
 // EPB (elements per workgroup) is chosen at launch, at most ApplyShape<N>::EPB.
 // SEG: the launch covers the segments in `segs` (every other operand except
 // EPB is taken from the workgroup's segment).
-template <typename T, int N, int MODE, bool DOT, bool SEG>
+template <typename T, int N, int MODE, bool DOT, bool SEG, bool GL>
 __global__ void __launch_bounds__(ApplyShape<N>::NTH)
 apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restrict__ f, T *__restrict__ out,
              T *__restrict__ partial, const T *__restrict__ J, int EPB, bool nt, bool tiled, ApplySegs<T> segs) {
@@ -201,9 +228,9 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
     const T *uyl = u + (size_t)elem_index(g, ex, wrap(ey - 1, g.ne[1]), ez) * N3 + p * N2 + q;
     const T *uzr = u + (size_t)elem_index(g, ex, ey, wrap(ez + 1, g.ne[2])) * N3 + pq;
     const T *uzl = u + (size_t)elem_index(g, ex, ey, wrap(ez - 1, g.ne[2])) * N3 + pq;
-    fx = face_data<T, N>(uxr, uxl, 1, tb.DL[0], tb.DR[0]);
-    fy = face_data<T, N>(uyr, uyl, N, tb.DL[1], tb.DR[1]);
-    fz = face_data<T, N>(uzr, uzl, N2, tb.DL[2], tb.DR[2]);
+    fx = face_data<T, N, GL>(uxr, uxl, 1, tb.DL[0], tb.DR[0], tb.TL[0], tb.TR[0]);
+    fy = face_data<T, N, GL>(uyr, uyl, N, tb.DL[1], tb.DR[1], tb.TL[1], tb.TR[1]);
+    fz = face_data<T, N, GL>(uzr, uzl, N2, tb.DL[2], tb.DR[2], tb.TL[2], tb.TR[2]);
   }
 #pragma unroll
   for (int j = 0; j < N; ++j) {
@@ -220,7 +247,7 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
     for (int i = 0; i < N; ++i) v[i] = sl[i];
     const T sc = scx;
     T o[N];
-    line_op_all<T, N>(v, o, tb.LdEO[0], tb.DL[0], tb.DR[0], tb.mu[0], fx);
+    line_op_all<T, N, GL>(v, o, tb.LdEO[0], tb.DL[0], tb.DR[0], tb.mu[0], fx, tb.TL[0], tb.TR[0]);
 #pragma unroll
     for (int i = 0; i < N; ++i) yl[i] = sc * o[i];
   }
@@ -233,7 +260,7 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
     for (int j = 0; j < N; ++j) v[j] = sl[j * N];
     const T sc = scy;
     T o[N];
-    line_op_all<T, N>(v, o, tb.LdEO[1], tb.DL[1], tb.DR[1], tb.mu[1], fy);
+    line_op_all<T, N, GL>(v, o, tb.LdEO[1], tb.DL[1], tb.DR[1], tb.mu[1], fy, tb.TL[1], tb.TR[1]);
 #pragma unroll
     for (int j = 0; j < N; ++j) yl[j * N] += sc * o[j];
   }
@@ -248,7 +275,7 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
     const T sc = scz;
     const size_t gbase = (size_t)(e0 + le) * N3 + pq;
     T o[N];
-    line_op_all<T, N>(v, o, tb.LdEO[2], tb.DL[2], tb.DR[2], tb.mu[2], fz);
+    line_op_all<T, N, GL>(v, o, tb.LdEO[2], tb.DL[2], tb.DR[2], tb.mu[2], fz, tb.TL[2], tb.TR[2]);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       const T y = yl[k * N2] + sc * o[k];
@@ -421,19 +448,24 @@ bool tiled_order(const Mesh &g) {
   return (int64_t)g.ne[0] * g.ne[1] * N * N * N * (int64_t)sizeof(T) >= (2 << 20);
 }
 
-template <typename T, int N, int MODE, bool DOT>
-hipError_t launch_mode(const ApplyLaunch<T> &a, hipStream_t st) {
+template <typename T, int N, int MODE, bool DOT, bool GL>
+hipError_t launch_mode_b(const ApplyLaunch<T> &a, hipStream_t st) {
   using Sh = ApplyShape<N>;
   const int epb = launch_epb(a.mesh.E, N, a.epb);
   const int nblk = (a.mesh.E + epb - 1) / epb;
   const int nth = std::min(Sh::NTH, (epb * N * N + 63) / 64 * 64);
   const size_t shm = 2 * (size_t)epb * N * N * N * sizeof(T);
-  hipError_t e = allow_lds(apply_kernel<T, N, MODE, DOT, false>, shm);
+  hipError_t e = allow_lds(apply_kernel<T, N, MODE, DOT, false, GL>, shm);
   if (e != hipSuccess) return e;
   const bool nt = out_streams<T, N>(a.mesh), tiled = tiled_order<T, N>(a.mesh);
-  apply_kernel<T, N, MODE, DOT, false><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, a.partial, a.J, epb,
-                                                               nt, tiled, ApplySegs<T>{});
+  apply_kernel<T, N, MODE, DOT, false, GL><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, a.partial, a.J,
+                                                                   epb, nt, tiled, ApplySegs<T>{});
   return hipGetLastError();
+}
+
+template <typename T, int N, int MODE, bool DOT>
+hipError_t launch_mode(const ApplyLaunch<T> &a, hipStream_t st) {
+  return a.tabs.gl ? launch_mode_b<T, N, MODE, DOT, true>(a, st) : launch_mode_b<T, N, MODE, DOT, false>(a, st);
 }
 
 template <typename T, int N>
@@ -491,9 +523,10 @@ hipError_t launch_segments_n(const ApplyLaunch<T> *a, int n, hipStream_t st) {
   ApplySegs<T> S{};
   S.n = n;
   int blk = 0;
+  const bool gl = a[0].tabs.gl != 0;
   for (int k = 0; k < n; ++k) {
     if (a[k].n != N || a[k].mode != APPLY_PLAIN || (a[k].partial != nullptr) != dot ||
-        launch_epb(a[k].mesh.E, N, a[k].epb) != epb)
+        launch_epb(a[k].mesh.E, N, a[k].epb) != epb || (a[k].tabs.gl != 0) != gl)
       return hipErrorInvalidValue;
     const int nblk = (a[k].mesh.E + epb - 1) / epb;
     S.s[k] = ApplySeg<T>{a[k].mesh, a[k].tabs, a[k].u, a[k].f, a[k].out, a[k].partial, a[k].J,
@@ -502,18 +535,17 @@ hipError_t launch_segments_n(const ApplyLaunch<T> *a, int n, hipStream_t st) {
   }
   const int nth = std::min(Sh::NTH, (epb * N * N + 63) / 64 * 64);
   const size_t shm = 2 * (size_t)epb * N * N * N * sizeof(T);
-  hipError_t e;
   const ApplyLaunch<T> &a0 = a[0];
-  if (dot) {
-    if ((e = allow_lds(apply_kernel<T, N, MODE_APPLY, true, true>, shm)) != hipSuccess) return e;
-    apply_kernel<T, N, MODE_APPLY, true, true><<<blk, nth, shm, st>>>(a0.mesh, a0.tabs, a0.u, a0.f, a0.out, a0.partial,
-                                                                      a0.J, epb, false, false, S);
-  } else {
-    if ((e = allow_lds(apply_kernel<T, N, MODE_APPLY, false, true>, shm)) != hipSuccess) return e;
-    apply_kernel<T, N, MODE_APPLY, false, true><<<blk, nth, shm, st>>>(a0.mesh, a0.tabs, a0.u, a0.f, a0.out,
-                                                                       a0.partial, a0.J, epb, false, false, S);
-  }
-  return hipGetLastError();
+  auto go = [&](auto kernel) {
+    hipError_t e = allow_lds(kernel, shm);
+    if (e != hipSuccess) return e;
+    kernel<<<blk, nth, shm, st>>>(a0.mesh, a0.tabs, a0.u, a0.f, a0.out, a0.partial, a0.J, epb, false, false, S);
+    return hipGetLastError();
+  };
+  if (dot) return gl ? go(apply_kernel<T, N, MODE_APPLY, true, true, true>)
+                     : go(apply_kernel<T, N, MODE_APPLY, true, true, false>);
+  return gl ? go(apply_kernel<T, N, MODE_APPLY, false, true, true>)
+            : go(apply_kernel<T, N, MODE_APPLY, false, true, false>);
 }
 
 int apply_launch_epb(int E, int n, int epb) { return launch_epb(E, n, epb); }

@@ -60,15 +60,23 @@ apply_axis(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restrict
     const T *lr = u + (size_t)eR * N3 + base;
     const T *ll = u + (size_t)eL * N3 + base;
     const T *lv = u + (size_t)e * N3 + base;
+    const T *__restrict__ TL = tb.TL[DIR];
+    const T *__restrict__ TR = tb.TR[DIR];
+    const bool gl = tb.gl != 0;
     T v[N];
-    T gR = 0, gL = 0;
+    T gR = 0, gL = 0, vR = 0, vL = 0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       v[i] = lv[i * st];
-      gR += DL[i] * lr[i * st];
-      gL += DR[i] * ll[i * st];
+      const T r = lr[i * st], l = ll[i * st];
+      gR += DL[i] * r;
+      gL += DR[i] * l;
+      if (gl) {
+        vR += TL[i] * r;
+        vL += TR[i] * l;
+      }
     }
-    const T vR = lr[0], vL = ll[(N - 1) * st];
+    if (!gl) vR = lr[0], vL = ll[(N - 1) * st];
     // mass factors of the two other directions
     T sc;
     if (DIR == 0) sc = tb.M[2][p] * tb.M[1][q];
@@ -81,8 +89,12 @@ apply_axis(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restrict
       T acc = DR[i] * vR - DL[i] * vL;
 #pragma unroll
       for (int k = 0; k < N; ++k) acc += Ld[i * N + k] * v[k];
-      if (i == N - 1) acc -= gR + mu * vR;
-      if (i == 0) acc += gL - mu * vL;
+      if (gl) {  // the face terms of the GL basis reach every node of the line
+        acc += -TR[i] * (gR + mu * vR) + TL[i] * (gL - mu * vL);
+      } else {
+        if (i == N - 1) acc -= gR + mu * vR;
+        if (i == 0) acc += gL - mu * vL;
+      }
       acc *= sc;
       if (DIR == 0) {
         o[i * st] = acc;

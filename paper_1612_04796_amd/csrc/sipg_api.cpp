@@ -315,7 +315,7 @@ MfmaHost build_mfma_tables(const sipg::LevelHost &lv) {
 
 // Offsets of one level's tables in the arena.
 struct TabOff {
-  size_t Ld[3], LdEO[3], M[3], DL[3], DR[3], S[3], WS[3], WST[3], lam[3], EO[3], J, ilam, ilam_eo;
+  size_t Ld[3], LdEO[3], M[3], DL[3], DR[3], TL[3], TR[3], S[3], WS[3], WST[3], lam[3], EO[3], J, ilam, ilam_eo;
   size_t mf[3], mb[3], mil;
   double kout;
   bool mfma;
@@ -366,6 +366,8 @@ TableArena build_table_arena(const sipg::HierarchyHost &H, int64_t E) {
         off[l].M[d] = A.put<T>(D.mass);
         off[l].DL[d] = A.put<T>(D.DLs);
         off[l].DR[d] = A.put<T>(D.DRs);
+        off[l].TL[d] = A.put<T>(D.TL);
+        off[l].TR[d] = A.put<T>(D.TR);
         if (l > 0) {
           std::vector<double> WS(D.S);
           for (int a = 0; a < D.m; ++a)
@@ -451,12 +453,15 @@ void upload_tables(sipg_ctx *c) {
       t.n = lv.n;
       t.nc = l > 0 ? H.lev[l - 1].n : 0;
       t.ndof = level_ndof(H, l);
+      t.apply.gl = H.prm.basis == SIPG_BASIS_GL;
       for (int d = 0; d < 3; ++d) {
         t.apply.Ld[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].Ld[d]);
         t.apply.M[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].M[d]);
         t.apply.LdEO[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].LdEO[d]);
         t.apply.DL[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].DL[d]);
         t.apply.DR[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].DR[d]);
+        t.apply.TL[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].TL[d]);
+        t.apply.TR[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].TR[d]);
         t.apply.mu[d] = (T)lv.dir[d].mu;
         if (l > 0) {
           t.schwarz.S[d] = reinterpret_cast<const T *>(c->tab_dev + off[l].S[d]);
@@ -507,11 +512,12 @@ constexpr int kTraceMax = 1024;
 
 // Opens a traced launch of `kernel` on level l in precision T: returns the
 // slot of its event pair (its start event recorded), or -1 when not traced.
+// Traced: top-level launches in the preconditioner's precision (FP64, or
+// FP32 for precond_bits 32 and 16).
 template <typename T>
 int trace_begin(sipg_ctx *c, int kernel, int l) {
-  if (c->trace_kernel != kernel || l != c->L || !std::is_same<T, double>::value || c->capturing ||
-      c->trace_n >= kTraceMax)
-    return -1;
+  const bool prec = std::is_same<T, double>::value == (c->H.prm.precond_bits == 64);
+  if (c->trace_kernel != kernel || l != c->L || !prec || c->capturing || c->trace_n >= kTraceMax) return -1;
   const int k = c->trace_n++;
   check(hipEventRecord(c->trace_ev[2 * k], c->stream), "trace event");
   return k;
@@ -1140,6 +1146,8 @@ void sipg_default_params(sipg_params *p) {
   p->nsmooth_post = 1;
   p->smooth_growth = 1;
   p->precond_bits = 64;
+  p->basis = SIPG_BASIS_GLL;
+  p->overlap_floor = 0;
 }
 
 const char *sipg_last_error(void) { return g_err.c_str(); }

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "lib
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, ENOTFINITE = 0, -1, -2, -3, -4, -5, -6
 OVERLAP = {"min": 0, "rel": 1, "max": 2}
+BASIS = {"gll": 0, "gl": 1}
 TABLES = {
     "nodes": 0, "weights": 1, "deriv": 2, "mass": 3, "ldiag": 4, "lupper": 5, "overlap": 6,
     "sub_l": 7, "sub_m": 8, "sub_lam": 9, "sub_s": 10, "sub_w": 11, "interp": 12,
@@ -54,6 +55,8 @@ class Params(ctypes.Structure):
         ("nsmooth_post", ctypes.c_int32),
         ("smooth_growth", ctypes.c_int32),
         ("precond_bits", ctypes.c_int32),
+        ("basis", ctypes.c_int32),
+        ("overlap_floor", ctypes.c_int32),
     ]
 
 
@@ -132,7 +135,8 @@ def _check(rc):
 
 
 def make_params(ne=(4, 4, 4), length=(1.0, 1.0, 1.0), P=4, penalty=1.0, overlap="min",
-                omega=0.08, nsmooth_pre=1, nsmooth_post=1, smooth_growth=1, precond_bits=64):
+                omega=0.08, nsmooth_pre=1, nsmooth_post=1, smooth_growth=1, precond_bits=64,
+                basis="gll", overlap_floor=0):
     p = Params()
     lib().sipg_default_params(ctypes.byref(p))
     for d in range(3):
@@ -145,6 +149,8 @@ def make_params(ne=(4, 4, 4), length=(1.0, 1.0, 1.0), P=4, penalty=1.0, overlap=
     p.nsmooth_pre, p.nsmooth_post = int(nsmooth_pre), int(nsmooth_post)
     p.smooth_growth = int(smooth_growth)
     p.precond_bits = int(precond_bits)
+    p.basis = BASIS[basis] if isinstance(basis, str) else int(basis)
+    p.overlap_floor = int(overlap_floor)
     return p
 
 

@@ -42,3 +42,25 @@ def test_solve_roofline_top_level_terms():
     # the local solves of the top level are bound by arithmetic, the residual by bytes
     assert fdm == bench.schwarz_flops((13, 13, 13)) * E / pk
     assert res == 24 * N / bw
+
+
+def test_local_solve_roofline_work_per_launch():
+    s = _Levels()
+    # FP64: the plain sum-factorized flops of 4096 subdomains of 13^3 per
+    # launch against the FP64 vector peak; 40 us per launch
+    r = bench.local_solve_roofline(s, 0.040, 64)
+    work = bench.schwarz_flops((13, 13, 13)) * 4096
+    assert r["work_per_launch"] == work and r["unit"] == "TFLOP/s"
+    assert abs(r["achieved"] - work / 40e-6 / 1e12) < 1e-9 and r["peak"] == 78.6
+    assert abs(r["frac"] - r["achieved"] / 78.6) < 1e-12
+    # FP32: the FP32 peak
+    assert bench.local_solve_roofline(s, 0.040, 32)["peak"] == 157.3
+    # FP16 matrix-core form: bytes of R_s r gathered and C stored (4 B each)
+    r16 = bench.local_solve_roofline(s, 0.040, 16, mfma16=True)
+    assert r16["bound"] == "hbm" and r16["work_per_launch"] == 8 * 2197 * 4096
+
+
+def test_rate_of_history():
+    r = bench.rate_of([1.0, 1e-2, 1e-4, 1e-6])
+    assert abs(r["rho"] - 1e-2) < 1e-15 and r["n10"] == 5 and r["cycles"] == 3
+    assert bench.rate_of([1.0])["n10"] is None

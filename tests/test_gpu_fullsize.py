@@ -113,21 +113,23 @@ def test_cube32_p7_fcg(bits):
 
 def test_cube32_p7_fp16_preconditioner():
     """The FP16 local solves at their benchmarked size (the tiled visiting
-    order of the matrix-core kernel): the preconditioner stays within the
-    FP16 form's documented distance of the FP32 one (which the oracle pins),
-    and the flexible CG it drives reaches 1e-10 in no more iterations than
-    allowed for the FP64 form."""
+    order of the matrix-core kernel switches on only here): the FP16-form
+    preconditioner against the oracle's FP64 V-cycle element by element at
+    the FP16 form's tolerance (1e-2, as on small meshes: FP16 tables and
+    tensors, about 3 significant digits), and the FP64 flexible CG it drives
+    against the oracle's exact discrete solution, within the bound every
+    solve test uses (measured 3.0e-12, as for the FP64 and FP32
+    preconditioners)."""
     announce("fullsize cube32_p7_rel fp16")
     wl, h, s16, b, _ = _setup("cube32_p7_rel", precond_bits=16)
-    s32 = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
-                      smooth_growth=wl.growth, precond_bits=32)
-    z16, z32 = zeros(s16.ndof()), zeros(s16.ndof())
+    bh = host(b)
+    z16 = zeros(s16.ndof())
     s16.precond(b, z16)
-    s32.precond(b, z32)
-    d = rel(host(z16), host(z32))
+    ref = oracle.vcycle(np.zeros_like(bh), bh, h)
+    d = rel(host(z16), ref)
     assert 0.0 < d <= 1e-2, d
-    s32.close()
     x = zeros(s16.ndof())
     it, rr = s16.pcg_solve(x, b, rtol=1e-10, maxit=60)
     assert rr <= 1e-10 and it <= 12
+    assert rel(host(x), oracle.exact_solution(bh, h)) <= TOL_EXACT
     s16.close()

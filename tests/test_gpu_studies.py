@@ -21,11 +21,13 @@ from _gpu import announce
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table1_gll.txt")
+GOLDEN_FIG5 = os.path.join(os.path.dirname(__file__), "golden", "fig5_rates.txt")
 
 
 def _oracle_history(params, solver, ncyc, tol=1e-11):
     h = oracle.Hierarchy(params["ne"], params["length"], params["P"], overlap=params["overlap"],
-                         omega=params["omega"], growth=params.get("smooth_growth", 1))
+                         omega=params["omega"], growth=params.get("smooth_growth", 1),
+                         basis=params.get("basis", "gll"), overlap_floor=params.get("overlap_floor", 0))
     k, phi, amp = fourier_modes(0, 3)
     b = oracle.fourier_rhs(k, phi, amp, h)
     x0 = uniform_vector(7, b.size)
@@ -48,9 +50,9 @@ def _compare(params, solver, ncyc, tol=1e-11):
 
 @pytest.mark.parametrize("row", sorted(studies.TABLE1_ROWS))
 def test_table1_methods_match_oracle_small(row):
-    solver, overlap, omega = studies.TABLE1_ROWS[row]
+    solver, overlap, omega, basis, floor = studies.TABLE1_ROWS[row]
     announce(f"table1 row {row} small")
-    _compare(studies.table1_params(4, overlap, omega, ne=4), solver, ncyc=6)
+    _compare(studies.table1_params(4, overlap, omega, ne=4, basis=basis, overlap_floor=floor), solver, ncyc=6)
 
 
 @pytest.mark.parametrize("method", sorted(studies.ANISO_METHODS))
@@ -63,12 +65,13 @@ def test_aniso_methods_match_oracle_small(method, AR):
 
 def _table1_paper():
     rows = {}
-    with open(GOLDEN) as fh:
-        for line in fh:
-            if line.startswith("#") or not line.strip():
-                continue
-            t = line.split()
-            rows[int(t[0])] = dict(zip((4, 8, 16, 32), (float(v) for v in t[8:12])))
+    for path in (GOLDEN, GOLDEN.replace("table1_gll", "table1_gl")):
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith("#") or not line.strip():
+                    continue
+                t = line.split()
+                rows[int(t[0])] = dict(zip((4, 8, 16, 32), (float(v) for v in t[8:12])))
     return rows
 
 
@@ -79,18 +82,41 @@ def test_table1_at_paper_meshes():
     where 3-5 cycles reach 1e-11 and the rate estimate is coarser."""
     announce("table1 at paper meshes")
     paper = _table1_paper()
-    for rec in studies.run_table1():
+    for rec in studies.run_table1(rows=(1, 2, 3, 4, 5, 6)):
         want = paper[rec["row"]][rec["P"]]
         tol = 0.2 if rec["row"] <= 4 else 0.3
         assert abs(rec["neg_lg_rho"] - want) <= tol, (rec["row"], rec["P"], rec["neg_lg_rho"], want)
 
 
+def test_table1_gl_at_paper_meshes():
+    """The GL rows (7-14) of Table 1 at (128/P)^3 elements: every cell within
+    0.3 of the paper's, except row 7 at P = 4, whose printed 0.73 repeats row
+    9's cell although rows 7 and 13 have the same overlap layers at P = 4
+    (row 13 reads 1.36; both measure about 1.38 here)."""
+    announce("table1 GL at paper meshes")
+    paper = _table1_paper()
+    bad = []
+    for rec in studies.run_table1(rows=tuple(range(7, 15))):
+        if rec["row"] == 7 and rec["P"] == 4:
+            continue
+        want = paper[rec["row"]][rec["P"]]
+        if abs(rec["neg_lg_rho"] - want) > 0.3:
+            bad.append((rec["row"], rec["P"], rec["neg_lg_rho"], want))
+    assert not bad, bad
+
+
 def test_aniso_study_trends():
-    """The anisotropic study (8^3 elements, P = 16, AR up to 48): the
-    overlap relative to each element's own width degrades quickly with the
-    aspect ratio, the variable V-cycle does not cure it, and an overlap set
-    by the largest element side keeps a few cycles per decade over the
-    whole range (the paper: from 4 to 13 cycles at AR = 48)."""
+    """The anisotropic study (8^3 elements, P = 16, AR up to 48), the parts
+    of the paper's account (Sec. 4, Anisotropic Meshes) that this build
+    reproduces: the overlap relative to each element's own width degrades
+    quickly with the aspect ratio; the overlap set by the largest element
+    side with the variable V-cycle ("max_var") keeps the cycle count nearly
+    constant up to AR = 12, grows beyond, and still converges at AR = 48
+    (the approach "feasible for aspect ratios up to 50").  Not reproduced,
+    and not asserted: the paper's 13 cycles at AR = 48 (27 here) and the
+    convergence of the relative-overlap methods beyond AR = 12 (they
+    diverge here); the readings tried for it are listed in the design
+    notes, the discrepancy is unresolved."""
     announce("aniso study")
     res = {(r["method"], r["AR"]): r for r in studies.run_aniso(ars=(1, 8, 16, 48), ncyc=40)}
     for m in studies.ANISO_METHODS:
@@ -98,4 +124,33 @@ def test_aniso_study_trends():
     assert res[("rel_fix", 8)]["neg_lg_rho"] < 0.5 * res[("rel_fix", 1)]["neg_lg_rho"]
     assert res[("max_var", 16)]["neg_lg_rho"] > res[("rel_var", 16)]["neg_lg_rho"] + 1.0
     n10 = [res[("max_var", ar)]["n10"] for ar in (1, 8, 16, 48)]
-    assert all(v is not None for v in n10) and n10[-1] <= 30 and n10[1:] == sorted(n10[1:]) and n10[0] <= 6
+    assert all(v is not None for v in n10), n10            # converges up to AR = 48
+    assert n10[0] <= 6 and n10[1] <= n10[0] + 1, n10       # nearly constant to AR = 8
+    assert n10[1:] == sorted(n10[1:]), n10                 # grows beyond
+
+
+def test_fig5_mesh_independence_and_rates():
+    """Fig. 5 as the paper's text states it (Sec. 4): with 8 % overlap the
+    V(1,1) rate is mesh independent from about 12^3 elements for P <= 16,
+    and reaches about 6.3e-3 at P = 16 and 1.6e-3 at P = 32.  Checked on a
+    reduced sweep: the rates on meshes of 8^3 elements and more agree within
+    a factor 1.5 for each P <= 16, and the rates on the finest meshes run
+    are within a factor 2 of the stated values (a rate from 4-6 cycles to
+    1e-11 varies by about that much with the mesh)."""
+    announce("fig5 sweep")
+    stated = {}
+    with open(GOLDEN_FIG5) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                p, rho = line.split()
+                stated[int(p)] = float(rho)
+    meshes = {8: (4, 8, 16), 16: (4, 8, 12), 32: (4, 6, 8)}
+    res = {}
+    for rec in studies.run_fig5(orders=(8, 16, 32), meshes=meshes):
+        res[(rec["P"], rec["ne"])] = rec["rho"]
+    for P in (8, 16):
+        fine = [res[(P, ne)] for ne in meshes[P] if ne >= 8]
+        assert max(fine) <= 1.5 * min(fine), (P, fine)
+    for P in (16, 32):
+        got = res[(P, meshes[P][-1])]
+        assert stated[P] / 2 <= got <= 2 * stated[P], (P, got, stated[P])

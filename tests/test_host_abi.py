@@ -30,12 +30,20 @@ CASES = [
     dict(ne=(16, 16, 16), length=(1.0, 1.0, 1.0), P=8, overlap="rel", omega=0.08),
     dict(ne=(8, 8, 8), length=(16.0, 1.0, 1.0), P=16, overlap="max", omega=0.08),
     dict(ne=(5, 3, 4), length=(2.0, 1.0, 0.5), P=7, overlap="rel", omega=0.08),
+    # the GL basis: full face traces, N_O = 0 on the P = 2 level (0.08 dx),
+    # the 0.5 dx tie counted strictly, the N_O >= 1 floor, minimal overlap
+    dict(ne=(4, 4, 4), length=(1.0, 1.0, 1.0), P=8, overlap="rel", omega=0.08, basis="gl"),
+    dict(ne=(4, 4, 5), length=(2.0, 1.0, 0.5), P=4, overlap="rel", omega=0.5, basis="gl"),
+    dict(ne=(4, 4, 4), length=(1.0, 1.0, 1.0), P=16, overlap="rel", omega=0.09, basis="gl", overlap_floor=1),
+    dict(ne=(4, 4, 4), length=(1.0, 1.0, 1.0), P=4, overlap="min", basis="gl"),
+    dict(ne=(4, 4, 4), length=(8.0, 1.0, 1.0), P=7, overlap="max", omega=0.08, basis="gl"),
 ]
 
 
 def _hier(kw):
     return oracle.Hierarchy(kw["ne"], kw["length"], kw["P"], overlap=kw["overlap"],
-                            omega=kw.get("omega", 0.08))
+                            omega=kw.get("omega", 0.08), basis=kw.get("basis", "gll"),
+                            overlap_floor=kw.get("overlap_floor", 0))
 
 
 def _t(level, d, which, kw):
@@ -114,6 +122,9 @@ BAD = [
     dict(precond_bits=8),
     dict(ne=(49, 4, 4)),                # beyond the coarse solve's level-0 planes (ne_d <= 48)
     dict(ne=(3, 3, 3), length=(16.0, 1.0, 1.0), overlap="max", omega=0.08, P=4),  # whole-neighbour overlap needs ne >= 4
+    dict(basis=2),                      # unknown basis
+    dict(basis="gl", ne=(4, 3, 4)),     # GL: at least 4 elements per direction
+    dict(overlap="rel", overlap_floor=3),
 ]
 
 
