@@ -268,6 +268,19 @@ int sipg_autotune(sipg_ctx *c, int reps);
  * and subdomains per workgroup of the local-solve kernel; 0 = the built-in
  * default (not tuned, or the level has no such kernel). */
 int sipg_tuning(const sipg_ctx *c, int level, int bits, int *apply_epb, int *schwarz_spb);
+/* Sets the launch shapes of level `level` (>= 1, or -1 for the top) in
+ * precision `bits` (64, or 32 for a context whose preconditioner is not
+ * FP64): apply_epb elements per operator workgroup (0 = default, else
+ * 1..sipg_tuning_limits' first value) and schwarz_spb subdomains per
+ * local-solve workgroup (0 = default, else 1..its second value; only the
+ * compile-time-shape local solves take it).  The computed values do not
+ * depend on the shapes (only the partition of the fused partial sums does).
+ * Drops a captured preconditioner graph.  For restoring shapes tuned
+ * earlier (e.g. from a tuning cache); EINVAL for values out of range. */
+int sipg_set_tuning(sipg_ctx *c, int level, int bits, int apply_epb, int schwarz_spb);
+/* Largest values sipg_set_tuning accepts on that level (0 = the level has
+ * no choice of that shape). */
+int sipg_tuning_limits(const sipg_ctx *c, int level, int bits, int *max_apply_epb, int *max_schwarz_spb);
 
 /* Context options. */
 typedef enum {

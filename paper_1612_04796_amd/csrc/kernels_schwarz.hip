@@ -201,15 +201,31 @@ struct FdmShape {
   static constexpr int TILE = MZ * MY * RX;
   static constexpr int L1 = MY * MZ, L2 = MX * MZ, L3 = MX * MY;
   static constexpr int LINES = L1 > L2 ? (L1 > L3 ? L1 : L3) : (L2 > L3 ? L2 : L3);
-  // subdomains per workgroup: small workgroups (about three wavefronts)
-  // interleave best on a CU (measured against 2, 3 and 6 at m = 13)
+  // subdomains per workgroup by default: small workgroups (about three
+  // wavefronts) interleave best on a CU (measured against 2, 3 and 6 at
+  // m = 13)
   static constexpr int SPB = LINES >= 192 ? 1 : 192 / LINES;
+  // the most a launch may ask for (the autotuner tries 1 .. SPBMAX): up to 8
+  // subdomains, 1024 threads and 64 KiB of FP64 tile.  A partly filled last
+  // wavefront issues every instruction of a full one (144 lines of a 12^3
+  // subdomain fill 2.25 wavefronts; four subdomains fill 9 exactly).
+  static constexpr int SPB_LINES = 1024 / LINES > 8 ? 8 : 1024 / LINES;
+  static constexpr int SPB_LDS = (64 * 1024) / (TILE * 8 + 27 * 4);
+  static constexpr int SPBMAX0 = SPB_LINES < SPB_LDS ? SPB_LINES : SPB_LDS;
+  static constexpr int SPBMAX = SPBMAX0 > SPB ? SPBMAX0 : SPB;
   static constexpr int MMAX = MX > MY ? (MX > MZ ? MX : MZ) : (MY > MZ ? MY : MZ);
   // lines per thread in every phase (more lines per thread share each table
   // entry but lower the occupancy, which costs more: measured slower)
   static constexpr int LPT = 1;
-  static constexpr int NTH0 = ((SPB * LINES + LPT - 1) / LPT + 63) / 64 * 64;
+  static constexpr int NTH0 = ((SPBMAX * LINES + LPT - 1) / LPT + 63) / 64 * 64;
   static constexpr int NTH = NTH0 > 1024 ? 1024 : NTH0;
+  // threads of a launch with spb subdomains per workgroup
+  static int threads(int spb) {
+    const int v = ((spb * LINES + LPT - 1) / LPT + 63) / 64 * 64;
+    return v > 1024 ? 1024 : v;
+  }
+  // dynamic LDS bytes: the spb tiles, then the 27 neighbour indices per subdomain
+  static size_t lds(int spb, size_t eb) { return (size_t)spb * TILE * eb + (size_t)spb * 27 * sizeof(int); }
 };
 
 // Even-odd 1D transforms.  The subdomain pair (L_s, M_s) and the hat weights
@@ -311,18 +327,20 @@ __device__ __forceinline__ void eo_bwd(const T (&y)[K][M], T (&x)[K][M], const T
   }
 }
 
-// spb: subdomains per workgroup (at most Sh::SPB).  In every phase thread t
-// owns lines t, t + blockDim.x, ... (Sh::LPT of them), reads them from the
-// tile and writes them back in place; lines of one phase are disjoint.
+// spb: subdomains per workgroup (at most Sh::SPBMAX); the tiles live in
+// dynamic LDS (Sh::lds(spb) bytes).  In every phase thread t owns lines t,
+// t + blockDim.x, ... (Sh::LPT of them), reads them from the tile and writes
+// them back in place; lines of one phase are disjoint.
 template <typename T, int N, int MX, int MY, int MZ>
 __global__ void __launch_bounds__((FdmShape<MX, MY, MZ>::NTH))
 schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restrict__ C, int spb) {
   using Sh = FdmShape<MX, MY, MZ>;
-  constexpr int RX = Sh::RX, VOL = Sh::VOL, TILE = Sh::TILE, SPB = Sh::SPB, K = Sh::LPT;
+  constexpr int RX = Sh::RX, VOL = Sh::VOL, TILE = Sh::TILE, K = Sh::LPT;
   constexpr int NOX = (MX - N) / 2, NOY = (MY - N) / 2, NOZ = (MZ - N) / 2;
   constexpr int N3 = N * N * N;
-  __shared__ T t[SPB * TILE];
-  __shared__ int nb[SPB * 27];  // the 27 elements around each subdomain's core
+  extern __shared__ __align__(16) unsigned char fdm_smem[];
+  T *t = reinterpret_cast<T *>(fdm_smem);
+  int *nb = reinterpret_cast<int *>(fdm_smem + (size_t)spb * TILE * sizeof(T));  // 27 elements around each core
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int s0 = blk * spb;
   const int nsub = min(spb, g.E - s0);
@@ -632,11 +650,18 @@ hipError_t launch_assemble_fixed(const SchwarzLaunch<T> &a, hipStream_t st) {
 template <typename T, int N, int MX, int MY, int MZ>
 hipError_t launch_fixed(const SchwarzLaunch<T> &a, hipStream_t st) {
   using Sh = FdmShape<MX, MY, MZ>;
-  static_assert(Sh::SPB * Sh::TILE * sizeof(T) <= 160 * 1024, "subdomain tile exceeds LDS");
-  const int spb = a.spb > 0 ? std::min(a.spb, Sh::SPB) : Sh::SPB;
+  static_assert(Sh::SPB * Sh::TILE * sizeof(T) + Sh::SPB * 27 * sizeof(int) <= 160 * 1024,
+                "subdomain tile exceeds LDS");
+  const int spb = a.spb > 0 ? std::min(a.spb, Sh::SPBMAX) : Sh::SPB;
   const int nblk = (a.mesh.E + spb - 1) / spb;
-  const int nth = std::min(Sh::NTH, ((spb * Sh::LINES + Sh::LPT - 1) / Sh::LPT + 63) / 64 * 64);
-  schwarz_fdm_fixed<T, N, MX, MY, MZ><<<nblk, nth, 0, st>>>(a.mesh, a.tabs, a.r, a.C, spb);
+  const int nth = Sh::threads(spb);
+  const size_t shm = Sh::lds(spb, sizeof(T));
+  if (shm > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)schwarz_fdm_fixed<T, N, MX, MY, MZ>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  schwarz_fdm_fixed<T, N, MX, MY, MZ><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.r, a.C, spb);
   return hipGetLastError();
 }
 
@@ -668,7 +693,7 @@ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 int schwarz_fixed_max_spb(int n, const int m[3]) {
 #define SIPG_MAXSPB(NN, AX, AY, AZ) \
-  if (n == NN && m[0] == AX && m[1] == AY && m[2] == AZ) return FdmShape<AX, AY, AZ>::SPB;
+  if (n == NN && m[0] == AX && m[1] == AY && m[2] == AZ) return FdmShape<AX, AY, AZ>::SPBMAX;
   SIPG_FDM_SHAPES(SIPG_MAXSPB)
 #undef SIPG_MAXSPB
   return 0;

@@ -1131,6 +1131,22 @@ size_t context_bytes(const sipg::HierarchyHost &H) {
 
 }  // namespace
 
+namespace {
+
+// level index (1..L) of `level` (-1 = top), or 0 if invalid
+int level_arg(const sipg_ctx *c, int level) {
+  const int l = level == -1 ? c->L : level;
+  return (l >= 1 && l <= c->L) ? l : 0;
+}
+
+template <typename T>
+void tuning_limits_of(const sipg_ctx *c, const LevelTabs<T> &t, int *max_epb, int *max_spb) {
+  *max_epb = sipg::apply_max_epb(t.n);
+  *max_spb = mfma_of(c, t) ? 0 : sipg::schwarz_fixed_max_spb(t.n, t.schwarz.m);
+}
+
+}  // namespace
+
 extern "C" {
 
 void sipg_default_params(sipg_params *p) {
@@ -1517,6 +1533,45 @@ int sipg_tuning(const sipg_ctx *c, int level, int bits, int *apply_epb, int *sch
     *schwarz_spb = c->t32[l].schwarz_spb;
   }
   return SIPG_OK;
+}
+
+int sipg_tuning_limits(const sipg_ctx *c, int level, int bits, int *max_apply_epb, int *max_schwarz_spb) {
+  if (!c || !max_apply_epb || !max_schwarz_spb) return fail(SIPG_EINVAL, "null argument");
+  if (bits != 64 && bits != 32) return fail(SIPG_EINVAL, "bits must be 64 or 32");
+  if (bits == 32 && c->H.prm.precond_bits == 64) return fail(SIPG_EINVAL, "an FP64 context has no FP32 levels");
+  const int l = level_arg(c, level);
+  if (!l) return fail(SIPG_EINVAL, "level must be in 1..L or -1");
+  if (bits == 64)
+    tuning_limits_of<double>(c, c->t64[l], max_apply_epb, max_schwarz_spb);
+  else
+    tuning_limits_of<float>(c, c->t32[l], max_apply_epb, max_schwarz_spb);
+  return SIPG_OK;
+}
+
+int sipg_set_tuning(sipg_ctx *c, int level, int bits, int apply_epb, int schwarz_spb) {
+  int me = 0, ms = 0;
+  const int st = sipg_tuning_limits(c, level, bits, &me, &ms);
+  if (st != SIPG_OK) return st;
+  if (apply_epb < 0 || apply_epb > std::max(me, 0) || (apply_epb > 0 && me < 1))
+    return fail(SIPG_EINVAL, "apply_epb out of range for this level");
+  if (schwarz_spb < 0 || schwarz_spb > std::max(ms, 0) || (schwarz_spb > 0 && ms < 1))
+    return fail(SIPG_EINVAL, "schwarz_spb out of range for this level");
+  return guarded([&]() {
+    if (c->precond_graph) {
+      check(hipStreamSynchronize(c->stream), "sync");
+      check(hipGraphExecDestroy(c->precond_graph), "graph");
+      c->precond_graph = nullptr;
+    }
+    const int l = level_arg(c, level);
+    if (bits == 64) {
+      c->t64[l].apply_epb = apply_epb;
+      c->t64[l].schwarz_spb = schwarz_spb;
+    } else {
+      c->t32[l].apply_epb = apply_epb;
+      c->t32[l].schwarz_spb = schwarz_spb;
+    }
+    return (int)SIPG_OK;
+  });
 }
 
 int sipg_set_option(sipg_ctx *c, int option, int value) {

@@ -27,7 +27,7 @@ EXPORTS = (
     "sipg_level_info", "sipg_rhs_fourier", "sipg_apply_A", "sipg_residual", "sipg_schwarz",
     "sipg_smooth", "sipg_restrict", "sipg_prolong_add", "sipg_coarse_solve", "sipg_vcycle",
     "sipg_precond", "sipg_mg_solve", "sipg_pcg_solve", "sipg_residual_history",
-    "sipg_last_error", "sipg_host_table", "sipg_time_kernel", "sipg_autotune", "sipg_tuning",
+    "sipg_last_error", "sipg_host_table", "sipg_time_kernel", "sipg_autotune", "sipg_tuning", "sipg_set_tuning", "sipg_tuning_limits",
     "sipg_set_option", "sipg_traced_kernel_ms", "sipg_ndof", "sipg_rhs_mean", "sipg_device_bytes",
     "sipg_schwarz_noalloc",
     "sipg_server_create", "sipg_server_submit", "sipg_server_progress", "sipg_server_status",
@@ -106,6 +106,8 @@ def lib():
             "sipg_time_kernel": (c_int, [vp, c_int, c_int, c_int, c_int, P(c_double)]),
             "sipg_autotune": (c_int, [vp, c_int]),
             "sipg_tuning": (c_int, [vp, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
+            "sipg_set_tuning": (c_int, [vp, c_int, c_int, c_int, c_int]),
+            "sipg_tuning_limits": (c_int, [vp, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
             "sipg_set_option": (c_int, [vp, c_int, c_int]),
             "sipg_traced_kernel_ms": (c_int, [vp, P(c_double), P(c_int)]),
             "sipg_server_create": (c_int, [ctypes.c_size_t, c_int, P(vp)]),
@@ -338,6 +340,17 @@ class Solver:
         """(elements per workgroup, subdomains per workgroup) in use; 0 = default."""
         a, b = ctypes.c_int(), ctypes.c_int()
         _check(lib().sipg_tuning(self._h, level, bits, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def set_tuning(self, level=-1, bits=64, apply_epb=0, schwarz_spb=0):
+        """Set the launch shapes of one level (see sipg_set_tuning); 0 = default."""
+        _check(lib().sipg_set_tuning(self._h, level, bits, int(apply_epb), int(schwarz_spb)))
+
+    def tuning_limits(self, level=-1, bits=64):
+        """(largest elements per operator workgroup, largest subdomains per
+        local-solve workgroup) accepted by set_tuning; 0 = no choice."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(lib().sipg_tuning_limits(self._h, level, bits, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
     def set_option(self, option, value):

@@ -83,3 +83,38 @@ def test_kernel_trace_counts_launches_and_keeps_results():
     assert s.traced_kernel_ms()[1] == 0
     with pytest.raises(sipg.SipgError):
         s.set_option(1, 7)
+
+
+@pytest.mark.parametrize("ne,P,bits", [((3, 4, 5), 7, 64), ((5, 3, 4), 7, 32), ((4, 3, 5), 8, 64), ((3, 5, 4), 4, 32)])
+def test_every_launch_shape_gives_the_same_values(ne, P, bits):
+    """sipg_set_tuning: every accepted number of subdomains per local-solve
+    workgroup (up to several per workgroup and a ragged last workgroup on
+    these meshes) and of elements per operator workgroup computes the same
+    preconditioner, bitwise, as the defaults; values beyond the limits are
+    refused."""
+    announce("set_tuning", ne, P, bits)
+    h, s = pair(ne, (1.0, 1.0, 1.0), P, overlap="rel", precond_bits=bits)
+    k, phi, amp = fourier_modes(3, 3)
+    f = dev(oracle.fourier_rhs(k, phi, amp, h))
+    tb = 64 if bits == 64 else 32
+
+    def z_of():
+        z = zeros(h.ndof())
+        s.precond(f, z)
+        return host(z)
+
+    ref = z_of()
+    limits = {lv: s.tuning_limits(lv, tb) for lv in range(1, h.L + 1)}
+    most = max(ms for _, ms in limits.values())
+    assert most >= 1
+    for spb in range(1, most + 1):
+        for lv, (me, ms) in limits.items():
+            s.set_tuning(lv, tb, min(me, 1 + spb % max(me, 1)) if me else 0, min(spb, ms))
+        assert np.array_equal(z_of(), ref), spb
+    for lv, (me, ms) in limits.items():
+        assert s.tuning(lv, tb)[1] == min(most, ms)
+        with pytest.raises(sipg.SipgError):
+            s.set_tuning(lv, tb, me + 1, 0)
+        with pytest.raises(sipg.SipgError):
+            s.set_tuning(lv, tb, 0, ms + 1)
+    s.close()

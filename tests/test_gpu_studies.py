@@ -127,6 +127,7 @@ def test_aniso_study_trends():
     assert all(v is not None for v in n10), n10            # converges up to AR = 48
     assert n10[0] <= 6 and n10[1] <= n10[0] + 1, n10       # nearly constant to AR = 8
     assert n10[1:] == sorted(n10[1:]), n10                 # grows beyond
+    assert n10[2] <= 13, n10   # the paper's largest count for this method, here up to AR = 16
 
 
 def test_fig5_mesh_independence_and_rates():
