@@ -315,23 +315,83 @@ def workload_rhs(wl):
     return b, (k, phi, amp)
 
 
-def serving_run(nreq, seed, log_every=4):
-    """Serving stream: heterogeneous requests (4^3..24^3 elements, P in
-    {2,4,8,16,32}, aspect ratio 1..8, "max" overlap, FP32-preconditioned
-    FP64 flexible CG to 1e-10) with Poisson arrivals at the rate that gives
-    about 70 % utilisation.  The mean service time is measured first by
-    serving the same requests one at a time; then the stream is replayed in
-    real time into a server with 8 slots (same-order requests that are ready
-    together share their operator launches).  Latency = finish - arrival."""
+def _replay(reqs, arrivals, submit, budget, options):
+    """Replays a request stream in real time into a server with 8 slots and
+    the given options; latency = finish - arrival."""
+    import numpy as np
+    from paper_1612_04796_amd import sipg
+
+    nreq = len(reqs)
+    lat, ndof, iters = [], [], []
+    with sipg.Server(budget, max_active=8) as srv:
+        for opt, val in options.items():
+            srv.set_option(opt, val)
+        t0 = time.perf_counter()
+        ids = [None] * nreq
+        sub_wall = [0.0] * nreq
+        nxt = 0
+        finished = 0
+        while finished < nreq:
+            now = time.perf_counter() - t0
+            while nxt < nreq and arrivals[nxt] <= now:
+                ids[nxt] = submit(srv, reqs[nxt])
+                sub_wall[nxt] = time.perf_counter() - t0
+                nxt += 1
+            wait = 1 if nxt < nreq else 50
+            srv.progress(wait_ms=wait)
+            finished = sum(1 for i in range(nxt) if srv.status(ids[i])["state"] in (sipg.REQ_DONE, sipg.REQ_FAILED))
+        t_end = time.perf_counter() - t0
+        fused_launches, fused_requests = srv.stats()
+        cohort_cycles, cohort_requests = srv.smooth_stats()
+        for i, rid in enumerate(ids):
+            st = srv.status(rid)
+            if st["state"] != sipg.REQ_DONE or st["relres"] > 1e-10:
+                raise RuntimeError(f"request {i} did not converge: {st}")
+            # server clock: submit -> done, plus the wait between arrival and submit
+            lat.append(st["t_done"] - st["t_submit"] + (sub_wall[i] - arrivals[i]))
+            ndof.append(st["ndof"])
+            iters.append(st["iters"])
+    lat = np.array(lat)
+    return {
+        "p50_latency_ms": float(1e3 * np.percentile(lat, 50)),
+        "p99_latency_ms": float(1e3 * np.percentile(lat, 99)),
+        "max_latency_ms": float(1e3 * lat.max()),
+        "unknowns_per_s": float(sum(ndof) / t_end),
+        "makespan_s": t_end,
+        "total_unknowns": int(sum(ndof)),
+        "iterations": iters,
+        "batched_operator_launches": fused_launches,
+        "requests_in_batched_launches": fused_requests,
+        "cohort_vcycles": cohort_cycles,
+        "requests_in_cohort_vcycles": cohort_requests,
+    }
+
+
+def serving_run(nreq, seed, stream="mixed", variants=None, burst=False):
+    """Serving stream, FP32-preconditioned FP64 flexible CG to 1e-10.
+    stream "mixed": heterogeneous requests (4^3..24^3 elements, P in
+    {2,4,8,16,32}, aspect ratio 1..8, "max" overlap); "same_order": small
+    order-8 requests (4..7 elements per direction, 8 % overlap) that all share
+    one preconditioner signature.  Poisson arrivals at the rate that gives
+    about 70 % utilisation: the mean service time is measured first by serving
+    the same requests one at a time; then the stream is replayed in real time
+    into a server with 8 slots, once per variant (name -> server options), at
+    the same arrival times; with burst, also with every request submitted at
+    once (the makespan then measures the saturated throughput)."""
     import numpy as np
     import torch
     from paper_1612_04796_amd import sipg
-    from paper_1612_04796_amd.workloads import fourier_modes, serving_stream
+    from paper_1612_04796_amd.workloads import fourier_modes, serving_stream, serving_stream_same_order
 
     free, _total = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
-    reqs = serving_stream(seed, nreq, 1.0)
-    common = dict(overlap="max", omega=0.08, precond_bits=32)
+    if stream == "mixed":
+        reqs = serving_stream(seed, nreq, 1.0)
+        common = dict(overlap="max", omega=0.08, precond_bits=32)
+    else:
+        reqs = serving_stream_same_order(seed, nreq, 1.0)
+        common = dict(overlap="rel", omega=0.08, precond_bits=32)
+    variants = variants or {"default": {}}
 
     def submit(srv, r):
         k, phi, amp = fourier_modes(r["rhs_seed"], 3)
@@ -354,50 +414,30 @@ def serving_run(nreq, seed, log_every=4):
     qps = 0.7 / mean_s
     # arrival times: the stream's exponential gaps rescaled to this rate
     arrivals = [r["t_arrival"] / qps for r in reqs]
-    log(f"serving: {nreq} requests, mean service {1e3 * mean_s:.2f} ms alone, replay at {qps:.1f} req/s")
-    lat, ndof, iters, relres = [], [], [], []
-    with sipg.Server(budget, max_active=8) as srv:
-        t0 = time.perf_counter()
-        ids = [None] * nreq
-        sub_wall = [0.0] * nreq
-        nxt = 0
-        finished = 0
-        while finished < nreq:
-            now = time.perf_counter() - t0
-            while nxt < nreq and arrivals[nxt] <= now:
-                ids[nxt] = submit(srv, reqs[nxt])
-                sub_wall[nxt] = time.perf_counter() - t0
-                nxt += 1
-            wait = 1 if nxt < nreq else 50
-            _a, _q, c = srv.progress(wait_ms=wait)
-            finished = sum(1 for i in range(nxt) if srv.status(ids[i])["state"] in (sipg.REQ_DONE, sipg.REQ_FAILED))
-        t_end = time.perf_counter() - t0
-        fused_launches, fused_requests = srv.stats()
-        for i, rid in enumerate(ids):
-            st = srv.status(rid)
-            if st["state"] != sipg.REQ_DONE or st["relres"] > 1e-10:
-                raise RuntimeError(f"request {i} did not converge: {st}")
-            # server clock: submit -> done, plus the wait between arrival and submit
-            lat.append(st["t_done"] - st["t_submit"] + (sub_wall[i] - arrivals[i]))
-            ndof.append(st["ndof"])
-            iters.append(st["iters"])
-    lat = np.array(lat)
-    return {
+    log(f"serving ({stream}): {nreq} requests, mean service {1e3 * mean_s:.2f} ms alone, replay at {qps:.1f} req/s")
+    out = {
+        "stream": stream,
         "requests": nreq,
         "qps": qps,
         "utilisation_target": 0.7,
         "mean_service_alone_ms": 1e3 * mean_s,
-        "p50_latency_ms": float(1e3 * np.percentile(lat, 50)),
-        "p99_latency_ms": float(1e3 * np.percentile(lat, 99)),
-        "max_latency_ms": float(1e3 * lat.max()),
-        "unknowns_per_s": float(sum(ndof) / t_end),
-        "makespan_s": t_end,
-        "total_unknowns": int(sum(ndof)),
-        "iterations": iters,
         "precision": "FP32 preconditioner, FP64 flexible CG",
-        "batched_operator_launches": fused_launches,
-        "requests_in_batched_launches": fused_requests,
     }
+    for name, options in variants.items():
+        res = _replay(reqs, arrivals, submit, budget, options)
+        log(f"serving ({stream}, {name}): p50 {res['p50_latency_ms']:.2f} ms, p99 {res['p99_latency_ms']:.2f} ms, "
+            f"{res['unknowns_per_s']:.4g} unknowns/s, {res['cohort_vcycles']} cohort V-cycles")
+        if burst:
+            # every request at once: the server's throughput when saturated
+            res["burst"] = _replay(reqs, [0.0] * nreq, submit, budget, options)
+            bu = res["burst"]
+            log(f"serving ({stream}, {name}, all at once): makespan {1e3 * bu['makespan_s']:.2f} ms, "
+                f"{bu['unknowns_per_s']:.4g} unknowns/s, {bu['cohort_vcycles']} cohort V-cycles")
+        if len(variants) == 1:
+            out.update(res)
+        else:
+            out[name] = res
+    return out
 
 
 def main():
@@ -579,11 +619,18 @@ def main():
         del b4
 
     if args.serving_requests > 0:
+        from paper_1612_04796_amd import sipg as _s
         log("serving stream ...")
         detail["serving"] = serving_run(args.serving_requests, seed=5)
         sv = detail["serving"]
         log(f"serving: p50 {sv['p50_latency_ms']:.2f} ms, p99 {sv['p99_latency_ms']:.2f} ms, "
             f"{sv['unknowns_per_s']:.4g} unknowns/s over {sv['makespan_s']:.2f} s")
+        # one order, one preconditioner signature: with and without the
+        # cohort V-cycles (segmented local solves and assemblies)
+        detail["serving_same_order"] = serving_run(
+            args.serving_requests, seed=6, stream="same_order",
+            variants={"cohort_vcycles": {_s.SERVER_FUSE_SMOOTH: 1},
+                      "no_cohort_vcycles": {_s.SERVER_FUSE_SMOOTH: 0}}, burst=True)
 
     out = {
         "metric": METRIC,

@@ -281,6 +281,16 @@ int sipg_set_tuning(sipg_ctx *c, int level, int bits, int apply_epb, int schwarz
 /* Largest values sipg_set_tuning accepts on that level (0 = the level has
  * no choice of that shape). */
 int sipg_tuning_limits(const sipg_ctx *c, int level, int bits, int *max_apply_epb, int *max_schwarz_spb);
+/* The process-wide tuning cache (the choices sipg_autotune made, keyed by
+ * precision, order, subdomain shape, element count and local-solve kind)
+ * as a JSON file: saved to `path` (written to path.tmp, then renamed), or
+ * merged from such a file (nloaded: entries read, may be null).  Later
+ * sipg_autotune calls and served requests take cached choices without
+ * timing.  EINVAL for an unreadable or malformed file (then nothing is
+ * merged).  The serving loop loads the file named by the environment
+ * variable SIPG_TUNING_CACHE when it is created. */
+int sipg_tuning_cache_save(const char *path);
+int sipg_tuning_cache_load(const char *path, int *nloaded);
 
 /* Context options. */
 typedef enum {
@@ -361,11 +371,28 @@ int sipg_server_fetch(sipg_server *s, int64_t id, double *u, void *hip_stream);
  * member's preconditioner; the rest of the members' steps follows on that
  * stream, and members stay in phase from step to step.  Every member computes exactly what
  * it computes alone.  0: every request steps on its own stream only. */
-typedef enum { SIPG_SERVER_FUSE_APPLY = 0 } sipg_server_option;
+/* SIPG_SERVER_FUSE_SMOOTH (default 1): within such a group, the members
+ * whose preconditioners have the same signature (precision, level orders,
+ * subdomain shapes and smoothing counts, every level on a compile-time
+ * local-solve shape) run their preconditioner V-cycles as one cohort on the
+ * group's stream: level by level, the Schwarz local solves of all members
+ * in one launch and their assemblies in one launch, the residuals,
+ * transfers and coarse solves per member.  Every member again computes
+ * exactly what it computes alone.  0: each member's V-cycle on its own
+ * stream.
+ * SIPG_SERVER_TUNE (default 1): launch shapes of admitted requests.  0: the
+ * built-in defaults; 1: the shapes the process-wide tuning cache holds for
+ * the request's levels (see sipg_tuning_cache_load; no timing); 2:
+ * sipg_autotune at admission (shapes already cached are taken without
+ * timing), and at sipg_server_destroy the cache is saved to the file named
+ * by SIPG_TUNING_CACHE, if set. */
+typedef enum { SIPG_SERVER_FUSE_APPLY = 0, SIPG_SERVER_FUSE_SMOOTH = 1, SIPG_SERVER_TUNE = 2 } sipg_server_option;
 int sipg_server_set_option(sipg_server *s, int option, int value);
 
 /* Fused operator launches so far and the requests they served. */
 int sipg_server_stats(const sipg_server *s, int64_t *fused_launches, int64_t *fused_requests);
+/* Cohort V-cycles (SIPG_SERVER_FUSE_SMOOTH) so far and the requests they served. */
+int sipg_server_smooth_stats(const sipg_server *s, int64_t *cohort_cycles, int64_t *cohort_requests);
 
 /* Waits for the device and frees everything the server holds. */
 int sipg_server_destroy(sipg_server *s);

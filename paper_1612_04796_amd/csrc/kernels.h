@@ -30,9 +30,9 @@ struct ApplyLaunch {
 template <typename T>
 hipError_t launch_apply(const ApplyLaunch<T> &a, hipStream_t st);
 
-// Several PLAIN applications of one order (n <= 17) and one elements-per-
-// workgroup choice in one launch (at most kMaxApplySegments): each computes
-// exactly what its own launch_apply would, partial sums included.
+// Several applications of one order (n <= 17), one mode and one elements-
+// per-workgroup choice in one launch (at most kMaxApplySegments): each
+// computes exactly what its own launch_apply would, partial sums included.
 constexpr int kMaxApplySegments = 8;
 // elements per workgroup a launch with ApplyLaunch::epb = epb uses
 int apply_launch_epb(int E, int n, int epb);
@@ -72,6 +72,10 @@ template <typename T, typename TC>
 hipError_t launch_prolong(const ProlongLaunch<T, TC> &a, hipStream_t st);
 template <typename T, typename TC>
 hipError_t launch_prolong_large(const ProlongLaunch<T, TC> &a, T *tmp, hipStream_t st);
+// Several prolongations of one order (n <= 17) in one launch (at most
+// kMaxApplySegments), each computed as by its own launch_prolong.
+template <typename T, typename TC>
+hipError_t launch_prolong_segments(const ProlongLaunch<T, TC> *a, int n, hipStream_t st);
 
 // One weighted additive Schwarz correction: C[s] = W_s A_ss^{-1} R_s r for
 // every subdomain s (m_x*m_y*m_z values per subdomain, layout [s][c][b][a]),
@@ -111,6 +115,14 @@ struct SchwarzLaunch {
 // Largest subdomains-per-workgroup of the compile-time-shape local-solve
 // kernel for (n, m) (0 when there is none).
 int schwarz_fixed_max_spb(int n, const int m[3]);
+// Local solves and assembly of up to kMaxApplySegments levels of the same
+// subdomain shape (one per solve) in one launch each; every subdomain and
+// node is computed as in launch_schwarz.  Only the compile-time-shape
+// kernels: segments_supported says whether a level has one.
+template <typename T>
+bool schwarz_segments_supported(const SchwarzLaunch<T> &a);
+template <typename T>
+hipError_t launch_schwarz_segments(const SchwarzLaunch<T> *a, int n, hipStream_t st);
 template <typename T>
 hipError_t launch_schwarz(const SchwarzLaunch<T> &a, hipStream_t st);
 // the two phases separately: local solves into C, then the assembly into u

@@ -347,9 +347,9 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
 
 // u_f += (J x J x J)(u_c - mean), element by element; J is NF x NC.
 template <typename T, typename TC, int NF>
-__global__ void __launch_bounds__(ApplyShape<NF>::NTH)
-prolong_kernel(int E, const T *__restrict__ J, const TC *__restrict__ uc, const double *__restrict__ mean_partials,
-               int n_partials, double mean_scale, T *__restrict__ uf) {
+__device__ __forceinline__ void prolong_body(int E, const T *__restrict__ J, const TC *__restrict__ uc,
+                                             const double *__restrict__ mean_partials, int n_partials,
+                                             double mean_scale, T *__restrict__ uf, int blk) {
   using Sh = ApplyShape<NF>;
   constexpr int NC = coarse_n(NF);
   constexpr int NF2 = NF * NF, NF3 = NF2 * NF, NC2 = NC * NC, NC3 = NC2 * NC, EPB = Sh::EPB;
@@ -357,7 +357,6 @@ prolong_kernel(int E, const T *__restrict__ J, const TC *__restrict__ uc, const 
   T *s0 = reinterpret_cast<T *>(smem_raw);  // EPB * NC3  : coarse element
   T *s1 = s0 + EPB * NC3;                   // EPB * NC2 * NF : after x
   T *s2 = s1 + EPB * NC2 * NF;              // EPB * NC * NF2 : after y
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int e0 = blk * EPB;
   const int nloc = min(EPB, E - e0);
   const int t = threadIdx.x;
@@ -417,6 +416,36 @@ prolong_kernel(int E, const T *__restrict__ J, const TC *__restrict__ uc, const 
       o[k * NF2] += acc;
     }
   }
+}
+
+template <typename T, typename TC, int NF>
+__global__ void __launch_bounds__(ApplyShape<NF>::NTH)
+prolong_kernel(int E, const T *__restrict__ J, const TC *__restrict__ uc, const double *__restrict__ mean_partials,
+               int n_partials, double mean_scale, T *__restrict__ uf) {
+  prolong_body<T, TC, NF>(E, J, uc, mean_partials, n_partials, mean_scale, uf, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Prolongations of one order from several solves in one launch (segments
+// as in ApplySegs: each numbered and mapped as in its own launch)
+template <typename T, typename TC>
+struct ProlongSeg {
+  ProlongLaunch<T, TC> a;
+  int blk0, nblk;
+};
+template <typename T, typename TC>
+struct ProlongSegs {
+  ProlongSeg<T, TC> s[kMaxApplySegments];
+  int n;
+};
+
+template <typename T, typename TC, int NF>
+__global__ void __launch_bounds__(ApplyShape<NF>::NTH) prolong_seg_kernel(ProlongSegs<T, TC> S) {
+  int k = 0;
+  const int b = blockIdx.x;
+  while (k + 1 < S.n && b >= S.s[k + 1].blk0) ++k;
+  const ProlongSeg<T, TC> &g = S.s[k];
+  prolong_body<T, TC, NF>(g.a.E, g.a.J, g.a.uc, g.a.mean_partials, g.a.n_partials, g.a.mean_scale, g.a.uf,
+                          xcd_block(b - g.blk0, g.nblk));
 }
 
 template <typename K>
@@ -486,6 +515,29 @@ hipError_t launch_apply_n(const ApplyLaunch<T> &a, hipStream_t st) {
 }
 
 template <typename T, typename TC, int NF>
+hipError_t launch_prolong_segments_n(const ProlongLaunch<T, TC> *a, int n, hipStream_t st) {
+  if constexpr (NF >= 3) {
+    using Sh = ApplyShape<NF>;
+    constexpr int NC = coarse_n(NF);
+    ProlongSegs<T, TC> S{};
+    S.n = n;
+    int blk = 0;
+    for (int k = 0; k < n; ++k) {
+      if (a[k].nf != NF || a[k].nc != NC) return hipErrorInvalidValue;
+      const int nblk = (a[k].E + Sh::EPB - 1) / Sh::EPB;
+      S.s[k] = ProlongSeg<T, TC>{a[k], blk, nblk};
+      blk += nblk;
+    }
+    const size_t shm = (size_t)Sh::EPB * (NC * NC * NC + NC * NC * NF + NC * NF * NF) * sizeof(T);
+    hipError_t e = allow_lds(prolong_seg_kernel<T, TC, NF>, shm);
+    if (e != hipSuccess) return e;
+    prolong_seg_kernel<T, TC, NF><<<blk, Sh::NTH, shm, st>>>(S);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, typename TC, int NF>
 hipError_t launch_prolong_n(const ProlongLaunch<T, TC> &a, hipStream_t st) {
   if constexpr (NF >= 3) {
     using Sh = ApplyShape<NF>;
@@ -520,13 +572,16 @@ hipError_t launch_segments_n(const ApplyLaunch<T> *a, int n, hipStream_t st) {
   using Sh = ApplyShape<N>;
   const bool dot = a[0].partial != nullptr;
   const int epb = launch_epb(a[0].mesh.E, N, a[0].epb);
+  const int mode = a[0].mode;
+  if (mode == APPLY_RESTRICT && (N < 3 || dot)) return hipErrorInvalidValue;
   ApplySegs<T> S{};
   S.n = n;
   int blk = 0;
   const bool gl = a[0].tabs.gl != 0;
   for (int k = 0; k < n; ++k) {
-    if (a[k].n != N || a[k].mode != APPLY_PLAIN || (a[k].partial != nullptr) != dot ||
-        launch_epb(a[k].mesh.E, N, a[k].epb) != epb || (a[k].tabs.gl != 0) != gl)
+    if (a[k].n != N || a[k].mode != mode || (a[k].partial != nullptr) != dot ||
+        launch_epb(a[k].mesh.E, N, a[k].epb) != epb || (a[k].tabs.gl != 0) != gl ||
+        (mode == APPLY_RESTRICT && a[k].nc != coarse_n(N)))
       return hipErrorInvalidValue;
     const int nblk = (a[k].mesh.E + epb - 1) / epb;
     S.s[k] = ApplySeg<T>{a[k].mesh, a[k].tabs, a[k].u, a[k].f, a[k].out, a[k].partial, a[k].J,
@@ -542,6 +597,18 @@ hipError_t launch_segments_n(const ApplyLaunch<T> *a, int n, hipStream_t st) {
     kernel<<<blk, nth, shm, st>>>(a0.mesh, a0.tabs, a0.u, a0.f, a0.out, a0.partial, a0.J, epb, false, false, S);
     return hipGetLastError();
   };
+  if (mode == APPLY_RESTRICT) {
+    if constexpr (N >= 3)
+      return gl ? go(apply_kernel<T, N, MODE_RESTRICT, false, true, true>)
+                : go(apply_kernel<T, N, MODE_RESTRICT, false, true, false>);
+    return hipErrorInvalidValue;
+  }
+  if (mode == APPLY_RESID) {
+    if (dot) return gl ? go(apply_kernel<T, N, MODE_RESID, true, true, true>)
+                       : go(apply_kernel<T, N, MODE_RESID, true, true, false>);
+    return gl ? go(apply_kernel<T, N, MODE_RESID, false, true, true>)
+              : go(apply_kernel<T, N, MODE_RESID, false, true, false>);
+  }
   if (dot) return gl ? go(apply_kernel<T, N, MODE_APPLY, true, true, true>)
                      : go(apply_kernel<T, N, MODE_APPLY, true, true, false>);
   return gl ? go(apply_kernel<T, N, MODE_APPLY, false, true, true>)
@@ -584,9 +651,25 @@ hipError_t launch_prolong(const ProlongLaunch<T, TC> &a, hipStream_t st) {
   }
 }
 
+template <typename T, typename TC>
+hipError_t launch_prolong_segments(const ProlongLaunch<T, TC> *a, int n, hipStream_t st) {
+  if (n < 1 || n > kMaxApplySegments) return hipErrorInvalidValue;
+  switch (a[0].nf) {
+#define CASE(NN) \
+  case NN: return launch_prolong_segments_n<T, TC, NN>(a, n, st);
+    SIPG_ORDER_CASES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_prolong_segments<double, double>(const ProlongLaunch<double, double> *, int, hipStream_t);
+template hipError_t launch_prolong_segments<float, float>(const ProlongLaunch<float, float> *, int, hipStream_t);
+template hipError_t launch_prolong_segments<float, double>(const ProlongLaunch<float, double> *, int, hipStream_t);
 template hipError_t launch_apply<double>(const ApplyLaunch<double> &, hipStream_t);
 template hipError_t launch_apply<float>(const ApplyLaunch<float> &, hipStream_t);
 template hipError_t launch_apply_segments<double>(const ApplyLaunch<double> *, int, hipStream_t);
+template hipError_t launch_apply_segments<float>(const ApplyLaunch<float> *, int, hipStream_t);
 template hipError_t launch_prolong<double, double>(const ProlongLaunch<double, double> &, hipStream_t);
 template hipError_t launch_prolong<float, float>(const ProlongLaunch<float, float> &, hipStream_t);
 template hipError_t launch_prolong<float, double>(const ProlongLaunch<float, double> &, hipStream_t);

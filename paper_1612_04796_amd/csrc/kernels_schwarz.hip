@@ -332,8 +332,8 @@ __device__ __forceinline__ void eo_bwd(const T (&y)[K][M], T (&x)[K][M], const T
 // t + blockDim.x, ... (Sh::LPT of them), reads them from the tile and writes
 // them back in place; lines of one phase are disjoint.
 template <typename T, int N, int MX, int MY, int MZ>
-__global__ void __launch_bounds__((FdmShape<MX, MY, MZ>::NTH))
-schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restrict__ C, int spb) {
+__device__ __forceinline__ void fdm_fixed_body(const Mesh &g, const SchwarzTabs<T> &tb, const T *__restrict__ r,
+                                               T *__restrict__ C, int spb, int blk) {
   using Sh = FdmShape<MX, MY, MZ>;
   constexpr int RX = Sh::RX, VOL = Sh::VOL, TILE = Sh::TILE, K = Sh::LPT;
   constexpr int NOX = (MX - N) / 2, NOY = (MY - N) / 2, NOZ = (MZ - N) / 2;
@@ -341,7 +341,6 @@ schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restr
   extern __shared__ __align__(16) unsigned char fdm_smem[];
   T *t = reinterpret_cast<T *>(fdm_smem);
   int *nb = reinterpret_cast<int *>(fdm_smem + (size_t)spb * TILE * sizeof(T));  // 27 elements around each core
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int s0 = blk * spb;
   const int nsub = min(spb, g.E - s0);
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -532,6 +531,48 @@ schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restr
   }
 }
 
+// One launch per level: workgroup blk (in the XCD-aware order) owns
+// subdomains blk*spb .. blk*spb + spb - 1.
+template <typename T, int N, int MX, int MY, int MZ>
+__global__ void __launch_bounds__((FdmShape<MX, MY, MZ>::NTH))
+schwarz_fdm_fixed(Mesh g, SchwarzTabs<T> tb, const T *__restrict__ r, T *__restrict__ C, int spb) {
+  fdm_fixed_body<T, N, MX, MY, MZ>(g, tb, r, C, spb, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Several levels of the same subdomain shape (one per solve of a serving
+// cohort) in one launch: segment k owns the consecutive workgroups
+// blk0 .. blk0 + nblk - 1, numbered and mapped within the segment exactly as
+// in its own launch, so every subdomain is computed as there.
+template <typename T>
+struct SchwarzSeg {
+  Mesh g;
+  SchwarzTabs<T> tb;
+  const T *r;
+  T *C;
+  const T *u_in;
+  T *u_out;
+  int blk0, nblk;
+};
+template <typename T>
+struct SchwarzSegs {
+  SchwarzSeg<T> s[kMaxApplySegments];
+  int n;
+};
+
+template <typename T>
+__device__ __forceinline__ const SchwarzSeg<T> &seg_of(const SchwarzSegs<T> &S, int b) {
+  int k = 0;
+  while (k + 1 < S.n && b >= S.s[k + 1].blk0) ++k;
+  return S.s[k];
+}
+
+template <typename T, int N, int MX, int MY, int MZ>
+__global__ void __launch_bounds__((FdmShape<MX, MY, MZ>::NTH))
+schwarz_fdm_fixed_seg(SchwarzSegs<T> S, int spb) {
+  const SchwarzSeg<T> &a = seg_of(S, (int)blockIdx.x);
+  fdm_fixed_body<T, N, MX, MY, MZ>(a.g, a.tb, a.r, a.C, spb, xcd_block((int)blockIdx.x - a.blk0, a.nblk));
+}
+
 // Candidate subdomains of a node along one direction: its own element's
 // (offset 0) and, where the overlap reaches it, the left or right
 // neighbour's.  With an overlap below half an element (2 NO < N) a node lies
@@ -588,8 +629,8 @@ struct AsmShape {
 };
 
 template <typename T, int N, int MX, int MY, int MZ>
-__global__ void __launch_bounds__(AsmShape<N>::NTH)
-schwarz_assemble_fixed(Mesh g, const T *__restrict__ C, const T *u_in, T *u_out) {
+__device__ __forceinline__ void assemble_fixed_body(const Mesh &g, const T *__restrict__ C, const T *u_in, T *u_out,
+                                                    int blk) {
   using Sh = AsmShape<N>;
   constexpr int N3 = Sh::N3, VOL = MX * MY * MZ;
   const int tid = threadIdx.x;
@@ -597,10 +638,10 @@ schwarz_assemble_fixed(Mesh g, const T *__restrict__ C, const T *u_in, T *u_out)
   if constexpr (Sh::WHOLE) {
     const int le = tid / N3;
     loc = tid - le * N3;
-    e = xcd_block(blockIdx.x, gridDim.x) * Sh::EPB + le;
+    e = blk * Sh::EPB + le;
     if (le >= Sh::EPB || e >= g.E) return;
   } else {
-    const int gi = xcd_block(blockIdx.x, gridDim.x) * Sh::NTH + tid;
+    const int gi = blk * Sh::NTH + tid;
     if (gi >= g.E * N3) return;
     e = gi / N3;
     loc = gi - e * N3;
@@ -635,6 +676,19 @@ schwarz_assemble_fixed(Mesh g, const T *__restrict__ C, const T *u_in, T *u_out)
 #pragma unroll
       for (int xc = 0; xc < KX; ++xc) sum += v[zc][yc][xc];
   u_out[idx] = base + sum;
+}
+
+template <typename T, int N, int MX, int MY, int MZ>
+__global__ void __launch_bounds__(AsmShape<N>::NTH)
+schwarz_assemble_fixed(Mesh g, const T *__restrict__ C, const T *u_in, T *u_out) {
+  assemble_fixed_body<T, N, MX, MY, MZ>(g, C, u_in, u_out, xcd_block(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int N, int MX, int MY, int MZ>
+__global__ void __launch_bounds__(AsmShape<N>::NTH)
+schwarz_assemble_fixed_seg(SchwarzSegs<T> S) {
+  const SchwarzSeg<T> &a = seg_of(S, (int)blockIdx.x);
+  assemble_fixed_body<T, N, MX, MY, MZ>(a.g, a.C, a.u_in, a.u_out, xcd_block((int)blockIdx.x - a.blk0, a.nblk));
 }
 
 template <typename T, int N, int MX, int MY, int MZ>
@@ -685,6 +739,56 @@ hipError_t launch_fixed_if_any(const SchwarzLaunch<T> &a, hipStream_t st, bool &
 #undef SIPG_TRY
   done = false;
   return hipSuccess;
+}
+
+// Segmented launches: the same compile-time shape for every segment, the
+// first segment's subdomains-per-workgroup for all (a subdomain's values do
+// not depend on it).
+template <typename T, int N, int MX, int MY, int MZ>
+hipError_t launch_fixed_segments(const SchwarzLaunch<T> *a, int n, hipStream_t st) {
+  using Sh = FdmShape<MX, MY, MZ>;
+  const int spb = a[0].spb > 0 ? std::min(a[0].spb, Sh::SPBMAX) : Sh::SPB;
+  SchwarzSegs<T> S{};
+  S.n = n;
+  int blk = 0;
+  for (int k = 0; k < n; ++k) {
+    const int nblk = (a[k].mesh.E + spb - 1) / spb;
+    S.s[k] = SchwarzSeg<T>{a[k].mesh, a[k].tabs, a[k].r, a[k].C, a[k].u_in, a[k].u_out, blk, nblk};
+    blk += nblk;
+  }
+  const size_t shm = Sh::lds(spb, sizeof(T));
+  if (shm > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)schwarz_fdm_fixed_seg<T, N, MX, MY, MZ>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  schwarz_fdm_fixed_seg<T, N, MX, MY, MZ><<<blk, Sh::threads(spb), shm, st>>>(S, spb);
+  return hipGetLastError();
+}
+
+template <typename T, int N, int MX, int MY, int MZ>
+hipError_t launch_assemble_fixed_segments(const SchwarzLaunch<T> *a, int n, hipStream_t st) {
+  using Sh = AsmShape<N>;
+  SchwarzSegs<T> S{};
+  S.n = n;
+  int blk = 0;
+  for (int k = 0; k < n; ++k) {
+    if ((int64_t)a[k].mesh.E * MX * MY * MZ >= (int64_t)1 << 31) return hipErrorInvalidValue;
+    const int nblk = Sh::WHOLE ? (a[k].mesh.E + Sh::EPB - 1) / Sh::EPB
+                               : (int)(((int64_t)a[k].mesh.E * Sh::N3 + Sh::NTH - 1) / Sh::NTH);
+    S.s[k] = SchwarzSeg<T>{a[k].mesh, a[k].tabs, a[k].r, a[k].C, a[k].u_in, a[k].u_out, blk, nblk};
+    blk += nblk;
+  }
+  schwarz_assemble_fixed_seg<T, N, MX, MY, MZ><<<blk, Sh::NTH, 0, st>>>(S);
+  return hipGetLastError();
+}
+
+bool fixed_shape(int n, const int m[3]) {
+#define SIPG_IS(NN, AX, AY, AZ) \
+  if (n == NN && m[0] == AX && m[1] == AY && m[2] == AZ) return true;
+  SIPG_FDM_SHAPES(SIPG_IS)
+#undef SIPG_IS
+  return false;
 }
 
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
@@ -771,11 +875,43 @@ hipError_t launch_schwarz(const SchwarzLaunch<T> &a, hipStream_t st) {
   return launch_schwarz_assemble<T>(a, st);
 }
 
+template <typename T>
+bool schwarz_segments_supported(const SchwarzLaunch<T> &a) {
+  const int *m = a.tabs.m;
+  return a.mfma == nullptr && a.tabs.ilam_eo != nullptr && fixed_shape(a.n, m) &&
+         (int64_t)a.mesh.E * m[0] * m[1] * m[2] < ((int64_t)1 << 31);
+}
+
+template <typename T>
+hipError_t launch_schwarz_segments(const SchwarzLaunch<T> *a, int n, hipStream_t st) {
+  if (n < 1 || n > kMaxApplySegments) return hipErrorInvalidValue;
+  for (int k = 0; k < n; ++k) {
+    if (!schwarz_segments_supported<T>(a[k]) || a[k].n != a[0].n) return hipErrorInvalidValue;
+    for (int d = 0; d < 3; ++d)
+      if (a[k].tabs.m[d] != a[0].tabs.m[d]) return hipErrorInvalidValue;
+  }
+  const int *m = a[0].tabs.m;
+  hipError_t e = hipErrorInvalidValue;
+#define SIPG_TRY(NN, AX, AY, AZ)                                  \
+  if (a[0].n == NN && m[0] == AX && m[1] == AY && m[2] == AZ) {   \
+    e = launch_fixed_segments<T, NN, AX, AY, AZ>(a, n, st);       \
+    if (e == hipSuccess) e = launch_assemble_fixed_segments<T, NN, AX, AY, AZ>(a, n, st); \
+  }
+  SIPG_FDM_SHAPES(SIPG_TRY)
+#undef SIPG_TRY
+  return e;
+}
+
 template hipError_t launch_schwarz<double>(const SchwarzLaunch<double> &, hipStream_t);
 template hipError_t launch_schwarz<float>(const SchwarzLaunch<float> &, hipStream_t);
 template hipError_t launch_schwarz_local<double>(const SchwarzLaunch<double> &, hipStream_t);
 template hipError_t launch_schwarz_local<float>(const SchwarzLaunch<float> &, hipStream_t);
 template hipError_t launch_schwarz_assemble<double>(const SchwarzLaunch<double> &, hipStream_t);
 template hipError_t launch_schwarz_assemble<float>(const SchwarzLaunch<float> &, hipStream_t);
+
+template bool schwarz_segments_supported<double>(const SchwarzLaunch<double> &);
+template bool schwarz_segments_supported<float>(const SchwarzLaunch<float> &);
+template hipError_t launch_schwarz_segments<double>(const SchwarzLaunch<double> *, int, hipStream_t);
+template hipError_t launch_schwarz_segments<float>(const SchwarzLaunch<float> *, int, hipStream_t);
 
 }  // namespace sipg

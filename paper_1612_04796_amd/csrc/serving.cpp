@@ -21,11 +21,16 @@
 // q = A p over all members (launch_apply_segments, each member's workgroups
 // computing exactly what its own launch would) on a stream of the key that
 // waits for every member, followed by the members' remaining steps (one
-// launch per kernel for all of them) on that stream.
+// launch per kernel for all of them) on that stream.  Within such a group,
+// members whose preconditioners have the same signature (precision, orders,
+// subdomain shapes, smoothing counts) run their V-cycles as one cohort on
+// that stream: level by level, the local solves and the assembly of all of
+// them in one launch each, the other steps per member.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <deque>
 #include <map>
@@ -76,6 +81,17 @@ struct sipg_server {
   size_t budget = 0, used = 0;
   int max_active = 1;
   bool fuse = true;
+  // cohorts of equal preconditioner signature within a batched group run
+  // their V-cycles together (segmented local solves and assemblies)
+  bool fuse_smooth = true;
+  // launch shapes of admitted contexts: 0 built-in, 1 the process-wide
+  // tuning cache, 2 autotuned at admission (cached shapes without timing)
+  int tune = 1;
+  int64_t smooth_cycles = 0, smooth_requests = 0;
+  // captured cohort V-cycles by member contexts (in cohort order); an entry
+  // is dropped when one of its members leaves.  A null graph: capture failed,
+  // launched directly.
+  std::map<std::vector<sipg_ctx *>, hipGraphExec_t> cohort_graphs;
   // per batching key: the stream of its batched launches and joins (created
   // on first use; one per key, so cohorts of different keys never wait for
   // each other)
@@ -105,8 +121,22 @@ void unreserve(sipg_server *s, size_t b) {
   s->used -= b;
 }
 
+// drops the captured cohort V-cycles that use the context (their launches
+// completed before the member's last step event)
+void drop_cohort_graphs(sipg_server *s, const sipg_ctx *c) {
+  for (auto it = s->cohort_graphs.begin(); it != s->cohort_graphs.end();) {
+    if (std::find(it->first.begin(), it->first.end(), c) != it->first.end()) {
+      if (it->second) (void)hipGraphExecDestroy(it->second);
+      it = s->cohort_graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
 void release_compute(sipg_server *s, Request *r) {
   if (r->ctx) {
+    drop_cohort_graphs(s, r->ctx);
     sipg_destroy(r->ctx);
     r->ctx = nullptr;
   }
@@ -170,6 +200,14 @@ bool admit(sipg_server *s, Request *r) {
   if (sipg_setup(&r->prm, r->stream, &r->ctx) != SIPG_OK) {
     finish(s, r, SIPG_REQ_FAILED, sipg_last_error());
     return true;
+  }
+  if (s->tune == 2) {
+    if (sipg_autotune(r->ctx, 3) != SIPG_OK) {
+      finish(s, r, SIPG_REQ_FAILED, sipg_last_error());
+      return true;
+    }
+  } else if (s->tune == 1) {
+    sipg::detail::apply_cached_tuning(r->ctx);
   }
   if (hipMalloc(&r->x, r->ndof * sizeof(double)) != hipSuccess) {
     finish(s, r, SIPG_REQ_FAILED, "out of device memory");
@@ -293,10 +331,42 @@ std::vector<Request *> iterate_batched(sipg_server *s, hipStream_t fs, const std
   std::vector<Request *> left;
   bool ok = true;
   try {
+    // members of equal preconditioner signature: one cohort V-cycle on fs
+    std::map<std::vector<int>, std::vector<Request *>> cohorts;
     for (Request *r : g) {
-      sipg::detail::fcg_precond_update(r->ctx, r->x);
-      ok = ok && hipEventRecord(r->ev, r->stream) == hipSuccess &&
-           hipStreamWaitEvent(fs, r->ev, 0) == hipSuccess;
+      std::vector<int> sig;
+      if (s->fuse_smooth) sig = sipg::detail::precond_signature(r->ctx);
+      cohorts[sig].push_back(r);
+    }
+    for (auto &kv : cohorts) {
+      const std::vector<Request *> &m = kv.second;
+      if (kv.first.empty() || m.size() < 2) {
+        for (Request *r : m) {
+          sipg::detail::fcg_precond_update(r->ctx, r->x);
+          ok = ok && hipEventRecord(r->ev, r->stream) == hipSuccess &&
+               hipStreamWaitEvent(fs, r->ev, 0) == hipSuccess;
+        }
+        continue;
+      }
+      std::vector<sipg_ctx *> cs;
+      std::vector<double *> xs;
+      for (Request *r : m) {
+        ok = ok && hipStreamWaitEvent(fs, r->ev, 0) == hipSuccess;
+        cs.push_back(r->ctx);
+        xs.push_back(r->x);
+      }
+      auto git = s->cohort_graphs.find(cs);
+      if (git == s->cohort_graphs.end()) {
+        if (s->cohort_graphs.size() >= 64) {  // bounded: start over
+          for (auto &kv2 : s->cohort_graphs)
+            if (kv2.second) (void)hipGraphExecDestroy(kv2.second);
+          s->cohort_graphs.clear();
+        }
+        git = s->cohort_graphs.emplace(cs, sipg::detail::capture_cohort_precond(cs.data(), (int)cs.size(), fs)).first;
+      }
+      sipg::detail::fcg_precond_update_cohort(cs.data(), xs.data(), (int)cs.size(), fs, git->second);
+      s->smooth_cycles += 1;
+      s->smooth_requests += (int64_t)cs.size();
     }
     ok = ok && sipg::launch_apply_segments<double>(a.data(), (int)a.size(), fs) == hipSuccess;
     if (ok) {
@@ -413,6 +483,9 @@ int sipg_server_create(size_t memory_budget, int max_active, sipg_server **out) 
   if (!s) return fail(SIPG_ENOMEM, "host allocation failed");
   s->budget = memory_budget;
   s->max_active = max_active;
+  // a tuning cache saved earlier (a missing or unreadable file is ignored:
+  // the requests then run with the built-in shapes)
+  if (const char *path = std::getenv("SIPG_TUNING_CACHE")) (void)sipg_tuning_cache_load(path, nullptr);
   *out = s;
   return SIPG_OK;
 }
@@ -538,8 +611,23 @@ int sipg_server_fetch(sipg_server *s, int64_t id, double *u, void *hip_stream) {
 
 int sipg_server_set_option(sipg_server *s, int option, int value) {
   if (!s) return fail(SIPG_EINVAL, "null server");
-  if (option != SIPG_SERVER_FUSE_APPLY) return fail(SIPG_EINVAL, "unknown server option");
-  s->fuse = value != 0;
+  if (option == SIPG_SERVER_FUSE_APPLY) {
+    s->fuse = value != 0;
+  } else if (option == SIPG_SERVER_FUSE_SMOOTH) {
+    s->fuse_smooth = value != 0;
+  } else if (option == SIPG_SERVER_TUNE) {
+    if (value < 0 || value > 2) return fail(SIPG_EINVAL, "tuning mode must be 0, 1 or 2");
+    s->tune = value;
+  } else {
+    return fail(SIPG_EINVAL, "unknown server option");
+  }
+  return SIPG_OK;
+}
+
+int sipg_server_smooth_stats(const sipg_server *s, int64_t *cohort_cycles, int64_t *cohort_requests) {
+  if (!s) return fail(SIPG_EINVAL, "null server");
+  if (cohort_cycles) *cohort_cycles = s->smooth_cycles;
+  if (cohort_requests) *cohort_requests = s->smooth_requests;
   return SIPG_OK;
 }
 
@@ -554,7 +642,12 @@ int sipg_server_destroy(sipg_server *s) {
   if (!s) return SIPG_OK;
   (void)hipDeviceSynchronize();
   for (auto &kv : s->all) release_all(s, kv.second.get());
+  for (auto &kv : s->cohort_graphs)
+    if (kv.second) (void)hipGraphExecDestroy(kv.second);
   for (auto &kv : s->fuse_streams) (void)hipStreamDestroy(kv.second);
+  // shapes timed at admission are kept for later processes
+  if (s->tune == 2)
+    if (const char *path = std::getenv("SIPG_TUNING_CACHE")) (void)sipg_tuning_cache_save(path);
   delete s;
   return SIPG_OK;
 }

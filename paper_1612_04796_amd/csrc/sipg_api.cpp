@@ -8,6 +8,8 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -894,6 +896,170 @@ int guarded(F &&fn) {
   }
 }
 
+// ---- cohort V-cycles (serving): several contexts of one preconditioner
+// signature run their V-cycles level by level on one stream, the local
+// solves and assemblies of all of them in one launch each ----------------
+
+// every context's work on stream st while in scope
+struct StreamSwap {
+  sipg_ctx *const *cs;
+  int k;
+  hipStream_t saved[sipg::kMaxApplySegments];
+  StreamSwap(sipg_ctx *const *cs_, int k_, hipStream_t st) : cs(cs_), k(k_) {
+    for (int i = 0; i < k; ++i) {
+      saved[i] = cs[i]->stream;
+      cs[i]->stream = st;
+    }
+  }
+  ~StreamSwap() {
+    for (int i = 0; i < k; ++i) cs[i]->stream = saved[i];
+  }
+};
+
+template <typename T>
+bool level_segmentable(const sipg_ctx *c, int l, std::vector<int> &sig) {
+  const LevelTabs<T> &t = tabs_of<T>(const_cast<sipg_ctx *>(c), l);
+  sipg::SchwarzLaunch<T> a{c->mesh, t.n, t.schwarz, nullptr, nullptr, t.ilam, nullptr, nullptr,
+                           mfma_of(c, t), t.schwarz_spb, c->wide_planes};
+  if (!sipg::schwarz_segments_supported<T>(a)) return false;
+  sig.insert(sig.end(), {t.n, t.schwarz.m[0], t.schwarz.m[1], t.schwarz.m[2]});
+  return true;
+}
+
+// the weighted Schwarz correction of level l of every context in one launch
+// of the local solves and one of the assembly: u_out[i] = u_in[i] + sum_s ...
+template <typename T>
+void schwarz_cohort(sipg_ctx *const *cs, int k, int l, const T *const *r, const T *const *u_in, T *const *u_out) {
+  sipg::SchwarzLaunch<T> a[sipg::kMaxApplySegments];
+  const int spb = tabs_of<T>(cs[0], l).schwarz_spb;
+  for (int i = 0; i < k; ++i) {
+    const LevelTabs<T> &t = tabs_of<T>(cs[i], l);
+    a[i] = sipg::SchwarzLaunch<T>{cs[i]->mesh, t.n, t.schwarz, r[i], work_of<T>(cs[i]).C, t.ilam, u_in[i],
+                                  u_out[i], mfma_of(cs[i], t), spb, cs[i]->wide_planes};
+  }
+  check(sipg::launch_schwarz_segments<T>(a, k, cs[0]->stream), "schwarz cohort");
+}
+
+// one operator-kernel step (residual or residual + restriction) of every
+// context: one segmented launch, or one launch per context where their
+// launch shapes differ
+template <typename T>
+void apply_cohort(sipg_ctx *const *cs, int k, const sipg::ApplyLaunch<T> *a, const char *what) {
+  const hipError_t e = sipg::launch_apply_segments<T>(a, k, cs[0]->stream);
+  if (e == hipSuccess) return;
+  if (e != hipErrorInvalidValue) check(e, what);
+  (void)hipGetLastError();
+  for (int i = 0; i < k; ++i) run_apply<T>(cs[i], a[i], what);
+}
+
+template <typename T>
+void residual_cohort(sipg_ctx *const *cs, int k, int l, T *const *u, const T *const *f, T *const *r) {
+  sipg::ApplyLaunch<T> a[sipg::kMaxApplySegments];
+  for (int i = 0; i < k; ++i) {
+    const LevelTabs<T> &t = tabs_of<T>(cs[i], l);
+    a[i] = sipg::ApplyLaunch<T>{cs[i]->mesh, t.n, t.apply, u[i], f[i], r[i], sipg::APPLY_RESID, nullptr, nullptr, 0,
+                                t.apply_epb};
+  }
+  apply_cohort<T>(cs, k, a, "residual cohort");
+}
+
+template <typename T>
+void restrict_cohort(sipg_ctx *const *cs, int k, int l, T *const *u, const T *const *f, T *const *fc) {
+  sipg::ApplyLaunch<T> a[sipg::kMaxApplySegments];
+  for (int i = 0; i < k; ++i) {
+    const LevelTabs<T> &t = tabs_of<T>(cs[i], l);
+    a[i] = sipg::ApplyLaunch<T>{cs[i]->mesh, t.n, t.apply, u[i], f[i], fc[i], sipg::APPLY_RESTRICT, nullptr, t.J, t.nc,
+                                t.apply_epb};
+  }
+  apply_cohort<T>(cs, k, a, "restrict cohort");
+}
+
+// u_l += I_l u_{l-1} for every context (level 1: from the level-0 solution
+// with its mean removed, as op_prolong)
+template <typename T, typename TC>
+void prolong_cohort(sipg_ctx *const *cs, int k, int l, const TC *const *uc, T *const *uf) {
+  sipg::ProlongLaunch<T, TC> a[sipg::kMaxApplySegments];
+  for (int i = 0; i < k; ++i) {
+    const LevelTabs<T> &t = tabs_of<T>(cs[i], l);
+    const int64_t N0 = level_ndof(cs[i]->H, 0);
+    a[i] = sipg::ProlongLaunch<T, TC>{cs[i]->mesh.E, t.n, t.nc, t.J, uc[i],
+                                      l == 1 ? cs[i]->coarse.partial_u : nullptr,
+                                      sipg::coarse_num_partials(cs[i]->coarse), 1.0 / (double)N0, uf[i]};
+  }
+  check(sipg::launch_prolong_segments<T, TC>(a, k, cs[0]->stream), "prolong cohort");
+}
+
+// vcycle_impl from a zero start for every context, in the same order of
+// steps, each step of all contexts in one launch (the coarse solves per
+// context)
+template <typename T>
+void vcycle_cohort(sipg_ctx *const *cs, int k, T *const *uL, const T *const *fL) {
+  constexpr int KM = sipg::kMaxApplySegments;
+  const sipg::HierarchyHost &H = cs[0]->H;
+  const int L = cs[0]->L;
+  auto nsteps = [&](int base, int l) {
+    int s = base;
+    for (int q = l; q < L; ++q) s *= H.prm.smooth_growth;
+    return s;
+  };
+  T *ul[KM], *rr[KM], *fc[KM], *uc[KM];
+  const T *fl[KM], *none[KM] = {};
+  const double *u0[KM];
+  auto level_vectors = [&](int l) {
+    for (int i = 0; i < k; ++i) {
+      Work<T> &w = work_of<T>(cs[i]);
+      ul[i] = (l == L) ? uL[i] : w.u[l];
+      fl[i] = (l == L) ? fL[i] : w.f[l];
+      rr[i] = w.r;
+      fc[i] = w.f[l - 1];
+      uc[i] = w.u[l - 1];
+      u0[i] = cs[i]->u0;
+    }
+  };
+  auto smooth_from_residual = [&](int l) {
+    residual_cohort<T>(cs, k, l, ul, fl, rr);
+    schwarz_cohort<T>(cs, k, l, rr, ul, ul);
+  };
+  for (int l = L; l >= 1; --l) {
+    level_vectors(l);
+    const int ns = nsteps(H.prm.nsmooth_pre, l);
+    for (int s = 0; s < ns; ++s) {
+      if (s == 0) schwarz_cohort<T>(cs, k, l, fl, none, ul);
+      else smooth_from_residual(l);
+    }
+    if (ns == 0)
+      for (int i = 0; i < k; ++i) op_fill_zero<T>(cs[i], ul[i], level_ndof(cs[i]->H, l));
+    restrict_cohort<T>(cs, k, l, ul, fl, fc);
+  }
+  for (int i = 0; i < k; ++i)
+    check(sipg::launch_coarse<T>(cs[i]->coarse, work_of<T>(cs[i]).f[0], cs[i]->u0, false, cs[i]->stream), "coarse");
+  for (int l = 1; l <= L; ++l) {
+    level_vectors(l);
+    if (l == 1) prolong_cohort<T, double>(cs, k, 1, u0, ul);
+    else prolong_cohort<T, T>(cs, k, l, uc, ul);
+    const int ns = nsteps(H.prm.nsmooth_post, l);
+    for (int s = 0; s < ns; ++s) smooth_from_residual(l);
+  }
+}
+
+// the cohort's preconditioner V-cycles z = B r (the FP64 or FP32 vectors of
+// fcg_precond), every context's work on stream st
+void precond_cohort(sipg_ctx *const *cs, int k, hipStream_t st) {
+  StreamSwap swap(cs, k, st);
+  constexpr int KM = sipg::kMaxApplySegments;
+  if (cs[0]->H.prm.precond_bits == 64) {
+    double *u[KM];
+    const double *f[KM];
+    for (int i = 0; i < k; ++i) u[i] = cs[i]->cg_z, f[i] = cs[i]->cg_r;
+    vcycle_cohort<double>(cs, k, u, f);
+  } else {
+    float *u[KM];
+    const float *f[KM];
+    for (int i = 0; i < k; ++i) u[i] = cs[i]->w32.uL, f[i] = cs[i]->w32.fL;
+    vcycle_cohort<float>(cs, k, u, f);
+  }
+}
+
 }  // namespace
 
 // ---- flexible CG in enqueue-only pieces (shared by sipg_pcg_solve and the
@@ -989,9 +1155,9 @@ void fcg_restart_from_true(sipg_ctx *c) {
   op_apply<double>(c, c->L, c->cg_p, c->cg_q, nullptr);
 }
 
-void fcg_precond_update(sipg_ctx *c, double *x) {
+// after z = B r: beta, rz, x += alpha p if pending, p = z + beta p
+void fcg_after_precond(sipg_ctx *c, double *x) {
   const int64_t N = level_ndof(c->H, c->L);
-  fcg_precond(c);
   if (c->H.prm.precond_bits != 64) {
     check(sipg::launch_fcg_dot2<float>(c->w32.uL, c->cg_q, c->cg_r, N, c->partial, c->stream), "dot2");
     check(sipg::launch_fcg_finalize2(c->partial, c->scal, c->stream), "dot2");
@@ -1002,6 +1168,74 @@ void fcg_precond_update(sipg_ctx *c, double *x) {
     check(sipg::launch_fcg_xp<double>(x, c->cg_p, c->cg_z, N, c->scal, c->x_pending, c->stream), "fcg update");
   }
   c->x_pending = false;
+}
+
+void fcg_precond_update(sipg_ctx *c, double *x) {
+  fcg_precond(c);
+  fcg_after_precond(c, x);
+}
+
+std::vector<int> precond_signature(const sipg_ctx *c) {
+  const sipg_params &p = c->H.prm;
+  if (c->L < 1) return {};
+  std::vector<int> sig{p.precond_bits, c->L, p.nsmooth_pre, p.nsmooth_post, p.smooth_growth};
+  for (int l = 1; l <= c->L; ++l) {
+    const bool ok = p.precond_bits == 64 ? level_segmentable<double>(c, l, sig) : level_segmentable<float>(c, l, sig);
+    if (!ok) return {};
+  }
+  return sig;
+}
+
+// k in range, equal non-empty signatures, work vectors allocated (a capture
+// must not allocate)
+void check_cohort(sipg_ctx *const *cs, int k) {
+  if (k < 1 || k > sipg::kMaxApplySegments) throw std::invalid_argument("cohort size out of range");
+  const std::vector<int> sig = precond_signature(cs[0]);
+  if (sig.empty()) throw std::invalid_argument("context cannot join a cohort");
+  for (int i = 1; i < k; ++i)
+    if (precond_signature(cs[i]) != sig) throw std::invalid_argument("cohort signatures differ");
+  for (int i = 0; i < k; ++i) {
+    if (cs[i]->H.prm.precond_bits == 64) ensure_work<double>(cs[i]);
+    else ensure_work<float>(cs[i]);
+  }
+}
+
+void fcg_precond_update_cohort(sipg_ctx *const *cs, double *const *xs, int k, hipStream_t st,
+                               hipGraphExec_t graph) {
+  check_cohort(cs, k);
+  if (graph) {
+    check(hipGraphLaunch(graph, st), "cohort graph launch");
+  } else {
+    precond_cohort(cs, k, st);
+  }
+  StreamSwap swap(cs, k, st);
+  for (int i = 0; i < k; ++i) fcg_after_precond(cs[i], xs[i]);
+}
+
+hipGraphExec_t capture_cohort_precond(sipg_ctx *const *cs, int k, hipStream_t st) {
+  check_cohort(cs, k);
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
+  try {
+    precond_cohort(cs, k, st);
+  } catch (...) {
+    (void)hipStreamEndCapture(st, &g);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (hipStreamEndCapture(st, &g) != hipSuccess || !g) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return ex;
 }
 
 const double *host_scalars(const sipg_ctx *c) { return c->host_scal; }
@@ -1096,7 +1330,49 @@ void tune_level(sipg_ctx *c, int l, int reps) {
   g_tuned[key] = {t.apply_epb, t.schwarz_spb};
 }
 
+template <typename T>
+bool take_cached(sipg_ctx *c, int l) {
+  LevelTabs<T> &t = tabs_of<T>(c, l);
+  const std::array<int, 7> key{(int)(8 * sizeof(T)), t.n, t.schwarz.m[0], t.schwarz.m[1], t.schwarz.m[2],
+                               c->mesh.E, mfma_of(c, t) != nullptr};
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tuned.find(key);
+  if (it == g_tuned.end()) return false;
+  t.apply_epb = it->second[0];
+  t.schwarz_spb = it->second[1];
+  return true;
+}
+
+// value of `"key": <int>` in a JSON object's text
+bool json_int(const std::string &obj, const char *key, long *out) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t p = obj.find(k);
+  if (p == std::string::npos) return false;
+  p = obj.find(':', p + k.size());
+  if (p == std::string::npos) return false;
+  char *end = nullptr;
+  const long v = std::strtol(obj.c_str() + p + 1, &end, 10);
+  if (end == obj.c_str() + p + 1) return false;
+  *out = v;
+  return true;
+}
+
 }  // namespace
+
+namespace sipg {
+namespace detail {
+
+int apply_cached_tuning(sipg_ctx *c) {
+  int took = 0;
+  for (int l = 1; l <= c->L; ++l) {
+    took += take_cached<double>(c, l);
+    if (c->H.prm.precond_bits != 64) took += take_cached<float>(c, l);
+  }
+  return took;
+}
+
+}  // namespace detail
+}  // namespace sipg
 
 namespace {
 
@@ -1518,6 +1794,70 @@ int sipg_autotune(sipg_ctx *c, int reps) {
     check(hipStreamSynchronize(c->stream), "autotune");
     return (int)SIPG_OK;
   });
+}
+
+int sipg_tuning_cache_save(const char *path) {
+  if (!path) return fail(SIPG_EINVAL, "null path");
+  std::string out = "{\"sipg_tuning_cache\": 1, \"entries\": [";
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    bool first = true;
+    for (const auto &kv : g_tuned) {
+      const auto &k = kv.first;
+      char buf[256];
+      std::snprintf(buf, sizeof buf,
+                    "%s\n  {\"bits\": %d, \"n\": %d, \"mx\": %d, \"my\": %d, \"mz\": %d, \"elements\": %d, "
+                    "\"mfma\": %d, \"apply_epb\": %d, \"schwarz_spb\": %d}",
+                    first ? "" : ",", k[0], k[1], k[2], k[3], k[4], k[5], k[6], kv.second[0], kv.second[1]);
+      out += buf;
+      first = false;
+    }
+  }
+  out += "\n]}\n";
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *f = std::fopen(tmp.c_str(), "w");
+  if (!f) return fail(SIPG_EINVAL, std::string("cannot write ") + tmp);
+  const bool ok = std::fwrite(out.data(), 1, out.size(), f) == out.size();
+  if (std::fclose(f) != 0 || !ok || std::rename(tmp.c_str(), path) != 0)
+    return fail(SIPG_EINVAL, std::string("cannot write ") + path);
+  return SIPG_OK;
+}
+
+int sipg_tuning_cache_load(const char *path, int *nloaded) {
+  if (!path) return fail(SIPG_EINVAL, "null path");
+  FILE *f = std::fopen(path, "r");
+  if (!f) return fail(SIPG_EINVAL, std::string("cannot read ") + path);
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  if (text.find("\"sipg_tuning_cache\"") == std::string::npos) return fail(SIPG_EINVAL, "not a tuning cache");
+  size_t p = text.find("\"entries\"");
+  if (p == std::string::npos) return fail(SIPG_EINVAL, "tuning cache without entries");
+  std::vector<std::pair<std::array<int, 7>, std::array<int, 2>>> got_entries;
+  while ((p = text.find('{', p)) != std::string::npos) {
+    const size_t q = text.find('}', p);
+    if (q == std::string::npos) return fail(SIPG_EINVAL, "malformed tuning cache");
+    const std::string obj = text.substr(p, q - p + 1);
+    const char *keys[9] = {"bits", "n", "mx", "my", "mz", "elements", "mfma", "apply_epb", "schwarz_spb"};
+    long v[9];
+    for (int i = 0; i < 9; ++i)
+      if (!json_int(obj, keys[i], &v[i])) return fail(SIPG_EINVAL, std::string("tuning cache entry without ") + keys[i]);
+    const bool ok = (v[0] == 32 || v[0] == 64) && v[1] >= 2 && v[1] <= sipg::kMaxOrder + 1 && v[2] >= 1 &&
+                    v[2] <= 256 && v[3] >= 1 && v[3] <= 256 && v[4] >= 1 && v[4] <= 256 && v[5] >= 1 &&
+                    (v[6] == 0 || v[6] == 1) && v[7] >= 0 && v[7] <= 1024 && v[8] >= 0 && v[8] <= 64;
+    if (!ok) return fail(SIPG_EINVAL, "tuning cache entry out of range");
+    got_entries.push_back({{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5], (int)v[6]},
+                           {(int)v[7], (int)v[8]}});
+    p = q + 1;
+  }
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (const auto &e : got_entries) g_tuned[e.first] = e.second;
+  }
+  if (nloaded) *nloaded = (int)got_entries.size();
+  return SIPG_OK;
 }
 
 int sipg_tuning(const sipg_ctx *c, int level, int bits, int *apply_epb, int *schwarz_spb) {

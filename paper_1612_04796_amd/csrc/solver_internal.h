@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "kernels.h"
 #include "sipg_mg.h"
@@ -42,6 +43,28 @@ void fcg_confirm(sipg_ctx *c, double *x);
 void fcg_restart_from_true(sipg_ctx *c);
 // z = B r, beta = -alpha (z.q) / rz, rz = r.z, x += alpha p if pending, p = z + beta p
 void fcg_precond_update(sipg_ctx *c, double *x);
+
+// The preconditioner signature of a context: contexts with equal, non-empty
+// signatures (same precision, level count, orders, subdomain shapes and
+// smoothing counts, every level on the compile-time local-solve kernels)
+// can run their V-cycles as one cohort.  Empty when the context cannot.
+std::vector<int> precond_signature(const sipg_ctx *c);
+// fcg_precond_update of k <= kMaxApplySegments contexts with equal
+// signatures, all enqueued on stream st: the V-cycles level by level, each
+// step of all k in one segmented launch (local solves, assemblies,
+// residuals, restrictions, prolongations; the coarse solves per context),
+// then every context's CG update.  Each context computes exactly what
+// fcg_precond_update computes for it.  graph: the V-cycles captured earlier
+// by capture_cohort_precond for the same contexts in the same order (null:
+// launched directly).
+void fcg_precond_update_cohort(sipg_ctx *const *cs, double *const *xs, int k, hipStream_t st,
+                               hipGraphExec_t graph);
+// The cohort's V-cycles captured into an executable graph on stream st
+// (null when the capture fails; nothing is left enqueued then).
+hipGraphExec_t capture_cohort_precond(sipg_ctx *const *cs, int k, hipStream_t st);
+// Takes the launch shapes the process-wide tuning cache holds for the
+// context's levels (no timing); returns how many levels took one.
+int apply_cached_tuning(sipg_ctx *c);
 
 const double *host_scalars(const sipg_ctx *c);
 hipStream_t ctx_stream(const sipg_ctx *c);

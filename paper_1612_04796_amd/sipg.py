@@ -27,13 +27,14 @@ EXPORTS = (
     "sipg_level_info", "sipg_rhs_fourier", "sipg_apply_A", "sipg_residual", "sipg_schwarz",
     "sipg_smooth", "sipg_restrict", "sipg_prolong_add", "sipg_coarse_solve", "sipg_vcycle",
     "sipg_precond", "sipg_mg_solve", "sipg_pcg_solve", "sipg_residual_history",
-    "sipg_last_error", "sipg_host_table", "sipg_time_kernel", "sipg_autotune", "sipg_tuning", "sipg_set_tuning", "sipg_tuning_limits",
+    "sipg_last_error", "sipg_host_table", "sipg_time_kernel", "sipg_autotune", "sipg_tuning", "sipg_set_tuning", "sipg_tuning_limits", "sipg_tuning_cache_save", "sipg_tuning_cache_load",
     "sipg_set_option", "sipg_traced_kernel_ms", "sipg_ndof", "sipg_rhs_mean", "sipg_device_bytes",
     "sipg_schwarz_noalloc",
     "sipg_server_create", "sipg_server_submit", "sipg_server_progress", "sipg_server_status",
-    "sipg_server_fetch", "sipg_server_destroy", "sipg_server_set_option", "sipg_server_stats",
+    "sipg_server_fetch", "sipg_server_destroy", "sipg_server_set_option", "sipg_server_stats", "sipg_server_smooth_stats",
 )
 REQ_QUEUED, REQ_ACTIVE, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+SERVER_FUSE_APPLY, SERVER_FUSE_SMOOTH, SERVER_TUNE = 0, 1, 2
 KERNELS = {"residual": 0, "schwarz_solve": 1, "schwarz_assemble": 2, "restrict": 3, "prolong": 4}
 
 
@@ -107,6 +108,8 @@ def lib():
             "sipg_autotune": (c_int, [vp, c_int]),
             "sipg_tuning": (c_int, [vp, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
             "sipg_set_tuning": (c_int, [vp, c_int, c_int, c_int, c_int]),
+            "sipg_tuning_cache_save": (c_int, [ctypes.c_char_p]),
+            "sipg_tuning_cache_load": (c_int, [ctypes.c_char_p, ctypes.POINTER(c_int)]),
             "sipg_tuning_limits": (c_int, [vp, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
             "sipg_set_option": (c_int, [vp, c_int, c_int]),
             "sipg_traced_kernel_ms": (c_int, [vp, P(c_double), P(c_int)]),
@@ -120,6 +123,7 @@ def lib():
             "sipg_server_destroy": (c_int, [vp]),
             "sipg_server_set_option": (c_int, [vp, c_int, c_int]),
             "sipg_server_stats": (c_int, [vp, P(ctypes.c_int64), P(ctypes.c_int64)]),
+            "sipg_server_smooth_stats": (c_int, [vp, P(ctypes.c_int64), P(ctypes.c_int64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -154,6 +158,18 @@ def make_params(ne=(4, 4, 4), length=(1.0, 1.0, 1.0), P=4, penalty=1.0, overlap=
     p.basis = BASIS[basis] if isinstance(basis, str) else int(basis)
     p.overlap_floor = int(overlap_floor)
     return p
+
+
+def tuning_cache_save(path):
+    """Save the process-wide launch-shape cache as JSON (sipg_tuning_cache_save)."""
+    _check(lib().sipg_tuning_cache_save(os.fsencode(path)))
+
+
+def tuning_cache_load(path):
+    """Merge a saved launch-shape cache; returns the entries read."""
+    n = ctypes.c_int()
+    _check(lib().sipg_tuning_cache_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
 
 
 def footprint(**kw):
@@ -444,13 +460,22 @@ class Server:
 
     def set_option(self, option, value):
         """SIPG_SERVER_FUSE_APPLY (0): batch the operator launches of
-        same-order requests (1, the default) or not (0)."""
+        same-order requests (1, the default) or not (0);
+        SIPG_SERVER_FUSE_SMOOTH (1): cohort V-cycles of same-signature
+        requests (1, the default) or not (0); SIPG_SERVER_TUNE (2): launch
+        shapes of admitted requests (0 built-in, 1 cached, 2 autotuned)."""
         _check(lib().sipg_server_set_option(self._h, int(option), int(value)))
 
     def stats(self):
         """(fused operator launches, requests they served) so far."""
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().sipg_server_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def smooth_stats(self):
+        """(cohort V-cycles, requests they served) so far."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().sipg_server_smooth_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
     def fetch(self, rid, u):

@@ -62,6 +62,22 @@ WORKLOADS = {
 }
 
 
+def serving_stream_same_order(seed, nreq, qps, P=8, ne_range=(4, 7)):
+    """Poisson arrivals of small solves of one order on isotropic meshes
+    (edge element count uniform in ne_range, independently per direction,
+    unit element aspect ratio): every request has the same preconditioner
+    signature, so ready requests can share their V-cycle launches."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(nreq):
+        t += rng.exponential(1.0 / qps)
+        ne = tuple(int(v) for v in rng.integers(ne_range[0], ne_range[1] + 1, size=3))
+        out.append({"id": i, "t_arrival": t, "ne": ne, "P": int(P),
+                    "length": tuple(float(v) for v in ne), "rhs_seed": int(rng.integers(0, 2 ** 31))})
+    return out
+
+
 def serving_stream(seed, nreq, qps):
     """Poisson arrivals of heterogeneous solves: per request the edge element
     count (uniform 4..24, same in every direction), the order from

@@ -171,6 +171,101 @@ def test_batched_operator_launches_keep_results(bits):
                 assert np.array_equal(host(u), xs), (fuse, i)
 
 
+# one preconditioner signature (order 4, the 8 % overlap on isotropic
+# meshes: subdomains of 7^3 and 5^3 nodes on levels 2 and 1) and one size
+# class: their V-cycles run as cohorts when they are ready together
+SAME_SIGNATURE = [
+    dict(ne=(6, 6, 6), length=(1.0, 1.0, 1.0), P=4, overlap="rel", omega=0.08),
+    dict(ne=(5, 6, 7), length=(1.0, 1.2, 1.4), P=4, overlap="rel", omega=0.08),
+    dict(ne=(7, 6, 5), length=(1.0, 1.0, 1.0), P=4, overlap="max", omega=0.08),
+    dict(ne=(6, 5, 6), length=(1.0, 1.0, 1.0), P=4, overlap="rel", omega=0.08),
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("bits", [32, 64])
+def test_cohort_vcycles_keep_results(bits):
+    """Requests of one preconditioner signature served with cohort V-cycles
+    (every V-cycle step of the cohort in one segmented launch, the cycles
+    captured in graphs), with the built-in or autotuned launch shapes, give
+    bitwise the results of the same solves run alone with the same shapes, and
+    the cohorts happened; with SIPG_SERVER_FUSE_SMOOTH = 0 none is formed."""
+    from _gpu import announce, host, zeros
+    announce("serving cohorts", bits)
+
+    def alone_runs(tuned):
+        # tuned: the shapes the process-wide cache holds for these meshes
+        # (the server's autotuning put them there); the partial sums of the
+        # flexible-CG dot products follow the operator's launch shape
+        out = []
+        for i, prm in enumerate(SAME_SIGNATURE):
+            k, phi, amp = fourier_modes(300 + i, 3)
+            with sipg.Solver(precond_bits=bits, **prm) as s:
+                if tuned:
+                    s.autotune(reps=3)
+                b = zeros(s.ndof())
+                s.rhs_fourier(k, phi, amp, b)
+                x = zeros(s.ndof())
+                it, rr = s.pcg_solve(x, b, rtol=1e-10, maxit=100)
+                out.append((host(x), it))
+        return out
+
+    alone = alone_runs(False)
+    for smooth, tune in ((1, 0), (0, 0), (1, 2)):
+        with sipg.Server(64 << 30, max_active=4) as srv:
+            srv.set_option(sipg.SERVER_FUSE_SMOOTH, smooth)
+            srv.set_option(sipg.SERVER_TUNE, tune)
+            ids = []
+            for i, prm in enumerate(SAME_SIGNATURE):
+                k, phi, amp = fourier_modes(300 + i, 3)
+                ids.append(srv.submit(k, phi, amp, rtol=1e-10, maxit=100, precond_bits=bits, **prm))
+            for _ in range(100000):
+                a, q, _c = srv.progress(wait_ms=50)
+                if a == 0 and q == 0:
+                    break
+            cycles, served = srv.smooth_stats()
+            if smooth:
+                assert cycles >= 1 and served >= 2 * cycles, (cycles, served)
+            else:
+                assert (cycles, served) == (0, 0)
+            if tune == 2:
+                alone = alone_runs(True)
+            for i, rid in enumerate(ids):
+                st = srv.status(rid)
+                assert st["state"] == sipg.REQ_DONE, st
+                u = zeros(st["ndof"])
+                srv.fetch(rid, u)
+                xs, it = alone[i]
+                assert st["iters"] == it
+                assert np.array_equal(host(u), xs), (smooth, tune, i)
+
+
+def test_tuning_cache_round_trip(tmp_path):
+    """The launch-shape cache as JSON: entries written by hand are merged and
+    saved back; malformed files are refused."""
+    path = tmp_path / "cache.json"
+    path.write_text('{"sipg_tuning_cache": 1, "entries": [\n'
+                    ' {"bits": 64, "n": 9, "mx": 13, "my": 13, "mz": 13, "elements": 1000, "mfma": 0, '
+                    '"apply_epb": 2, "schwarz_spb": 3},\n'
+                    ' {"bits": 32, "n": 8, "mx": 12, "my": 12, "mz": 12, "elements": 777, "mfma": 1, '
+                    '"apply_epb": 4, "schwarz_spb": 0}]}\n')
+    assert sipg.tuning_cache_load(str(path)) == 2
+    out = tmp_path / "saved.json"
+    sipg.tuning_cache_save(str(out))
+    text = out.read_text()
+    assert '"elements": 1000' in text and '"schwarz_spb": 3' in text and '"elements": 777' in text
+    assert sipg.tuning_cache_load(str(out)) >= 2
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"sipg_tuning_cache": 1, "entries": [{"bits": 64, "n": 9}]}')
+    with pytest.raises(sipg.SipgError):
+        sipg.tuning_cache_load(str(bad))
+    bad.write_text('{"entries": []}')
+    with pytest.raises(sipg.SipgError):
+        sipg.tuning_cache_load(str(bad))
+    with pytest.raises(sipg.SipgError):
+        sipg.tuning_cache_load(str(tmp_path / "missing.json"))
+
+
 def test_submit_rejects_a_request_larger_than_the_budget():
     # a request whose footprint exceeds the whole budget could never be
     # admitted and would block the FIFO: it is refused at submit
@@ -207,6 +302,12 @@ def test_oversized_request_does_not_block_the_queue():
 def test_server_options_validated():
     with sipg.Server(1 << 30, 4) as srv:
         assert srv.stats() == (0, 0)
-        srv.set_option(0, 0)
+        assert srv.smooth_stats() == (0, 0)
+        srv.set_option(sipg.SERVER_FUSE_APPLY, 0)
+        srv.set_option(sipg.SERVER_FUSE_SMOOTH, 0)
+        for mode in (0, 1, 2):
+            srv.set_option(sipg.SERVER_TUNE, mode)
+        with pytest.raises(sipg.SipgError):
+            srv.set_option(sipg.SERVER_TUNE, 3)
         with pytest.raises(sipg.SipgError):
             srv.set_option(5, 1)
