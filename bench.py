@@ -448,6 +448,7 @@ def main():
     ap.add_argument("--workload", default="cube16_p8_rel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 32^3, P=7 mixed-precision solves")
+    ap.add_argument("--no-scale", action="store_true", help="skip the 64^3, P=7 (134M unknowns) solves")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 4^3 P=4 and the anisotropic 8^3 P=16 workloads")
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel timing")
@@ -617,6 +618,21 @@ def main():
             f"FP16 local solves {mixed['speedup_fp16_over_fp64']:.2f}x the FP64 one")
         sols = {bits: v.cpu().numpy() for bits, v in sols.items()}
         del b4
+
+    # ---- one GPU's share of a large job: 64^3 elements, P = 7 (134M unknowns)
+    if not args.no_scale:
+        wl6 = WORKLOADS["cube64_p7_rel"]
+        b6, _ = workload_rhs(wl6)
+        scale = {"workload": wl6.name, "ndof": wl6.ndof}
+        for bits in (64, 32):
+            scale[f"fcg_precond_fp{bits}"] = fcg_timing(wl6, bits, b6, 2, 1, autotune=not args.no_autotune)
+            sc = scale[f"fcg_precond_fp{bits}"]
+            log(f"FCG {wl6.name}, FP{bits} preconditioner: {sc['ms_per_solve']:.2f} ms/solve, "
+                f"{sc['unknowns_per_s']:.4g} unknowns/s, {sc['iterations']} iterations")
+        scale["speedup_fp32_over_fp64"] = (scale["fcg_precond_fp64"]["ms_per_solve"]
+                                           / scale["fcg_precond_fp32"]["ms_per_solve"])
+        detail["scale"] = scale
+        del b6
 
     if args.serving_requests > 0:
         from paper_1612_04796_amd import sipg as _s

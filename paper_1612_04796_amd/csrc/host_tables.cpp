@@ -465,10 +465,10 @@ std::string validate(const sipg_params &p) {
   if (p.smooth_growth < 1 || p.smooth_growth > 8) return "smooth_growth must be in 1..8";
   if (p.precond_bits != 64 && p.precond_bits != 32 && p.precond_bits != 16)
     return "precond_bits must be 64, 32 or 16";
-  // the coarse solve holds 2D planes of the level-0 tensor (2 ne_d nodes
-  // per direction) in LDS and at most 12 rows of a plane per thread
+  // the coarse solve moves level-0 lines (2 ne_d nodes) through chunks of
+  // 4096 values in LDS, a z line twice
   for (int d = 0; d < 3; ++d)
-    if (p.ne[d] > 48) return "ne[d] must be at most 48 (the level-0 planes of the coarse solve)";
+    if (p.ne[d] > 1024) return "ne[d] must be at most 1024 (the level-0 lines of the coarse solve)";
   const int64_t E = (int64_t)p.ne[0] * p.ne[1] * p.ne[2];
   if (E * (int64_t)(p.P + 1) * (p.P + 1) * (p.P + 1) > (int64_t)1 << 31)
     return "problem too large (more than 2^31 unknowns)";

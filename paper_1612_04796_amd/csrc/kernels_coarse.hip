@@ -385,6 +385,150 @@ coarse_split_xy_bwd(Dims d, CoarseLaunch c, const double *__restrict__ t, double
   if (tid == 0) c.partial_u[z * np + part] = s;
 }
 
+// ---- level-0 grids whose planes exceed the LDS --------------------------------
+// One workgroup per plane, five passes through global memory: x forward, y
+// forward, z forward + mean correction + Lambda^+ + z backward, y backward,
+// x backward.  A pass moves its plane's lines through LDS in chunks (all
+// loads of a chunk before any output is written, so the y passes can work in
+// place) and reads the 1D tables from global memory (they stay in the
+// caches).  Same arithmetic as the plane kernels, in another summation order.
+constexpr int kBigThreads = 256;
+constexpr int kBigChunk = 4096;  // line values per chunk in LDS
+
+// nl lines of length n: get(l, a) is entry a of line l, put(l, o, v) stores
+// output o; FWD: out[o] = sum_a A[a*n + o] in[a], else sum_a A[o*n + a] in[a]
+// lines lb .. le - 1 of a plane (the workgroup's part)
+template <bool FWD, typename Get, typename Put>
+__device__ void big_lines(double *buf, int lb, int le, int n, const double *__restrict__ A, Get get, Put put) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int L = max(1, kBigChunk / n);
+  for (int l0 = lb; l0 < le; l0 += L) {
+    const int cl = min(L, le - l0);
+    for (int i = tid; i < cl * n; i += nth) {
+      const int l = i / n;
+      buf[i] = get(l0 + l, i - l * n);
+    }
+    __syncthreads();
+    for (int i = tid; i < cl * n; i += nth) {
+      const int l = i / n, o = i - l * n;
+      const double *x = buf + l * n;
+      double acc = 0.0;
+      for (int a = 0; a < n; ++a) acc += (FWD ? A[a * n + o] : A[o * n + a]) * x[a];
+      put(l0 + l, o, acc);
+    }
+    __syncthreads();
+  }
+}
+
+// the part of a plane's nl lines that workgroup (blockIdx.x, blockIdx.y) owns
+__device__ __forceinline__ int part_begin(int nl) { return (int)((int64_t)nl * blockIdx.y / gridDim.y); }
+__device__ __forceinline__ int part_end(int nl) { return (int)((int64_t)nl * (blockIdx.y + 1) / gridDim.y); }
+
+__device__ double big_block_sum(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  const int t = threadIdx.x, w = t >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((t & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (t == 0)
+    for (int i = 0; i < nw; ++i) s += red[i];
+  __syncthreads();
+  return s;  // valid in thread 0
+}
+
+// x forward per z plane from the element-major f_0; plane sum -> partial[z]
+template <typename TI>
+__global__ void __launch_bounds__(kBigThreads)
+coarse_big_x_fwd(Dims d, CoarseLaunch c, const TI *__restrict__ f0, double *__restrict__ t) {
+  __shared__ double buf[kBigChunk];
+  __shared__ double red[kBigThreads / 64];
+  const int Nx = d.N[0], Ny = d.N[1], z = blockIdx.x;
+  double s = 0.0;
+  big_lines<true>(
+      buf, part_begin(Ny), part_end(Ny), Nx, c.S[0],
+      [&](int y, int x) {
+        const double v = (double)f0[elem_major_p1(d, x, y, z)];
+        s += v;
+        return v;
+      },
+      [&](int y, int o, double v) { t[((size_t)z * Ny + y) * Nx + o] = v; });
+  s = big_block_sum(s, red);
+  if (threadIdx.x == 0) c.partial[z * gridDim.y + blockIdx.y] = s;
+}
+
+// y forward (FWD) or backward per z plane, in place
+template <bool FWD>
+__global__ void __launch_bounds__(kBigThreads) coarse_big_y(Dims d, const double *__restrict__ Sy, double *t) {
+  __shared__ double buf[kBigChunk];
+  const int Nx = d.N[0], Ny = d.N[1], z = blockIdx.x;
+  double *tz = t + (size_t)z * Ny * Nx;
+  big_lines<FWD>(
+      buf, part_begin(Nx), part_end(Nx), Ny, Sy, [&](int x, int y) { return tz[(size_t)y * Nx + x]; },
+      [&](int x, int o, double v) { tz[(size_t)o * Nx + x] = v; });
+}
+
+// per y plane: z forward, mean correction, Lambda^+, z backward, in place
+__global__ void __launch_bounds__(kBigThreads) coarse_big_z(Dims d, CoarseLaunch c, double *t, int np) {
+  __shared__ double buf[kBigChunk];
+  __shared__ double red[kBigThreads / 64];
+  __shared__ double mean_sh;
+  const int Nx = d.N[0], Ny = d.N[1], Nz = d.N[2], y = blockIdx.x, tid = threadIdx.x;
+  double s = 0.0;
+  for (int i = tid; i < Nz * np; i += blockDim.x) s += c.partial[i];
+  s = big_block_sum(s, red);
+  if (tid == 0) mean_sh = s / ((double)Nx * Ny * Nz);
+  __syncthreads();
+  const double mean = mean_sh;
+  const size_t zs = (size_t)Ny * Nx;
+  double *ty = t + (size_t)y * Nx;
+  // forward into the LDS chunk, then scale and transform back through the
+  // caller's lines: two chunk passes per line set
+  const int L = max(1, kBigChunk / (2 * Nz));
+  double *fw = buf + L * Nz;
+  const int xe = part_end(Nx);
+  for (int x0 = part_begin(Nx); x0 < xe; x0 += L) {
+    const int cl = min(L, xe - x0);
+    for (int i = tid; i < cl * Nz; i += blockDim.x) {
+      const int l = i / Nz, z = i - l * Nz;
+      buf[i] = ty[z * zs + x0 + l];
+    }
+    __syncthreads();
+    for (int i = tid; i < cl * Nz; i += blockDim.x) {
+      const int l = i / Nz, o = i - l * Nz, x = x0 + l;
+      double acc = 0.0;
+      for (int a = 0; a < Nz; ++a) acc += c.S[2][a * Nz + o] * buf[l * Nz + a];
+      const double v = acc - mean * c.colsum[2][o] * c.colsum[0][x] * c.colsum[1][y];
+      const bool zero = (x == c.zero[0] && y == c.zero[1] && o == c.zero[2]);
+      fw[i] = zero ? 0.0 : v / (c.lam[0][x] + c.lam[1][y] + c.lam[2][o]);
+    }
+    __syncthreads();
+    for (int i = tid; i < cl * Nz; i += blockDim.x) {
+      const int l = i / Nz, o = i - l * Nz;
+      double acc = 0.0;
+      for (int a = 0; a < Nz; ++a) acc += c.S[2][o * Nz + a] * fw[l * Nz + a];
+      ty[o * zs + x0 + l] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// x backward per z plane into the element-major u_0; plane sum -> partial_u[z]
+__global__ void __launch_bounds__(kBigThreads)
+coarse_big_x_bwd(Dims d, CoarseLaunch c, const double *__restrict__ t, double *__restrict__ u0) {
+  __shared__ double buf[kBigChunk];
+  __shared__ double red[kBigThreads / 64];
+  const int Nx = d.N[0], Ny = d.N[1], z = blockIdx.x;
+  double s = 0.0;
+  big_lines<false>(
+      buf, part_begin(Ny), part_end(Ny), Nx, c.S[0], [&](int y, int x) { return t[((size_t)z * Ny + y) * Nx + x]; },
+      [&](int y, int o, double v) {
+        u0[elem_major_p1(d, o, y, z)] = v;
+        s += v;
+      });
+  s = big_block_sum(s, red);
+  if (threadIdx.x == 0) c.partial_u[z * gridDim.y + blockIdx.y] = s;
+}
+
 // LDS bytes of the plane kernels: two planes, plus the 1D tables when they fit
 constexpr size_t kCoarseLds = 150 * 1024;
 size_t plane_bytes(const Dims &d, int a, int b) { return 2 * (size_t)d.N[a] * d.N[b] * sizeof(double); }
@@ -397,7 +541,17 @@ size_t tab_bytes(const Dims &d, int a, int b) {
 // Workgroups per plane of the split kernels: doubled while the plane passes
 // have fewer than 256 workgroups and each part keeps at least 4 columns
 // (rows); 1 (one workgroup per plane) when their LDS would not fit.
+// Workgroups per plane of the line passes (level-0 planes beyond the LDS).
+constexpr int kBigParts = 8;
+
+static bool coarse_planes_fit(const CoarseLaunch &c) {
+  Dims d;
+  for (int i = 0; i < 3; ++i) d.N[i] = c.N[i], d.ne[i] = c.ne[i];
+  return plane_bytes(d, 0, 1) <= kCoarseLds && plane_bytes(d, 0, 2) <= kCoarseLds;
+}
+
 int coarse_parts(const CoarseLaunch &c) {
+  if (!coarse_planes_fit(c)) return kBigParts;
   const int N0 = c.N[0], N1 = c.N[1], N2 = c.N[2];
   int np = 1;
   while (np < 8 && std::min(N1, N2) * np * 2 <= 256 && N0 / (2 * np) >= 4 && N1 / (2 * np) >= 4) np *= 2;
@@ -417,6 +571,20 @@ template <typename K>
 static hipError_t allow_lds(K kernel, size_t shm) {
   if (shm <= 64 * 1024) return hipSuccess;
   return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+}
+
+template <typename TI>
+hipError_t launch_big(const Dims &d, const CoarseLaunch &c, const TI *f0, double *u0, hipStream_t st) {
+  // a z line and its transform must fit one chunk (a part may own no lines:
+  // its plane sum is then 0)
+  if (2 * d.N[2] > kBigChunk || d.N[0] > kBigChunk || d.N[1] > kBigChunk) return hipErrorInvalidValue;
+  const int np = kBigParts;
+  coarse_big_x_fwd<TI><<<dim3(d.N[2], np), kBigThreads, 0, st>>>(d, c, f0, c.t0);
+  coarse_big_y<true><<<dim3(d.N[2], np), kBigThreads, 0, st>>>(d, c.S[1], c.t0);
+  coarse_big_z<<<dim3(d.N[1], np), kBigThreads, 0, st>>>(d, c, c.t0, np);
+  coarse_big_y<false><<<dim3(d.N[2], np), kBigThreads, 0, st>>>(d, c.S[1], c.t0);
+  coarse_big_x_bwd<<<dim3(d.N[2], np), kBigThreads, 0, st>>>(d, c, c.t0, u0);
+  return hipGetLastError();
 }
 
 // one workgroup per plane
@@ -459,7 +627,9 @@ hipError_t launch_coarse(const CoarseLaunch &c, const TI *f0, double *u0, bool s
   const int64_t N0 = (int64_t)d.N[0] * d.N[1] * d.N[2];
   hipError_t e;
   const int np = coarse_parts(c);
-  if (np > 1) {
+  if (!coarse_planes_fit(c)) {
+    if ((e = launch_big<TI>(d, c, f0, u0, st)) != hipSuccess) return e;
+  } else if (np > 1) {
     const int Nx = d.N[0], Ny = d.N[1], Nz = d.N[2];
     const size_t cw = (Nx + np - 1) / np, rh = (Ny + np - 1) / np;
     const size_t tabs = (size_t)Nx * Nx + (size_t)Ny * Ny;

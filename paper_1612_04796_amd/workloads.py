@@ -59,6 +59,8 @@ WORKLOADS = {
     "cube16_p8_rel": Workload("cube16_p8_rel", (16, 16, 16), (1.0, 1.0, 1.0), 8, "rel", 0.08, 8, "mg"),
     "aniso16_p16_max": Workload("aniso16_p16_max", (8, 8, 8), (16.0, 1.0, 1.0), 16, "max", 0.08, 3, "fcg"),
     "cube32_p7_rel": Workload("cube32_p7_rel", (32, 32, 32), (1.0, 1.0, 1.0), 7, "rel", 0.08, 8, "fcg"),
+    # one GPU's share of a large job: 64^3 elements, 134,217,728 unknowns
+    "cube64_p7_rel": Workload("cube64_p7_rel", (64, 64, 64), (1.0, 1.0, 1.0), 7, "rel", 0.08, 8, "fcg"),
 }
 
 

@@ -133,3 +133,34 @@ def test_cube32_p7_fp16_preconditioner():
     assert rr <= 1e-10 and it <= 12
     assert rel(host(x), oracle.exact_solution(bh, h)) <= TOL_EXACT
     s16.close()
+
+
+@pytest.mark.parametrize("bits", [32])
+def test_cube64_p7_fcg_at_scale(bits):
+    """64^3 elements at P = 7 (134,217,728 unknowns; the level-0 coarse
+    problem, 128^3 nodes, runs on the line passes through global memory): the
+    operator against the oracle's on the whole vector, and the flexible-CG
+    solve checked by the oracle's own residual b - A x of the returned x (the
+    oracle's exact solution is too slow at this size) and its zero mean."""
+    announce("fullsize cube64_p7_rel", bits)
+    wl = WORKLOADS["cube64_p7_rel"]
+    h = oracle.Hierarchy(wl.ne, wl.length, wl.P, overlap=wl.overlap, omega=wl.omega, growth=wl.growth)
+    s = sipg.Solver(ne=wl.ne, length=wl.length, P=wl.P, overlap=wl.overlap, omega=wl.omega,
+                    smooth_growth=wl.growth, precond_bits=bits)
+    k, phi, amp = fourier_modes(0, wl.kmax)
+    b = zeros(s.ndof())
+    s.rhs_fourier(k, phi, amp, b)
+    u = uniform_vector(6, s.ndof())
+    y = zeros(s.ndof())
+    s.apply_A(dev(u), y)
+    assert rel(host(y), oracle.apply_level(u, h)) <= TOL_OP
+    del u, y
+    x = zeros(s.ndof())
+    it, rr = s.pcg_solve(x, b, rtol=1e-10, maxit=60)
+    assert rr <= 1e-10 and it <= 12
+    xh, bh = host(x), host(b)
+    bp = bh - bh.mean()
+    r = bp - oracle.apply_level(xh, h)
+    assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(bp)
+    assert abs(xh.mean()) <= 1e-14 * np.abs(xh).max()
+    s.close()

@@ -106,12 +106,15 @@ def test_transfers(ne, length, P):
     s.close()
 
 
-# up to the 48 elements per direction the coarse planes allow, with odd and
-# unequal counts
+# odd and unequal counts; planes in LDS up to 48 elements per direction,
+# beyond that (a plane of more than 150 KB) the line passes through global
+# memory
 COARSE = [((3, 3, 3), (1.0, 1.0, 1.0)), ((4, 3, 5), (2.0, 1.0, 0.5)), ((16, 16, 16), (1.0, 1.0, 1.0)),
           ((7, 32, 9), (1.0, 3.0, 1.0)), ((3, 40, 3), (1.0, 1.0, 1.0)), ((5, 4, 48), (1.0, 1.0, 2.0)),
           # planes shared by 4 workgroups with a ragged last part: columns (18 = 5+5+5+3), rows (18)
-          ((9, 20, 20), (1.0, 1.0, 1.0)), ((20, 9, 11), (2.0, 1.0, 1.0))]
+          ((9, 20, 20), (1.0, 1.0, 1.0)), ((20, 9, 11), (2.0, 1.0, 1.0)),
+          # line passes: chunks of whole and of partial line sets
+          ((50, 50, 4), (1.0, 1.0, 1.0)), ((64, 50, 49), (1.0, 2.0, 1.0)), ((61, 3, 97), (1.0, 1.0, 3.0))]
 
 
 @pytest.mark.parametrize("ne,length", COARSE)

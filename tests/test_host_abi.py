@@ -120,7 +120,7 @@ BAD = [
     dict(overlap="rel", omega=1.5),     # overlap wider than the neighbour
     dict(nsmooth_pre=0, nsmooth_post=0),
     dict(precond_bits=8),
-    dict(ne=(49, 4, 4)),                # beyond the coarse solve's level-0 planes (ne_d <= 48)
+    dict(ne=(1025, 4, 4)),              # beyond the coarse solve's level-0 lines (ne_d <= 1024)
     dict(ne=(3, 3, 3), length=(16.0, 1.0, 1.0), overlap="max", omega=0.08, P=4),  # whole-neighbour overlap needs ne >= 4
     dict(basis=2),                      # unknown basis
     dict(basis="gl", ne=(4, 3, 4)),     # GL: at least 4 elements per direction
