@@ -380,12 +380,16 @@ int sipg_server_fetch(sipg_server *s, int64_t id, double *u, void *hip_stream);
  * transfers and coarse solves per member.  Every member again computes
  * exactly what it computes alone.  0: each member's V-cycle on its own
  * stream.
- * SIPG_SERVER_TUNE (default 1): launch shapes of admitted requests.  0: the
- * built-in defaults; 1: the shapes the process-wide tuning cache holds for
- * the request's levels (see sipg_tuning_cache_load; no timing); 2:
- * sipg_autotune at admission (shapes already cached are taken without
- * timing), and at sipg_server_destroy the cache is saved to the file named
- * by SIPG_TUNING_CACHE, if set. */
+ * SIPG_SERVER_TUNE: launch shapes of admitted requests.  0 (the default):
+ * the built-in defaults; 1 (the default when SIPG_TUNING_CACHE names a cache
+ * file, which sipg_server_create then loads): the shapes the process-wide
+ * tuning cache holds for the request's levels (see sipg_tuning_cache_load;
+ * no timing); 2: sipg_autotune at admission (shapes already cached are
+ * taken without timing), and at sipg_server_destroy the cache is saved to
+ * the file named by SIPG_TUNING_CACHE, if set.  A served result equals,
+ * bitwise, the same solve run alone with the same launch shapes (the
+ * operator's launch shape sets the partition of the flexible-CG dot
+ * products). */
 typedef enum { SIPG_SERVER_FUSE_APPLY = 0, SIPG_SERVER_FUSE_SMOOTH = 1, SIPG_SERVER_TUNE = 2 } sipg_server_option;
 int sipg_server_set_option(sipg_server *s, int option, int value);
 

@@ -85,8 +85,9 @@ struct sipg_server {
   // their V-cycles together (segmented local solves and assemblies)
   bool fuse_smooth = true;
   // launch shapes of admitted contexts: 0 built-in, 1 the process-wide
-  // tuning cache, 2 autotuned at admission (cached shapes without timing)
-  int tune = 1;
+  // tuning cache, 2 autotuned at admission (cached shapes without timing);
+  // set at creation (1 when a tuning cache file is configured)
+  int tune = 0;
   int64_t smooth_cycles = 0, smooth_requests = 0;
   // captured cohort V-cycles by member contexts (in cohort order); an entry
   // is dropped when one of its members leaves.  A null graph: capture failed,
@@ -485,7 +486,10 @@ int sipg_server_create(size_t memory_budget, int max_active, sipg_server **out) 
   s->max_active = max_active;
   // a tuning cache saved earlier (a missing or unreadable file is ignored:
   // the requests then run with the built-in shapes)
-  if (const char *path = std::getenv("SIPG_TUNING_CACHE")) (void)sipg_tuning_cache_load(path, nullptr);
+  if (const char *path = std::getenv("SIPG_TUNING_CACHE")) {
+    (void)sipg_tuning_cache_load(path, nullptr);
+    s->tune = 1;
+  }
   *out = s;
   return SIPG_OK;
 }

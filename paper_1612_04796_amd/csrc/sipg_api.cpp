@@ -1291,10 +1291,20 @@ void tune_level(sipg_ctx *c, int l, int reps) {
       return;
     }
   }
-  ensure_work<T>(c);
-  Work<T> &w = work_of<T>(c);
   const int64_t N = level_ndof(c->H, l);
-  T *u = w.uL, *f = w.fL, *r = w.r;
+  T *u, *f, *r;
+  // a context with a single-precision preconditioner runs FP64 kernels only
+  // in the outer flexible CG (the top-level operator): time that one on the
+  // CG vectors, without the FP64 work space its footprint does not hold
+  const bool outer_only = std::is_same<T, double>::value && c->H.prm.precond_bits != 64;
+  if (outer_only) {
+    if (l != c->L) return;
+    u = reinterpret_cast<T *>(c->cg_p), f = reinterpret_cast<T *>(c->cg_b), r = reinterpret_cast<T *>(c->cg_q);
+  } else {
+    ensure_work<T>(c);
+    Work<T> &w = work_of<T>(c);
+    u = w.uL, f = w.fL, r = w.r;
+  }
   check(sipg::launch_fill<T>(u, N, (T)0.25, c->stream), "fill");
   check(sipg::launch_fill<T>(f, N, (T)0.5, c->stream), "fill");
   check(sipg::launch_fill<T>(r, N, (T)0.75, c->stream), "fill");
@@ -1314,8 +1324,9 @@ void tune_level(sipg_ctx *c, int l, int reps) {
     t.apply_epb = pick;
   }
   // compile-time-shape local solves: 1 .. the most subdomains that fit
-  const int maxspb = mf ? 0 : sipg::schwarz_fixed_max_spb(t.n, t.schwarz.m);
+  const int maxspb = mf || outer_only ? 0 : sipg::schwarz_fixed_max_spb(t.n, t.schwarz.m);
   if (maxspb > 1) {
+    Work<T> &w = work_of<T>(c);
     double best = 1e30;
     int pick = 0;
     for (int sp = 1; sp <= maxspb; ++sp) {

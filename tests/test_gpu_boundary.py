@@ -85,6 +85,14 @@ def test_footprint_covers_a_served_solve(P, ne, overlap, bits):
         it, rr = s.pcg_solve(x, b, rtol=1e-10, maxit=100)
         assert rr <= 1e-10
         assert s.device_bytes() == fp, (s.device_bytes(), fp)
+        # autotuning (as a served request with SIPG_SERVER_TUNE = 2) stays
+        # within the footprint too: a single-precision preconditioner's
+        # context times its FP64 operator on the CG vectors
+        s.autotune(reps=1)
+        assert s.device_bytes() == fp, (s.device_bytes(), fp)
+        x.zero_()
+        it2, rr2 = s.pcg_solve(x, b, rtol=1e-10, maxit=100)
+        assert rr2 <= 1e-10 and s.device_bytes() == fp
         s.close()
     stream.synchronize()
 
