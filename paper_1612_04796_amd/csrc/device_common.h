@@ -96,6 +96,22 @@ struct ApplyTabs {
 // Fast-diagonalization data of one level (Sec. 3.1): per direction the
 // eigenvectors S (m x m, S[a*m+j] = node a of pair j), the weighted
 // eigenvectors WS = diag(w) S and the eigenvalues, with m = n + 2 N_O.
+// A table pointer passed through an empty asm statement: loads through the
+// returned pointer cannot be hoisted above this point.  Fully unrolled
+// contractions take a fresh one per table row, so at most a row of table
+// entries (uniform values in scalar registers) is live at a time; with every
+// entry loadable up front the compiler fetched them all at the start and
+// spilled scalar registers into vector lanes (the even-odd local solves of
+// FP64 subdomains of 13 nodes or more per direction: up to 70 % of their
+// vector instructions were those spill moves).
+template <typename T>
+using ConstPtr = const __attribute__((address_space(4))) T *;  // read-only, scalar-loadable
+template <typename T>
+__device__ __forceinline__ ConstPtr<T> row_fence(const T *p) {
+  ConstPtr<T> q = (ConstPtr<T>)p;
+  asm volatile("" : "+s"(q));
+  return q;
+}
 template <typename T>
 struct SchwarzTabs {
   const T *S[3];

@@ -304,9 +304,10 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
       for (int i = 0; i < N; ++i) v[i] = sy[le * N3 + pq * N + i];
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
+        const auto Jr = row_fence(J);
         T acc = 0;
 #pragma unroll
-        for (int i = 0; i < N; ++i) acc += J[i * NC + a] * v[i];
+        for (int i = 0; i < N; ++i) acc += Jr[i * NC + a] * v[i];
         su[le * N3 + pq * NC + a] = acc;
       }
     }
@@ -320,9 +321,10 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
       for (int j = 0; j < N; ++j) v[j] = su[l2 * N3 + (k * N + j) * NC + a];
 #pragma unroll
       for (int b = 0; b < NC; ++b) {
+        const auto Jr = row_fence(J);
         T acc = 0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) acc += J[j * NC + b] * v[j];
+        for (int j = 0; j < N; ++j) acc += Jr[j * NC + b] * v[j];
         sy[l2 * N3 + (k * NC + b) * NC + a] = acc;
       }
     }
@@ -336,9 +338,10 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
       for (int k = 0; k < N; ++k) v[k] = sy[l2 * N3 + k * NC2 + ba];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
+        const auto Jr = row_fence(J);
         T acc = 0;
 #pragma unroll
-        for (int k = 0; k < N; ++k) acc += J[k * NC + c] * v[k];
+        for (int k = 0; k < N; ++k) acc += Jr[k * NC + c] * v[k];
         out[(size_t)(e0 + l2) * NC3 + c * NC2 + ba] = acc;
       }
     }

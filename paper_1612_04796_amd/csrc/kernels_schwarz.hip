@@ -239,6 +239,14 @@ struct FdmShape {
 // H NE + (m odd) NE + H^2 multiply-adds instead of m^2.  Table layout: see
 // pack_even_odd on the host.  K lines are transformed together, so that every
 // table entry (uniform, from the scalar cache) feeds K multiply-adds.
+// F: fence (else the plain pointer; the FP64 23^3 kernel spilled more with
+// the fences than without)
+template <bool F, typename T>
+__device__ __forceinline__ auto row_ptr(const T *p) {
+  if constexpr (F) return row_fence(p);
+  else return p;
+}
+
 template <int M>
 struct Eo {
   static constexpr int H = M / 2, NE = M - H, ODD = M & 1;
@@ -246,7 +254,7 @@ struct Eo {
   static constexpr int BE = FO + H * H, BC = BE + H * NE, BO = BC + ODD * NE;
 };
 
-template <typename T, int M, int K>
+template <typename T, int M, int K, bool F = true>
 __device__ __forceinline__ void eo_fwd(const T (&v)[K][M], T (&y)[K][M], const T *__restrict__ tab) {
   using E = Eo<M>;
   T sm[K][E::H], df[K][E::H];
@@ -262,47 +270,50 @@ __device__ __forceinline__ void eo_fwd(const T (&v)[K][M], T (&y)[K][M], const T
 #pragma unroll
     for (int j = 0; j < M; ++j) y[l][j] = 0;
   if constexpr (E::ODD) {
+    const auto t = row_ptr<F>(tab);
 #pragma unroll
     for (int j = 0; j < E::NE; ++j) {
-      const T c = tab[E::FC + j];
+      const T c = t[E::FC + j];
 #pragma unroll
       for (int l = 0; l < K; ++l) y[l][j] = c * v[l][E::H];
     }
   }
 #pragma unroll
   for (int a = 0; a < E::H; ++a) {
+    const auto t = row_ptr<F>(tab);
 #pragma unroll
     for (int j = 0; j < E::NE; ++j) {
-      const T c = tab[E::FE + a * E::NE + j];
+      const T c = t[E::FE + a * E::NE + j];
 #pragma unroll
       for (int l = 0; l < K; ++l) y[l][j] += c * sm[l][a];
     }
 #pragma unroll
     for (int j = 0; j < E::H; ++j) {
-      const T c = tab[E::FO + a * E::H + j];
+      const T c = t[E::FO + a * E::H + j];
 #pragma unroll
       for (int l = 0; l < K; ++l) y[l][E::NE + j] += c * df[l][a];
     }
   }
 }
 
-template <typename T, int M, int K>
+template <typename T, int M, int K, bool F = true>
 __device__ __forceinline__ void eo_bwd(const T (&y)[K][M], T (&x)[K][M], const T *__restrict__ tab) {
   using E = Eo<M>;
 #pragma unroll
   for (int a = 0; a < E::H; ++a) {
+    const auto t = row_ptr<F>(tab);
     T ev[K], od[K];
 #pragma unroll
     for (int l = 0; l < K; ++l) ev[l] = od[l] = 0;
 #pragma unroll
     for (int j = 0; j < E::NE; ++j) {
-      const T c = tab[E::BE + a * E::NE + j];
+      const T c = t[E::BE + a * E::NE + j];
 #pragma unroll
       for (int l = 0; l < K; ++l) ev[l] += c * y[l][j];
     }
 #pragma unroll
     for (int j = 0; j < E::H; ++j) {
-      const T c = tab[E::BO + a * E::H + j];
+      const T c = t[E::BO + a * E::H + j];
 #pragma unroll
       for (int l = 0; l < K; ++l) od[l] += c * y[l][E::NE + j];
     }
@@ -313,12 +324,13 @@ __device__ __forceinline__ void eo_bwd(const T (&y)[K][M], T (&x)[K][M], const T
     }
   }
   if constexpr (E::ODD) {
+    const auto t = row_ptr<F>(tab);
     T cs[K];
 #pragma unroll
     for (int l = 0; l < K; ++l) cs[l] = 0;
 #pragma unroll
     for (int j = 0; j < E::NE; ++j) {
-      const T c = tab[E::BC + j];
+      const T c = t[E::BC + j];
 #pragma unroll
       for (int l = 0; l < K; ++l) cs[l] += c * y[l][j];
     }
@@ -338,6 +350,7 @@ __device__ __forceinline__ void fdm_fixed_body(const Mesh &g, const SchwarzTabs<
   constexpr int RX = Sh::RX, VOL = Sh::VOL, TILE = Sh::TILE, K = Sh::LPT;
   constexpr int NOX = (MX - N) / 2, NOY = (MY - N) / 2, NOZ = (MZ - N) / 2;
   constexpr int N3 = N * N * N;
+  constexpr bool FENCE = !(sizeof(T) == 8 && MX >= 23 && MY >= 23 && MZ >= 23);
   extern __shared__ __align__(16) unsigned char fdm_smem[];
   T *t = reinterpret_cast<T *>(fdm_smem);
   int *nb = reinterpret_cast<int *>(fdm_smem + (size_t)spb * TILE * sizeof(T));  // 27 elements around each core
@@ -383,7 +396,7 @@ __device__ __forceinline__ void fdm_fixed_body(const Mesh &g, const SchwarzTabs<
         for (int a = 0; a < NOX; ++a) v[l][NOX + N + a] = rr[a];
       }
     }
-    eo_fwd<T, MX, K>(v, y, tb.EO[0]);
+    eo_fwd<T, MX, K, FENCE>(v, y, tb.EO[0]);
 #pragma unroll
     for (int l = 0; l < K; ++l) {
       const int li = tid + l * nth;
@@ -410,7 +423,7 @@ __device__ __forceinline__ void fdm_fixed_body(const Mesh &g, const SchwarzTabs<
 #pragma unroll
       for (int b = 0; b < MY; ++b) v[l][b] = base[b * RX];
     }
-    eo_fwd<T, MY, K>(v, y, tb.EO[1]);
+    eo_fwd<T, MY, K, FENCE>(v, y, tb.EO[1]);
 #pragma unroll
     for (int l = 0; l < K; ++l) {
       const int li = tid + l * nth;
@@ -438,7 +451,7 @@ __device__ __forceinline__ void fdm_fixed_body(const Mesh &g, const SchwarzTabs<
 #pragma unroll
       for (int c = 0; c < MZ; ++c) v[l][c] = base[c * st];
     }
-    eo_fwd<T, MZ, K>(v, y, tb.EO[2]);
+    eo_fwd<T, MZ, K, FENCE>(v, y, tb.EO[2]);
 #pragma unroll
     for (int l = 0; l < K; ++l) {
       const int li = min(tid + l * nth, nl - 1);
@@ -447,7 +460,7 @@ __device__ __forceinline__ void fdm_fixed_body(const Mesh &g, const SchwarzTabs<
 #pragma unroll
       for (int o = 0; o < MZ; ++o) y[l][o] *= il[o * MY * MX];
     }
-    eo_bwd<T, MZ, K>(y, v, tb.EO[2]);
+    eo_bwd<T, MZ, K, FENCE>(y, v, tb.EO[2]);
 #pragma unroll
     for (int l = 0; l < K; ++l) {
       const int li = tid + l * nth;
@@ -474,7 +487,7 @@ __device__ __forceinline__ void fdm_fixed_body(const Mesh &g, const SchwarzTabs<
 #pragma unroll
       for (int b = 0; b < MY; ++b) y[l][b] = base[b * RX];
     }
-    eo_bwd<T, MY, K>(y, v, tb.EO[1]);
+    eo_bwd<T, MY, K, FENCE>(y, v, tb.EO[1]);
 #pragma unroll
     for (int l = 0; l < K; ++l) {
       const int li = tid + l * nth;
@@ -500,7 +513,7 @@ __device__ __forceinline__ void fdm_fixed_body(const Mesh &g, const SchwarzTabs<
 #pragma unroll
       for (int o = 0; o < MX; ++o) y[l][o] = base[o];
     }
-    eo_bwd<T, MX, K>(y, v, tb.EO[0]);
+    eo_bwd<T, MX, K, FENCE>(y, v, tb.EO[0]);
 #pragma unroll
     for (int l = 0; l < K; ++l) {
       const int li = tid + l * nth;
