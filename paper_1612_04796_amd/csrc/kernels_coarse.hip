@@ -395,9 +395,50 @@ coarse_split_xy_bwd(Dims d, CoarseLaunch c, const double *__restrict__ t, double
 constexpr int kBigThreads = 256;
 constexpr int kBigChunk = 4096;  // line values per chunk in LDS
 
+// Contraction of the cl lines of length n in buf: out(l, o, v) receives
+// output o of line l; FWD: sum_a A[a*n + o] x[a], else sum_a A[o*n + a] x[a].
+// For n <= blockDim.x, thread t computes output o = t % n of lines
+// t / n + G r (G = blockDim.x / n line groups; a wavefront shares its line,
+// so the line entries are LDS broadcasts) for up to 8 lines at once, each
+// table entry loaded once for all of them.
+template <bool FWD, typename Out>
+__device__ void big_contract(const double *buf, int cl, int n, const double *__restrict__ A, Out out) {
+  constexpr int RB = 8;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if (n <= nth) {
+    const int G = nth / n, o = tid % n, lg = tid / n;
+    if (lg >= G) return;
+    for (int l0 = lg; l0 < cl; l0 += G * RB) {
+      double acc[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) acc[r] = 0.0;
+      for (int a = 0; a < n; ++a) {
+        const double av = FWD ? A[a * n + o] : A[o * n + a];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const int l = l0 + r * G;
+          if (l < cl) acc[r] += av * buf[l * n + a];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int l = l0 + r * G;
+        if (l < cl) out(l, o, acc[r]);
+      }
+    }
+  } else {
+    for (int i = tid; i < cl * n; i += nth) {
+      const int l = i / n, o = i - l * n;
+      const double *x = buf + l * n;
+      double acc = 0.0;
+      for (int a = 0; a < n; ++a) acc += (FWD ? A[a * n + o] : A[o * n + a]) * x[a];
+      out(l, o, acc);
+    }
+  }
+}
+
 // nl lines of length n: get(l, a) is entry a of line l, put(l, o, v) stores
-// output o; FWD: out[o] = sum_a A[a*n + o] in[a], else sum_a A[o*n + a] in[a]
-// lines lb .. le - 1 of a plane (the workgroup's part)
+// output o; lines lb .. le - 1 of a plane (the workgroup's part)
 template <bool FWD, typename Get, typename Put>
 __device__ void big_lines(double *buf, int lb, int le, int n, const double *__restrict__ A, Get get, Put put) {
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -409,13 +450,7 @@ __device__ void big_lines(double *buf, int lb, int le, int n, const double *__re
       buf[i] = get(l0 + l, i - l * n);
     }
     __syncthreads();
-    for (int i = tid; i < cl * n; i += nth) {
-      const int l = i / n, o = i - l * n;
-      const double *x = buf + l * n;
-      double acc = 0.0;
-      for (int a = 0; a < n; ++a) acc += (FWD ? A[a * n + o] : A[o * n + a]) * x[a];
-      put(l0 + l, o, acc);
-    }
+    big_contract<FWD>(buf, cl, n, A, [&](int l, int o, double v) { put(l0 + l, o, v); });
     __syncthreads();
   }
 }
@@ -493,21 +528,14 @@ __global__ void __launch_bounds__(kBigThreads) coarse_big_z(Dims d, CoarseLaunch
       buf[i] = ty[z * zs + x0 + l];
     }
     __syncthreads();
-    for (int i = tid; i < cl * Nz; i += blockDim.x) {
-      const int l = i / Nz, o = i - l * Nz, x = x0 + l;
-      double acc = 0.0;
-      for (int a = 0; a < Nz; ++a) acc += c.S[2][a * Nz + o] * buf[l * Nz + a];
+    big_contract<true>(buf, cl, Nz, c.S[2], [&](int l, int o, double acc) {
+      const int x = x0 + l;
       const double v = acc - mean * c.colsum[2][o] * c.colsum[0][x] * c.colsum[1][y];
       const bool zero = (x == c.zero[0] && y == c.zero[1] && o == c.zero[2]);
-      fw[i] = zero ? 0.0 : v / (c.lam[0][x] + c.lam[1][y] + c.lam[2][o]);
-    }
+      fw[l * Nz + o] = zero ? 0.0 : v / (c.lam[0][x] + c.lam[1][y] + c.lam[2][o]);
+    });
     __syncthreads();
-    for (int i = tid; i < cl * Nz; i += blockDim.x) {
-      const int l = i / Nz, o = i - l * Nz;
-      double acc = 0.0;
-      for (int a = 0; a < Nz; ++a) acc += c.S[2][o * Nz + a] * fw[l * Nz + a];
-      ty[o * zs + x0 + l] = acc;
-    }
+    big_contract<false>(fw, cl, Nz, c.S[2], [&](int l, int o, double acc) { ty[o * zs + x0 + l] = acc; });
     __syncthreads();
   }
 }
