@@ -55,12 +55,13 @@ def test_table1_methods_match_oracle_small(row):
     _compare(studies.table1_params(4, overlap, omega, ne=4, basis=basis, overlap_floor=floor), solver, ncyc=6)
 
 
+@pytest.mark.parametrize("solver", ["mg", "fcg"])
 @pytest.mark.parametrize("method", sorted(studies.ANISO_METHODS))
 @pytest.mark.parametrize("AR", [4, 8])
-def test_aniso_methods_match_oracle_small(method, AR):
-    announce(f"aniso {method} AR={AR} small")
+def test_aniso_methods_match_oracle_small(method, AR, solver):
+    announce(f"aniso {method} AR={AR} {solver} small")
     params = studies.aniso_params(AR, method, ne=4, P=4)
-    _compare(params, "mg", ncyc=6)
+    _compare(params, solver, ncyc=6)
 
 
 def _table1_paper():
@@ -106,28 +107,35 @@ def test_table1_gl_at_paper_meshes():
 
 
 def test_aniso_study_trends():
-    """The anisotropic study (8^3 elements, P = 16, AR up to 48), the parts
-    of the paper's account (Sec. 4, Anisotropic Meshes) that this build
-    reproduces: the overlap relative to each element's own width degrades
-    quickly with the aspect ratio; the overlap set by the largest element
-    side with the variable V-cycle ("max_var") keeps the cycle count nearly
-    constant up to AR = 12, grows beyond, and still converges at AR = 48
-    (the approach "feasible for aspect ratios up to 50").  Not reproduced,
-    and not asserted: the paper's 13 cycles at AR = 48 (27 here) and the
-    convergence of the relative-overlap methods beyond AR = 12 (they
-    diverge here); the readings tried for it are listed in the design
-    notes, the discrepancy is unresolved."""
+    """The anisotropic study (8^3 elements, P = 16, AR up to 48, the three
+    methods as preconditioners of flexible CG) against the paper's account
+    (Sec. 4, Anisotropic Meshes): the "max" overlap with the variable
+    V-cycle needs 4 cycles per ten decades on the isotropic mesh and at most
+    13 at AR = 48, and it is the best of the three at every aspect ratio
+    from 8 on; the fixed V-cycle with the relative overlap has slowed by
+    about two orders of magnitude at AR = 16 (its rate rho here grows by a
+    factor 30 to 300) but still converges; the variable V-cycle improves on
+    the fixed one up to AR = 12.  Not reproduced, and not asserted: the
+    relative overlap with the variable cycle keeping a nearly constant
+    count to AR = 12 and staying ahead of the fixed cycle beyond (it
+    stagnates from AR = 16 here); the design notes list the readings
+    tried."""
     announce("aniso study")
-    res = {(r["method"], r["AR"]): r for r in studies.run_aniso(ars=(1, 8, 16, 48), ncyc=40)}
-    for m in studies.ANISO_METHODS:
-        assert res[(m, 1)]["n10"] <= 6
-    assert res[("rel_fix", 8)]["neg_lg_rho"] < 0.5 * res[("rel_fix", 1)]["neg_lg_rho"]
-    assert res[("max_var", 16)]["neg_lg_rho"] > res[("rel_var", 16)]["neg_lg_rho"] + 1.0
-    n10 = [res[("max_var", ar)]["n10"] for ar in (1, 8, 16, 48)]
-    assert all(v is not None for v in n10), n10            # converges up to AR = 48
-    assert n10[0] <= 6 and n10[1] <= n10[0] + 1, n10       # nearly constant to AR = 8
-    assert n10[1:] == sorted(n10[1:]), n10                 # grows beyond
-    assert n10[2] <= 13, n10   # the paper's largest count for this method, here up to AR = 16
+    ars = (1, 8, 12, 16, 48)
+    res = {(r["method"], r["AR"]): r for r in studies.run_aniso(ars=ars)}
+    n10 = {m: [res[(m, ar)]["n10"] for ar in ars] for m in studies.ANISO_METHODS}
+    mv = n10["max_var"]
+    assert all(v is not None for v in mv), n10
+    assert mv[0] <= 4 and mv[-1] <= 13, n10                       # 4 ... 13 in the paper
+    assert mv == sorted(mv), n10                                    # grows with AR
+    for i, ar in enumerate(ars):
+        if ar >= 8:
+            assert mv[i] < n10["rel_fix"][i] and mv[i] < n10["rel_var"][i], (ar, n10)
+    slow = res[("rel_fix", 16)]["rho"] / res[("rel_fix", 1)]["rho"]
+    assert 30 <= slow <= 300 and n10["rel_fix"][3] is not None, (slow, n10)
+    for i, ar in enumerate(ars):
+        if ar <= 12:
+            assert n10["rel_var"][i] <= n10["rel_fix"][i], (ar, n10)
 
 
 def test_fig5_mesh_independence_and_rates():
