@@ -288,7 +288,11 @@ wide_mfma2(int E, SchwarzTabs<T> tb, const T *__restrict__ ilam, T *__restrict__
   for (int i = lane; i < plane; i += 64) P[i] = (T)0;
   __syncthreads();
   const int V = mx * mz, J = CT ? JM : (V + 63) >> 6;
-  const int total = E * my, first = (blockIdx.x * NW + w) * ppw;
+  // the waves of a workgroup take adjacent planes at each step (plane
+  // base + q NW + w at step q): a plane's rows of m_x values lie between
+  // those of its y neighbours in W, so the workgroup reads and writes whole
+  // cache lines together
+  const int total = E * my, first = blockIdx.x * NW * ppw + w;
   if (first >= total) return;
   auto valid = [&](int j) { return j < J && lane + 64 * j < V; };
   T buf[JM], lam[JM];
@@ -326,7 +330,7 @@ wide_mfma2(int E, SchwarzTabs<T> tb, const T *__restrict__ ilam, T *__restrict__
   };
   load(first);
   for (int q = 0; q < ppw; ++q) {
-    const int gp = first + q;
+    const int gp = first + q * NW;
     if (gp >= total) break;
     const int s = gp / my, b = gp - s * my;
     // the scaling of this plane is loaded with it, in flight during the
@@ -337,7 +341,7 @@ wide_mfma2(int E, SchwarzTabs<T> tb, const T *__restrict__ ilam, T *__restrict__
       lam[j] = lb[wof];
     });
     wave_sync();
-    if (q + 1 < ppw && gp + 1 < total) load(gp + 1);
+    if (q + 1 < ppw && gp + NW < total) load(gp + NW);
     wave_contract<T, A, C, ks_of(MZ)>(P, 1, pp, mx, mz, Ff);
     for_entries([&](int j, int o, int) { P[o] *= lam[j]; });
     wave_sync();
