@@ -26,6 +26,9 @@ struct ApplyLaunch {
   const T *J;       // RESTRICT: n x nc interpolation matrix
   int nc;           // RESTRICT: coarse nodes per direction
   int epb = 0;      // elements per workgroup (0: the default choice)
+  // PLAIN with T = double: a single-precision input vector in place of u
+  // (read and promoted to double; n <= 17)
+  const float *u32 = nullptr;
 };
 template <typename T>
 hipError_t launch_apply(const ApplyLaunch<T> &a, hipStream_t st);
@@ -244,11 +247,13 @@ hipError_t launch_fcg_dot2(const TZ *z, const double *q, const double *r, int64_
 //   s[ZQ], s[RZNEW] from those partials; beta = -alpha s[ZQ] / s[RZ]; s[RZ] = s[RZNEW]
 hipError_t launch_fcg_finalize2(const double *partial, double *s, hipStream_t st);
 //   x += alpha p (deferred from the residual update, when update_x); p = z + beta p
-template <typename TZ>
-hipError_t launch_fcg_xp(double *x, double *p, const TZ *z, int64_t n, const double *s, bool update_x,
+//   (p in double, or in single precision with a single-precision z)
+template <typename TZ, typename TP>
+hipError_t launch_fcg_xp(double *x, TP *p, const TZ *z, int64_t n, const double *s, bool update_x,
                          hipStream_t st);
 //   x += alpha p (before a convergence check of the true residual)
-hipError_t launch_fcg_x(double *x, const double *p, int64_t n, const double *s, hipStream_t st);
+template <typename TP>
+hipError_t launch_fcg_x(double *x, const TP *p, int64_t n, const double *s, hipStream_t st);
 
 // Fourier right-hand side: b = M f(nodes) (before mean removal)
 struct RhsLaunch {

@@ -27,6 +27,8 @@
 // nodes is fixed by n: n_c = 2^floor(log2(n - 2)) + 1.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 
 #include "device_common.h"
@@ -61,8 +63,9 @@ struct FaceData {
   T vR, gR, vL, gL;
 };
 
-template <typename T, int N, bool GL>
-__device__ __forceinline__ FaceData<T> face_data(const T *__restrict__ lr, const T *__restrict__ ll, int st,
+// (lines stored in TI, computed in T)
+template <typename T, int N, bool GL, typename TI>
+__device__ __forceinline__ FaceData<T> face_data(const TI *__restrict__ lr, const TI *__restrict__ ll, int st,
                                                  const T *__restrict__ DL, const T *__restrict__ DR,
                                                  const T *__restrict__ TL, const T *__restrict__ TR) {
   FaceData<T> fd;
@@ -71,7 +74,7 @@ __device__ __forceinline__ FaceData<T> face_data(const T *__restrict__ lr, const
     T vR = 0, vL = 0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const T r = lr[i * st], l = ll[i * st];
+      const T r = (T)lr[i * st], l = (T)ll[i * st];
       gR += DL[i] * r;
       gL += DR[i] * l;
       vR += TL[i] * r;
@@ -82,11 +85,11 @@ __device__ __forceinline__ FaceData<T> face_data(const T *__restrict__ lr, const
   } else {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      gR += DL[i] * lr[i * st];
-      gL += DR[i] * ll[i * st];
+      gR += DL[i] * (T)lr[i * st];
+      gL += DR[i] * (T)ll[i * st];
     }
-    fd.vR = lr[0];
-    fd.vL = ll[(N - 1) * st];
+    fd.vR = (T)lr[0];
+    fd.vL = (T)ll[(N - 1) * st];
   }
   fd.gR = gR;
   fd.gL = gL;
@@ -154,6 +157,7 @@ struct ApplySeg {
   const T *J;
   int blk0, nblk;
   bool nt, tiled;
+  const float *u32;  // the input when the kernel reads single precision
 };
 template <typename T>
 struct ApplySegs {
@@ -163,10 +167,11 @@ struct ApplySegs {
 
 // EPB (elements per workgroup) is chosen at launch, at most ApplyShape<N>::EPB.
 // SEG: the launch covers the segments in `segs` (every other operand except
-// EPB is taken from the workgroup's segment).
-template <typename T, int N, int MODE, bool DOT, bool SEG, bool GL>
+// EPB is taken from the workgroup's segment).  TI: the precision u is stored
+// in (promoted to T on load).
+template <typename T, int N, int MODE, bool DOT, bool SEG, bool GL, typename TI = T>
 __global__ void __launch_bounds__(ApplyShape<N>::NTH)
-apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restrict__ f, T *__restrict__ out,
+apply_kernel(Mesh g, ApplyTabs<T> tb, const TI *__restrict__ u, const T *__restrict__ f, T *__restrict__ out,
              T *__restrict__ partial, const T *__restrict__ J, int EPB, bool nt, bool tiled, ApplySegs<T> segs) {
   using Sh = ApplyShape<N>;
   int bid = blockIdx.x, nblocks = gridDim.x;
@@ -176,7 +181,8 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
     const ApplySeg<T> &a = segs.s[k];
     g = a.g;
     tb = a.tb;
-    u = a.u;
+    if constexpr (std::is_same<TI, T>::value) u = a.u;
+    else u = a.u32;
     f = a.f;
     out = a.out;
     partial = a.partial;
@@ -207,7 +213,7 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const int idx = t + j * (int)blockDim.x;
-    st[j] = idx < nloc * N3 ? u[(size_t)e0 * N3 + idx] : (T)0;
+    st[j] = idx < nloc * N3 ? (T)u[(size_t)e0 * N3 + idx] : (T)0;
   }
   T fl[N];
   if (MODE != MODE_APPLY && active) {
@@ -222,15 +228,15 @@ apply_kernel(Mesh g, ApplyTabs<T> tb, const T *__restrict__ u, const T *__restri
     const int e = e0 + le;
     const int ex = e % g.ne[0], rest = e / g.ne[0];
     const int ey = rest % g.ne[1], ez = rest / g.ne[1];
-    const T *uxr = u + (size_t)elem_index(g, wrap(ex + 1, g.ne[0]), ey, ez) * N3 + pq * N;
-    const T *uxl = u + (size_t)elem_index(g, wrap(ex - 1, g.ne[0]), ey, ez) * N3 + pq * N;
-    const T *uyr = u + (size_t)elem_index(g, ex, wrap(ey + 1, g.ne[1]), ez) * N3 + p * N2 + q;
-    const T *uyl = u + (size_t)elem_index(g, ex, wrap(ey - 1, g.ne[1]), ez) * N3 + p * N2 + q;
-    const T *uzr = u + (size_t)elem_index(g, ex, ey, wrap(ez + 1, g.ne[2])) * N3 + pq;
-    const T *uzl = u + (size_t)elem_index(g, ex, ey, wrap(ez - 1, g.ne[2])) * N3 + pq;
-    fx = face_data<T, N, GL>(uxr, uxl, 1, tb.DL[0], tb.DR[0], tb.TL[0], tb.TR[0]);
-    fy = face_data<T, N, GL>(uyr, uyl, N, tb.DL[1], tb.DR[1], tb.TL[1], tb.TR[1]);
-    fz = face_data<T, N, GL>(uzr, uzl, N2, tb.DL[2], tb.DR[2], tb.TL[2], tb.TR[2]);
+    const TI *uxr = u + (size_t)elem_index(g, wrap(ex + 1, g.ne[0]), ey, ez) * N3 + pq * N;
+    const TI *uxl = u + (size_t)elem_index(g, wrap(ex - 1, g.ne[0]), ey, ez) * N3 + pq * N;
+    const TI *uyr = u + (size_t)elem_index(g, ex, wrap(ey + 1, g.ne[1]), ez) * N3 + p * N2 + q;
+    const TI *uyl = u + (size_t)elem_index(g, ex, wrap(ey - 1, g.ne[1]), ez) * N3 + p * N2 + q;
+    const TI *uzr = u + (size_t)elem_index(g, ex, ey, wrap(ez + 1, g.ne[2])) * N3 + pq;
+    const TI *uzl = u + (size_t)elem_index(g, ex, ey, wrap(ez - 1, g.ne[2])) * N3 + pq;
+    fx = face_data<T, N, GL, TI>(uxr, uxl, 1, tb.DL[0], tb.DR[0], tb.TL[0], tb.TR[0]);
+    fy = face_data<T, N, GL, TI>(uyr, uyl, N, tb.DL[1], tb.DR[1], tb.TL[1], tb.TR[1]);
+    fz = face_data<T, N, GL, TI>(uzr, uzl, N2, tb.DL[2], tb.DR[2], tb.TL[2], tb.TR[2]);
   }
 #pragma unroll
   for (int j = 0; j < N; ++j) {
@@ -480,6 +486,12 @@ bool tiled_order(const Mesh &g) {
   return (int64_t)g.ne[0] * g.ne[1] * N * N * N * (int64_t)sizeof(T) >= (2 << 20);
 }
 
+// a single-precision input only for y = A u in double
+template <typename T, int MODE>
+constexpr bool single_input_ok() {
+  return MODE == MODE_APPLY && std::is_same<T, double>::value;
+}
+
 template <typename T, int N, int MODE, bool DOT, bool GL>
 hipError_t launch_mode_b(const ApplyLaunch<T> &a, hipStream_t st) {
   using Sh = ApplyShape<N>;
@@ -487,9 +499,19 @@ hipError_t launch_mode_b(const ApplyLaunch<T> &a, hipStream_t st) {
   const int nblk = (a.mesh.E + epb - 1) / epb;
   const int nth = std::min(Sh::NTH, (epb * N * N + 63) / 64 * 64);
   const size_t shm = 2 * (size_t)epb * N * N * N * sizeof(T);
+  const bool nt = out_streams<T, N>(a.mesh), tiled = tiled_order<T, N>(a.mesh);
+  if (a.u32) {
+    if constexpr (single_input_ok<T, MODE>()) {
+      hipError_t e = allow_lds(apply_kernel<T, N, MODE, DOT, false, GL, float>, shm);
+      if (e != hipSuccess) return e;
+      apply_kernel<T, N, MODE, DOT, false, GL, float><<<nblk, nth, shm, st>>>(
+          a.mesh, a.tabs, a.u32, a.f, a.out, a.partial, a.J, epb, nt, tiled, ApplySegs<T>{});
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   hipError_t e = allow_lds(apply_kernel<T, N, MODE, DOT, false, GL>, shm);
   if (e != hipSuccess) return e;
-  const bool nt = out_streams<T, N>(a.mesh), tiled = tiled_order<T, N>(a.mesh);
   apply_kernel<T, N, MODE, DOT, false, GL><<<nblk, nth, shm, st>>>(a.mesh, a.tabs, a.u, a.f, a.out, a.partial, a.J,
                                                                    epb, nt, tiled, ApplySegs<T>{});
   return hipGetLastError();
@@ -581,25 +603,37 @@ hipError_t launch_segments_n(const ApplyLaunch<T> *a, int n, hipStream_t st) {
   S.n = n;
   int blk = 0;
   const bool gl = a[0].tabs.gl != 0;
+  const bool in32 = a[0].u32 != nullptr;
+  if (in32 && mode != APPLY_PLAIN) return hipErrorInvalidValue;
   for (int k = 0; k < n; ++k) {
     if (a[k].n != N || a[k].mode != mode || (a[k].partial != nullptr) != dot ||
         launch_epb(a[k].mesh.E, N, a[k].epb) != epb || (a[k].tabs.gl != 0) != gl ||
-        (mode == APPLY_RESTRICT && a[k].nc != coarse_n(N)))
+        (a[k].u32 != nullptr) != in32 || (mode == APPLY_RESTRICT && a[k].nc != coarse_n(N)))
       return hipErrorInvalidValue;
     const int nblk = (a[k].mesh.E + epb - 1) / epb;
     S.s[k] = ApplySeg<T>{a[k].mesh, a[k].tabs, a[k].u, a[k].f, a[k].out, a[k].partial, a[k].J,
-                         blk, nblk, out_streams<T, N>(a[k].mesh), tiled_order<T, N>(a[k].mesh)};
+                         blk, nblk, out_streams<T, N>(a[k].mesh), tiled_order<T, N>(a[k].mesh), a[k].u32};
     blk += nblk;
   }
   const int nth = std::min(Sh::NTH, (epb * N * N + 63) / 64 * 64);
   const size_t shm = 2 * (size_t)epb * N * N * N * sizeof(T);
   const ApplyLaunch<T> &a0 = a[0];
-  auto go = [&](auto kernel) {
+  auto go_in = [&](auto kernel, auto u0) {
     hipError_t e = allow_lds(kernel, shm);
     if (e != hipSuccess) return e;
-    kernel<<<blk, nth, shm, st>>>(a0.mesh, a0.tabs, a0.u, a0.f, a0.out, a0.partial, a0.J, epb, false, false, S);
+    kernel<<<blk, nth, shm, st>>>(a0.mesh, a0.tabs, u0, a0.f, a0.out, a0.partial, a0.J, epb, false, false, S);
     return hipGetLastError();
   };
+  auto go = [&](auto kernel) { return go_in(kernel, a0.u); };
+  if (in32) {
+    if constexpr (single_input_ok<T, MODE_APPLY>()) {
+      if (dot) return gl ? go_in(apply_kernel<T, N, MODE_APPLY, true, true, true, float>, a0.u32)
+                         : go_in(apply_kernel<T, N, MODE_APPLY, true, true, false, float>, a0.u32);
+      return gl ? go_in(apply_kernel<T, N, MODE_APPLY, false, true, true, float>, a0.u32)
+                : go_in(apply_kernel<T, N, MODE_APPLY, false, true, false, float>, a0.u32);
+    }
+    return hipErrorInvalidValue;
+  }
   if (mode == APPLY_RESTRICT) {
     if constexpr (N >= 3)
       return gl ? go(apply_kernel<T, N, MODE_RESTRICT, false, true, true>)

@@ -211,23 +211,25 @@ fcg_dot2_kernel(const TZ *__restrict__ z, const double *__restrict__ q, const do
   }
 }
 
-// x += alpha p (when update_x); p = z + beta p
-template <typename TZ>
+// x += alpha p (when update_x); p = z + beta p, formed in double and stored
+// in p's precision
+template <typename TZ, typename TP>
 __global__ void __launch_bounds__(256)
-fcg_xp_kernel(double *__restrict__ x, double *__restrict__ p, const TZ *__restrict__ z, int64_t n,
+fcg_xp_kernel(double *__restrict__ x, TP *__restrict__ p, const TZ *__restrict__ z, int64_t n,
               const double *__restrict__ s, int update_x) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double pi = p[i];
+  const double pi = (double)p[i];
   if (update_x) x[i] += s[FS_ALPHA] * pi;
-  p[i] = (double)z[i] + s[FS_BETA] * pi;
+  p[i] = (TP)((double)z[i] + s[FS_BETA] * pi);
 }
 
 // x += alpha p
+template <typename TP>
 __global__ void __launch_bounds__(256)
-fcg_x_kernel(double *__restrict__ x, const double *__restrict__ p, int64_t n, const double *__restrict__ s) {
+fcg_x_kernel(double *__restrict__ x, const TP *__restrict__ p, int64_t n, const double *__restrict__ s) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] += s[FS_ALPHA] * p[i];
+  if (i < n) x[i] += s[FS_ALPHA] * (double)p[i];
 }
 
 __global__ void __launch_bounds__(256) rhs_kernel(RhsLaunch a, double *__restrict__ b) {
@@ -332,15 +334,16 @@ hipError_t launch_fcg_dot2(const TZ *z, const double *q, const double *r, int64_
   return hipGetLastError();
 }
 
-template <typename TZ>
-hipError_t launch_fcg_xp(double *x, double *p, const TZ *z, int64_t n, const double *s, bool update_x,
+template <typename TZ, typename TP>
+hipError_t launch_fcg_xp(double *x, TP *p, const TZ *z, int64_t n, const double *s, bool update_x,
                          hipStream_t st) {
-  fcg_xp_kernel<TZ><<<nblocks(n), 256, 0, st>>>(x, p, z, n, s, update_x ? 1 : 0);
+  fcg_xp_kernel<TZ, TP><<<nblocks(n), 256, 0, st>>>(x, p, z, n, s, update_x ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_fcg_x(double *x, const double *p, int64_t n, const double *s, hipStream_t st) {
-  fcg_x_kernel<<<nblocks(n), 256, 0, st>>>(x, p, n, s);
+template <typename TP>
+hipError_t launch_fcg_x(double *x, const TP *p, int64_t n, const double *s, hipStream_t st) {
+  fcg_x_kernel<TP><<<nblocks(n), 256, 0, st>>>(x, p, n, s);
   return hipGetLastError();
 }
 
@@ -358,10 +361,14 @@ template hipError_t launch_fcg_dot2<double>(const double *, const double *, cons
                                             hipStream_t);
 template hipError_t launch_fcg_dot2<float>(const float *, const double *, const double *, int64_t, double *,
                                            hipStream_t);
-template hipError_t launch_fcg_xp<double>(double *, double *, const double *, int64_t, const double *, bool,
-                                          hipStream_t);
-template hipError_t launch_fcg_xp<float>(double *, double *, const float *, int64_t, const double *, bool,
-                                         hipStream_t);
+template hipError_t launch_fcg_xp<double, double>(double *, double *, const double *, int64_t, const double *,
+                                                  bool, hipStream_t);
+template hipError_t launch_fcg_xp<float, double>(double *, double *, const float *, int64_t, const double *, bool,
+                                                 hipStream_t);
+template hipError_t launch_fcg_xp<float, float>(double *, float *, const float *, int64_t, const double *, bool,
+                                                hipStream_t);
+template hipError_t launch_fcg_x<double>(double *, const double *, int64_t, const double *, hipStream_t);
+template hipError_t launch_fcg_x<float>(double *, const float *, int64_t, const double *, hipStream_t);
 template hipError_t launch_sub_scalar<double>(double *, int64_t, const double *, hipStream_t);
 template hipError_t launch_sub_scalar_copy<double>(const double *, double *, int64_t, const double *, hipStream_t);
 template hipError_t launch_sub_scalar<float>(float *, int64_t, const double *, hipStream_t);
@@ -370,6 +377,7 @@ template hipError_t launch_sum_partials<float>(const float *, int64_t, double *,
 template hipError_t launch_fill<double>(double *, int64_t, double, hipStream_t);
 template hipError_t launch_fill<float>(float *, int64_t, float, hipStream_t);
 template hipError_t launch_convert<double, double>(const double *, double *, int64_t, hipStream_t);
+template hipError_t launch_convert<float, float>(const float *, float *, int64_t, hipStream_t);
 template hipError_t launch_convert<float, double>(const double *, float *, int64_t, hipStream_t);
 template hipError_t launch_convert<double, float>(const float *, double *, int64_t, hipStream_t);
 

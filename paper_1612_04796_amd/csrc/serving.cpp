@@ -51,8 +51,9 @@ using Clock = std::chrono::steady_clock;
 enum Phase { PH_START = 0, PH_ITER = 1, PH_CONFIRM = 2 };
 
 // batching key: order (nodes per direction), elements per operator
-// workgroup, size class (unknowns in [8^k, 8^(k+1)))
-using BatchKey = std::tuple<int, int, int>;
+// workgroup, size class (unknowns in [8^k, 8^(k+1))), precision of the
+// operator's input p (1: single)
+using BatchKey = std::tuple<int, int, int, int>;
 
 struct Request {
   int64_t id = 0;
@@ -404,7 +405,7 @@ bool batch_key(sipg_server *s, Request *r, BatchKey *key, sipg::ApplyLaunch<doub
   if (!s->fuse || !sipg::detail::fcg_apply_launch(r->ctx, a)) return false;
   int cls = 0;
   while ((r->ndof >> (3 * (cls + 1))) > 0) ++cls;
-  *key = std::make_tuple(a->n, a->epb, cls);
+  *key = std::make_tuple(a->n, a->epb, cls, a->u32 ? 1 : 0);
   return true;
 }
 

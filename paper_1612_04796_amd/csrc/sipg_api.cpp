@@ -1067,6 +1067,30 @@ void precond_cohort(sipg_ctx *const *cs, int k, hipStream_t st) {
 namespace sipg {
 namespace detail {
 
+// With a single-precision preconditioner the search direction p is kept in
+// single precision (in the first half of the cg_p buffer): p = z + beta p is
+// formed in double and rounded once, and x += alpha p, q = A p (in double)
+// use that same rounded p, so x and r stay consistent and only the
+// direction, not the accuracy of the iterate, carries the rounding (flexible
+// CG tolerates a perturbed direction).  Orders whose operator takes the
+// large-element path keep p in double.
+bool p_single(const sipg_ctx *c) {
+  return c->H.prm.precond_bits != 64 && !sipg::apply_is_large(c->t64[c->L].n);
+}
+float *p32_of(sipg_ctx *c) { return reinterpret_cast<float *>(c->cg_p); }
+
+// q = A p (with per-block partials of p.q when partial is given)
+void fcg_apply_p(sipg_ctx *c, double *partial) {
+  if (p_single(c)) {
+    const LevelTabs<double> &t = c->t64[c->L];
+    sipg::ApplyLaunch<double> a{c->mesh, t.n, t.apply, nullptr, nullptr, c->cg_q, sipg::APPLY_PLAIN, partial,
+                                nullptr, 0, t.apply_epb, p32_of(c)};
+    check(sipg::launch_apply<double>(a, c->stream), "apply_A");
+  } else {
+    op_apply<double>(c, c->L, c->cg_p, c->cg_q, partial);
+  }
+}
+
 void fcg_start(sipg_ctx *c, double *x, const double *b) {
   project_rhs(c, b);
   residual_norm2(c, x, c->cg_b, c->cg_r, sipg::FS_RR, true);
@@ -1082,7 +1106,8 @@ void fcg_first_precond(sipg_ctx *c) {
   fcg_precond(c);
   if (single) {
     check(sipg::launch_dot_partials<double, float>(c->cg_r, c->w32.uL, N, c->partial, c->stream), "dot");
-    check(sipg::launch_convert<double, float>(c->w32.uL, c->cg_p, N, c->stream), "copy");
+    if (p_single(c)) check(sipg::launch_convert<float, float>(c->w32.uL, p32_of(c), N, c->stream), "copy");
+    else check(sipg::launch_convert<double, float>(c->w32.uL, c->cg_p, N, c->stream), "copy");
   } else {
     check(sipg::launch_dot_partials<double, double>(c->cg_r, c->cg_z, N, c->partial, c->stream), "dot");
     check(sipg::launch_convert<double, double>(c->cg_z, c->cg_p, N, c->stream), "copy");
@@ -1128,19 +1153,24 @@ void fcg_after_apply_batched(sipg_ctx *const *cs, int k, hipStream_t st) {
 bool fcg_apply_launch(sipg_ctx *c, sipg::ApplyLaunch<double> *a) {
   const LevelTabs<double> &t = c->t64[c->L];
   if (sipg::apply_is_large(t.n)) return false;
-  *a = sipg::ApplyLaunch<double>{c->mesh, t.n, t.apply, c->cg_p, nullptr, c->cg_q, sipg::APPLY_PLAIN, c->partial,
-                                 nullptr, 0, sipg::apply_launch_epb(c->mesh.E, t.n, t.apply_epb)};
+  const bool ps = p_single(c);
+  *a = sipg::ApplyLaunch<double>{c->mesh, t.n, t.apply, ps ? nullptr : c->cg_p, nullptr, c->cg_q,
+                                 sipg::APPLY_PLAIN, c->partial, nullptr, 0,
+                                 sipg::apply_launch_epb(c->mesh.E, t.n, t.apply_epb), ps ? p32_of(c) : nullptr};
   return true;
 }
 
 void fcg_apply_update(sipg_ctx *c) {
-  op_apply<double>(c, c->L, c->cg_p, c->cg_q, c->partial);
+  fcg_apply_p(c, c->partial);
   fcg_after_apply(c, c->stream);
 }
 
 void fcg_confirm(sipg_ctx *c, double *x) {
   const int64_t N = level_ndof(c->H, c->L);
-  if (c->x_pending) check(sipg::launch_fcg_x(x, c->cg_p, N, c->scal, c->stream), "fcg update");
+  if (c->x_pending) {
+    if (p_single(c)) check(sipg::launch_fcg_x<float>(x, p32_of(c), N, c->scal, c->stream), "fcg update");
+    else check(sipg::launch_fcg_x<double>(x, c->cg_p, N, c->scal, c->stream), "fcg update");
+  }
   c->x_pending = false;
   // the returned iterate has zero mean (A 1 = 0: the residual is unchanged)
   remove_mean(c, x);
@@ -1152,7 +1182,7 @@ void fcg_restart_from_true(sipg_ctx *c) {
   check(sipg::launch_convert<double, double>(c->cg_q, c->cg_r, N, c->stream), "copy");
   if (c->H.prm.precond_bits != 64)
     check(sipg::launch_convert<float, double>(c->cg_r, c->w32.fL, N, c->stream), "precond cast");
-  op_apply<double>(c, c->L, c->cg_p, c->cg_q, nullptr);
+  fcg_apply_p(c, nullptr);
 }
 
 // after z = B r: beta, rz, x += alpha p if pending, p = z + beta p
@@ -1161,11 +1191,17 @@ void fcg_after_precond(sipg_ctx *c, double *x) {
   if (c->H.prm.precond_bits != 64) {
     check(sipg::launch_fcg_dot2<float>(c->w32.uL, c->cg_q, c->cg_r, N, c->partial, c->stream), "dot2");
     check(sipg::launch_fcg_finalize2(c->partial, c->scal, c->stream), "dot2");
-    check(sipg::launch_fcg_xp<float>(x, c->cg_p, c->w32.uL, N, c->scal, c->x_pending, c->stream), "fcg update");
+    if (p_single(c))
+      check(sipg::launch_fcg_xp<float, float>(x, p32_of(c), c->w32.uL, N, c->scal, c->x_pending, c->stream),
+            "fcg update");
+    else
+      check(sipg::launch_fcg_xp<float, double>(x, c->cg_p, c->w32.uL, N, c->scal, c->x_pending, c->stream),
+            "fcg update");
   } else {
     check(sipg::launch_fcg_dot2<double>(c->cg_z, c->cg_q, c->cg_r, N, c->partial, c->stream), "dot2");
     check(sipg::launch_fcg_finalize2(c->partial, c->scal, c->stream), "dot2");
-    check(sipg::launch_fcg_xp<double>(x, c->cg_p, c->cg_z, N, c->scal, c->x_pending, c->stream), "fcg update");
+    check(sipg::launch_fcg_xp<double, double>(x, c->cg_p, c->cg_z, N, c->scal, c->x_pending, c->stream),
+          "fcg update");
   }
   c->x_pending = false;
 }
