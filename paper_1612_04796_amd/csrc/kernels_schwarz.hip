@@ -532,13 +532,31 @@ __device__ __forceinline__ void fdm_fixed_body(const Mesh &g, const SchwarzTabs<
   {
     T *out = C + (size_t)s0 * VOL;
     const int tot = nsub * VOL;
-    for (int i = tid; i < tot; i += nth) {
-      if constexpr (RX == MX) {
-        out[i] = t[i + (i / VOL) * (TILE - VOL)];
-      } else {
-        const int q = i / VOL, rem = i - q * VOL;
-        const int row = rem / MX, a = rem - row * MX;
-        out[i] = t[q * TILE + row * RX + a];
+    constexpr int VW = 16 / (int)sizeof(T);  // values per 16-byte store
+    if constexpr (RX != MX && MX % VW == 0) {
+      // 16-byte stores (a subdomain's run starts 16-byte aligned, VOL being
+      // a multiple of VW); the tile holds the run's rows of MX values RX
+      // apart (TILE = MZ MY RX), so entry i sits at (i / MX) RX + i % MX:
+      // one division per VW values instead of two per value
+      typedef T V __attribute__((ext_vector_type(VW)));
+      V *ov = reinterpret_cast<V *>(out);
+      for (int j = tid; j < tot / VW; j += nth) {
+        const int i = j * VW, row = i / MX, a = i - row * MX;
+        const T *src = t + row * RX + a;
+        V v;
+#pragma unroll
+        for (int u = 0; u < VW; ++u) v[u] = src[u];
+        ov[j] = v;
+      }
+    } else {
+      for (int i = tid; i < tot; i += nth) {
+        if constexpr (RX == MX) {
+          out[i] = t[i + (i / VOL) * (TILE - VOL)];
+        } else {
+          const int q = i / VOL, rem = i - q * VOL;
+          const int row = rem / MX, a = rem - row * MX;
+          out[i] = t[q * TILE + row * RX + a];
+        }
       }
     }
   }
