@@ -237,6 +237,34 @@ def test_fp32_preconditioner(ne, length, P, overlap):
     s.close()
 
 
+@pytest.mark.parametrize("bits", [32, 16])
+@pytest.mark.parametrize("ne,length,P,overlap,basis", [
+    ((4, 4, 4), (1.0, 1.0, 1.0), 8, "rel", "gll"),
+    ((4, 4, 4), (4.0, 1.0, 1.0), 8, "max", "gll"),
+    ((4, 4, 4), (1.0, 1.0, 1.0), 16, "rel", "gll"),
+    ((4, 4, 5), (1.0, 1.0, 1.0), 7, "rel", "gl"),
+])
+def test_single_precision_preconditioner_solves(ne, length, P, overlap, basis, bits):
+    """Flexible CG with a single-precision preconditioner (FP32, or FP32 with
+    FP16 local solves where the order has them), whose search direction p is
+    kept in FP32 and read by the FP64 outer operator: the solve reaches 1e-10,
+    ends within 1e-8 of the oracle's exact discrete solution and needs at
+    most one iteration more than the oracle's FP64 flexible CG (orders 7, 8
+    and 16, both bases: each single-precision-input operator kernel)."""
+    from paper_1612_04796_amd import sipg
+    announce("single precision solve", ne, length, P, overlap, basis, bits)
+    h = oracle.Hierarchy(ne, length, P, overlap=overlap, omega=0.08, basis=basis)
+    s = sipg.Solver(ne=ne, length=length, P=P, overlap=overlap, omega=0.08, basis=basis, precond_bits=bits)
+    k, phi, amp = fourier_modes(0, 3)
+    b = oracle.fourier_rhs(k, phi, amp, h)
+    x = zeros(h.ndof())
+    it, rr = s.pcg_solve(x, dev(b), rtol=1e-10, maxit=60)
+    s.close()
+    _, ito, _, _ = oracle.fcg_solve(b, h, tol=1e-10, maxit=60)
+    assert rr <= 1e-10 and it <= ito + 1, (it, ito)
+    assert rel(host(x), oracle.exact_solution(b, h)) <= 1e-8
+
+
 # ---- order 32: elements of 33^3 nodes (global-memory operator passes) and
 # subdomains up to 99 nodes wide (plane-by-plane Schwarz) -------------------
 @pytest.mark.parametrize("ne,length,overlap", [((3, 3, 4), (1.0, 1.0, 1.0), "rel"),
