@@ -171,6 +171,47 @@ def test_batched_operator_launches_keep_results(bits):
                 assert np.array_equal(host(u), xs), (fuse, i)
 
 
+@pytest.mark.gpu
+def test_mixed_precision_requests_batch_apart():
+    """Same-order requests with FP64 and single-precision preconditioners in
+    one server: the FP32 ones keep their search direction in FP32 (an
+    operator reading FP32) and the FP64 ones in FP64, so only requests of
+    one kind share a batched operator launch; every result equals, bitwise,
+    the same solve run alone."""
+    from _gpu import announce, host, zeros
+    announce("serving mixed precisions")
+    cases = [(prm, bits) for prm in SAME_ORDER for bits in (64, 32)]
+    alone = []
+    for i, (prm, bits) in enumerate(cases):
+        k, phi, amp = fourier_modes(300 + i, 3)
+        with sipg.Solver(precond_bits=bits, **prm) as s:
+            b = zeros(s.ndof())
+            s.rhs_fourier(k, phi, amp, b)
+            x = zeros(s.ndof())
+            it, rr = s.pcg_solve(x, b, rtol=1e-10, maxit=100)
+            alone.append((host(x), it))
+    with sipg.Server(64 << 30, max_active=8) as srv:
+        srv.set_option(0, 1)
+        ids = []
+        for i, (prm, bits) in enumerate(cases):
+            k, phi, amp = fourier_modes(300 + i, 3)
+            ids.append(srv.submit(k, phi, amp, rtol=1e-10, maxit=100, precond_bits=bits, **prm))
+        for _ in range(100000):
+            a, q, _c = srv.progress(wait_ms=50)
+            if a == 0 and q == 0:
+                break
+        launches, served = srv.stats()
+        assert launches >= 1 and served >= 2 * launches, (launches, served)
+        for i, rid in enumerate(ids):
+            st = srv.status(rid)
+            assert st["state"] == sipg.REQ_DONE, st
+            u = zeros(st["ndof"])
+            srv.fetch(rid, u)
+            xs, it = alone[i]
+            assert st["iters"] == it
+            assert np.array_equal(host(u), xs), (i, cases[i][1])
+
+
 # one preconditioner signature (order 4, the 8 % overlap on isotropic
 # meshes: subdomains of 7^3 and 5^3 nodes on levels 2 and 1) and one size
 # class: their V-cycles run as cohorts when they are ready together
