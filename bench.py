@@ -181,7 +181,7 @@ def cpu_baseline(wl, cycles, k, phi, amp, nsample=5):
 
 
 def cpu_per_config(gpu_rates, nsample):
-    """BASELINE's CPU plan: for each workload the oracle's seconds per cycle
+    """The CPU side of every workload: the oracle's seconds per cycle
     t_c on the host (a bounded sample), with the rate rho and cycles n10 of
     the same algorithm (taken from the GPU solve of the workload, which
     matches the oracle's iteration by iteration), tau10 = -10 t_c / lg rho
