@@ -66,8 +66,9 @@ typedef enum { SIPG_OVL_MIN = 0, SIPG_OVL_REL = 1, SIPG_OVL_MAX = 2 } sipg_overl
 typedef enum { SIPG_BASIS_GLL = 0, SIPG_BASIS_GL = 1 } sipg_basis;
 
 typedef struct {
-  int32_t ne[3];          /* elements per direction (x, y, z); 3..48, and >= 4 in a
-                             direction whose subdomain takes whole neighbours      */
+  int32_t ne[3];          /* elements per direction (x, y, z); 3..1024, and >= 4 in
+                             a direction whose subdomain takes whole neighbours
+                             (and in every direction with the GL basis)          */
   double len[3];          /* domain lengths lx, ly, lz > 0                         */
   int32_t P;              /* polynomial order, 1..16 or 32                         */
   double penalty;         /* c_mu: mu_d = c_mu P_l (P_l + 1) / h_d on level l;
